@@ -1,0 +1,187 @@
+/*
+ * libdcsd -- two-determinant distinguishable-cluster (2D-DCSD) and 2D-CCSD
+ * amplitude residual, energies and solver on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Schraivogel & Kats, "Two Determinant Distinguishable Cluster",
+ * Theory section.  An open-shell singlet (or M_s = 0 triplet) is described by
+ * two determinants Phi_A = |core, t alpha, u beta> and Phi_B = |core, u alpha,
+ * t beta> (Fig. 1) whose amplitudes are spin flips of each other.  The
+ * amplitude equations are the single-reference CCSD (or DCSD) equations of
+ * Phi_A plus the renormalisation terms M_x W; the Phi_A -> Phi_B double is
+ * fixed at zero and its residual element is W; the 2x2 effective Hamiltonian
+ * gives the singlet dE_A + W and the triplet dE_A - W.
+ *
+ * Inputs (all FP64, row-major, device memory):
+ *   B[P][p][q]  (naux x n x n) DF factors defining (pq|rs) = sum_P B[P,p,q] B[P,r,s];
+ *               must be symmetric in p,q.
+ *   F[p][q]     (n x n) spin-averaged Fock matrix of the open-shell reference;
+ *               the one-electron Hamiltonian is h = F - G_avg[B] (see DESIGN).
+ *   Orbital order [core 0..nc-1 | t = nc | u = nc+1 | virtuals], n = nc+2+nv.
+ *
+ * Packed amplitude / residual vector (length dcsd_amplitude_count), with
+ * o = nc+1 and v = nv+1 per spin:
+ *   [ t1a (o,v) | t1b (o,v) | t2aa (o,o,v,v) | t2bb (o,o,v,v) | t2ab (o,o,v,v) ]
+ * alpha-occ = [core, t], alpha-vir = [u, virt], beta-occ = [core, u],
+ * beta-vir = [t, virt].  Same-spin doubles are stored in full and must be
+ * antisymmetric.  t2ab[nc][nc][0][0] (Phi_A -> Phi_B) is ignored on input and
+ * is zero in every residual.
+ *
+ * Ownership: every pointer argument is owned by the caller.  B and F are
+ * borrowed and must stay alive and unchanged until dcsd_destroy.  The library
+ * allocates all of its device memory in dcsd_init and frees it in
+ * dcsd_destroy; no other call allocates.
+ *
+ * Streams: all device work is enqueued on the HIP stream given to dcsd_init.
+ * Calls that return host values synchronise that stream before returning.
+ *
+ * Errors: functions return a dcsd_status and never throw; dcsd_last_error
+ * gives a message.  After DCSD_ERR_HIP the context is unusable (sticky).
+ */
+#ifndef LIBDCSD_H
+#define LIBDCSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dcsd_ctx dcsd_ctx;
+
+typedef enum {
+  DCSD_OK = 0,
+  DCSD_ERR_ARG = 1,        /* invalid argument or configuration            */
+  DCSD_ERR_OOM = 2,        /* device allocation failed in dcsd_init        */
+  DCSD_ERR_HIP = 3,        /* HIP runtime error (context becomes unusable) */
+  DCSD_ERR_NOCONV = 4,     /* dcsd_solve reached max_iter                  */
+  DCSD_ERR_NONFINITE = 5,  /* a residual contained Inf/NaN                 */
+  DCSD_ERR_STATE = 6       /* call on a context in an error state          */
+} dcsd_status;
+
+enum { DCSD_METHOD_DCSD = 0, DCSD_METHOD_CCSD = 1 };
+enum { DCSD_PREC_FP64 = 0 };
+
+/* Residual term selection (all bits set in production). */
+enum {
+  DCSD_TERM_DRIVER = 1u << 0,   /* <ab||ij>~                              */
+  DCSD_TERM_FOCK = 1u << 1,     /* f_vv, f_oo terms with X, Y intermediates */
+  DCSD_TERM_HH = 1u << 2,       /* hole-hole ladder                         */
+  DCSD_TERM_PP = 1u << 3,       /* particle-particle ladder (DF-assembled)  */
+  DCSD_TERM_RING = 1u << 4,     /* ring terms (linear and quadratic)        */
+  DCSD_TERM_SINGLES = 1u << 5,  /* singles residual                         */
+  DCSD_TERM_COUPLING = 1u << 6, /* -K_x W coupling of the two determinants  */
+  DCSD_TERM_ALL = 0x7fu
+};
+
+typedef struct {
+  int32_t nc, nv, naux;   /* core (doubly occupied) orbitals, virtuals, DF rank */
+  int32_t method;         /* DCSD_METHOD_DCSD or DCSD_METHOD_CCSD               */
+  int32_t precision;      /* DCSD_PREC_FP64                                     */
+  int32_t diis_dim;       /* DIIS subspace size (0 = plain Jacobi)              */
+  int32_t diis_start;     /* first iteration that extrapolates                  */
+  int32_t max_iter;
+  double tol_residual;    /* convergence: max |R| <= tol                        */
+  double level_shift;     /* Jacobi step R/(D - shift), shift >= 0              */
+  int32_t ladder_block;   /* orbitals per ladder batch side (0 = automatic)    */
+  uint32_t term_mask;     /* DCSD_TERM_* bits                                   */
+} dcsd_config;
+
+typedef struct {
+  double dE_A;    /* single-reference correlation energy expression of Phi_A */
+  double W;       /* effective coupling <B| H_N e^T_A |A> (residual element) */
+  double E_S;     /* open-shell singlet correlation energy dE_A + W          */
+  double E_T;     /* M_s = 0 triplet correlation energy dE_A - W             */
+  double E_ref_A; /* <A|H|A>                                                 */
+} dcsd_energies;
+
+typedef struct {
+  int32_t iterations; /* residual evaluations performed                      */
+  int32_t converged;  /* 1 if max |R| <= tol_residual                        */
+  double res_max;     /* max |R| of the last residual                        */
+  dcsd_energies e;    /* energies of the last amplitudes                     */
+} dcsd_report;
+
+typedef void (*dcsd_iter_cb)(const dcsd_report* it, void* user);
+
+/* Length of the packed amplitude vector: 2 o v + 3 o^2 v^2. */
+int64_t dcsd_amplitude_count(int32_t nc, int32_t nv);
+
+/* Fills *cfg with defaults (DCSD, FP64, DIIS 8 from iteration 2, max_iter 200,
+ * tol 1e-10, no shift, all terms). */
+void dcsd_default_config(dcsd_config* cfg);
+
+/* Builds a context: validates sizes, allocates all device work memory, and
+ * forms the constant quantities of Phi_A (one-electron Hamiltonian, Fock
+ * matrices, (ov|ov) integrals, reference energy).  hip_stream may be NULL
+ * (default stream).  On failure *out is NULL. */
+dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
+                      dcsd_ctx** out);
+
+/* Residual of the 2D equations (Theory section, singles and doubles
+ * equations): R = <x| e^-T H e^T |A> - [DC dropped terms] - K_x W, with
+ * R at the Phi_A -> Phi_B double set to zero.  T_dev and R_dev are packed
+ * vectors (may not alias).  If W_host is not NULL it receives W and the call
+ * synchronises; otherwise it is asynchronous. */
+dcsd_status dcsd_residual(dcsd_ctx* ctx, const double* T_dev, double* R_dev, double* W_host);
+
+/* Energies for amplitudes T and coupling W (W as returned by dcsd_residual
+ * for the same T): dE_A, E_S = dE_A + W, E_T = dE_A - W, E_ref_A.
+ * Synchronises. */
+dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energies* out);
+
+/* Solves the amplitude equations starting from T_inout (zeros = the usual
+ * start): Jacobi steps with orbital-energy denominators plus Pulay DIIS, all
+ * vectors in FP64 on the device, until max |R| <= tol_residual.  T_inout
+ * receives the final amplitudes; *out the final report; cb (may be NULL) is
+ * called after every residual evaluation.  Returns DCSD_ERR_NOCONV after
+ * max_iter evaluations, DCSD_ERR_NONFINITE on Inf/NaN. */
+dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user);
+
+/* Changes the solver settings of an existing context (max_iter,
+ * tol_residual, level_shift, diis_start, term_mask).  Sizes, method,
+ * precision, diis_dim and ladder_block must equal those given to dcsd_init;
+ * otherwise DCSD_ERR_ARG and nothing changes. */
+dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg);
+
+/* Kernel timing, measured with HIP events recorded on the context's stream
+ * around every launch of the ladder integral assembly (DF GEMM building
+ * (pc|qd) for a batch of orbital pairs), of the ladder contraction with the
+ * amplitudes, and around each whole residual evaluation.  `flops` is the
+ * algorithmic count (2 per multiply-add) of the launches recorded. */
+typedef struct {
+  double ms;        /* summed event-to-event duration */
+  int64_t launches; /* launches recorded              */
+  double flops;     /* summed algorithmic flops       */
+} dcsd_kernel_time;
+
+typedef struct {
+  dcsd_kernel_time assembly;    /* ladder integral assembly (MFMA, K = naux)   */
+  dcsd_kernel_time contraction; /* ladder contraction (MFMA, K = (nv+2)^2)     */
+  dcsd_kernel_time residual;    /* whole dcsd_residual evaluations             */
+} dcsd_timing;
+
+/* Starts recording (clears earlier records).  The first call creates the
+ * event pool (host-side HIP events, no device memory); at most 16384 events
+ * are recorded per start. */
+dcsd_status dcsd_timing_start(dcsd_ctx* ctx);
+
+/* Synchronises the stream, stops recording and sums the recorded intervals. */
+dcsd_status dcsd_timing_stop(dcsd_ctx* ctx, dcsd_timing* out);
+
+/* Message of the last error on this context ("" if none). */
+const char* dcsd_last_error(const dcsd_ctx* ctx);
+
+/* Releases all device memory of the context (NULL is allowed). */
+void dcsd_destroy(dcsd_ctx* ctx);
+
+/* Diagnostic (not part of the method): C = A * B in FP64 through the
+ * library's MFMA GEMM, with A (M x K) and B (K x N) row-major device arrays
+ * and C (M x N) row-major.  Returns DCSD_ERR_ARG on non-positive sizes. */
+dcsd_status dcsd_selftest_gemm(int64_t M, int64_t N, int64_t K, const double* A_dev, const double* B_dev,
+                               double* C_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBDCSD_H */

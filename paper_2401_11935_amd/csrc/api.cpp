@@ -1,0 +1,207 @@
+// C ABI of libdcsd: argument checks, status codes and error messages.  No
+// exception crosses this boundary.
+#include <new>
+#include <string>
+
+#include "ctx.h"
+
+struct dcsd_ctx {
+  dcsd::Ctx c;
+};
+
+namespace {
+thread_local std::string g_init_error;
+
+template <class Fn>
+dcsd_status guarded(dcsd_ctx* h, Fn&& fn) {
+  if (!h) return DCSD_ERR_ARG;
+  if (h->c.sticky) return DCSD_ERR_STATE;
+  try {
+    h->c.err.clear();
+    return fn();
+  } catch (const dcsd::ArgError& e) {
+    h->c.err = e.what();
+    return DCSD_ERR_ARG;
+  } catch (const dcsd::HipError& e) {
+    h->c.err = e.what();
+    h->c.sticky = true;
+    return DCSD_ERR_HIP;
+  } catch (const std::bad_alloc&) {
+    h->c.err = "host allocation failed";
+    return DCSD_ERR_OOM;
+  } catch (const std::exception& e) {
+    h->c.err = e.what();
+    h->c.sticky = true;
+    return DCSD_ERR_HIP;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int64_t dcsd_amplitude_count(int32_t nc, int32_t nv) {
+  if (nc < 0 || nv < 1) return -1;
+  const int64_t o = nc + 1, v = nv + 1;
+  return 2 * o * v + 3 * o * o * v * v;
+}
+
+void dcsd_default_config(dcsd_config* c) {
+  if (!c) return;
+  *c = dcsd_config{};
+  c->method = DCSD_METHOD_DCSD;
+  c->precision = DCSD_PREC_FP64;
+  c->diis_dim = 8;
+  c->diis_start = 2;
+  c->max_iter = 200;
+  c->tol_residual = 1e-10;
+  c->level_shift = 0.0;
+  c->ladder_block = 0;
+  c->term_mask = DCSD_TERM_ALL;
+}
+
+dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
+                      dcsd_ctx** out) {
+  if (!out) return DCSD_ERR_ARG;
+  *out = nullptr;
+  if (!cfg) {
+    g_init_error = "cfg is NULL";
+    return DCSD_ERR_ARG;
+  }
+  dcsd_ctx* h = new (std::nothrow) dcsd_ctx;
+  if (!h) return DCSD_ERR_OOM;
+  dcsd_status st = DCSD_OK;
+  try {
+    h->c.init(*cfg, B_dev, F_dev, (hipStream_t)hip_stream);
+  } catch (const dcsd::ArgError& e) {
+    g_init_error = e.what();
+    st = DCSD_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    g_init_error = "device allocation failed";
+    st = DCSD_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_init_error = e.what();
+    st = DCSD_ERR_HIP;
+  }
+  if (st != DCSD_OK) {
+    if (!h->c.allocs.empty()) (void)hipStreamSynchronize((hipStream_t)hip_stream);
+    h->c.release();
+    delete h;
+    return st;
+  }
+  g_init_error.clear();
+  *out = h;
+  return DCSD_OK;
+}
+
+dcsd_status dcsd_residual(dcsd_ctx* ctx, const double* T_dev, double* R_dev, double* W_host) {
+  return guarded(ctx, [&] {
+    if (!T_dev || !R_dev || T_dev == R_dev) throw dcsd::ArgError("T and R must be distinct device pointers");
+    ctx->c.residual(T_dev, R_dev, W_host);
+    return DCSD_OK;
+  });
+}
+
+dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energies* out) {
+  return guarded(ctx, [&] {
+    if (!T_dev || !out) throw dcsd::ArgError("T and out are required");
+    const double e = ctx->c.energy_A(T_dev);
+    out->dE_A = e;
+    out->W = W;
+    out->E_S = e + W;
+    out->E_T = e - W;
+    out->E_ref_A = ctx->c.e_ref;
+    return DCSD_OK;
+  });
+}
+
+dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user) {
+  return guarded(ctx, [&] {
+    if (!T_inout) throw dcsd::ArgError("T_inout is required");
+    const int rc = ctx->c.solve(T_inout, out, cb, user);
+    if (rc == DCSD_ERR_NOCONV) ctx->c.err = "not converged within max_iter";
+    if (rc == DCSD_ERR_NONFINITE) ctx->c.err = "non-finite residual";
+    return (dcsd_status)rc;
+  });
+}
+
+dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg) {
+  return guarded(ctx, [&] {
+    if (!cfg) throw dcsd::ArgError("cfg is NULL");
+    const dcsd_config& c = ctx->c.cfg;
+    if (cfg->nc != c.nc || cfg->nv != c.nv || cfg->naux != c.naux || cfg->method != c.method ||
+        cfg->precision != c.precision || cfg->diis_dim != c.diis_dim || cfg->ladder_block != c.ladder_block)
+      throw dcsd::ArgError("only solver settings may change after dcsd_init");
+    if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0))
+      throw dcsd::ArgError("invalid solver settings");
+    ctx->c.cfg = *cfg;
+    return DCSD_OK;
+  });
+}
+
+dcsd_status dcsd_timing_start(dcsd_ctx* ctx) {
+  return guarded(ctx, [&] {
+    dcsd::Ctx& c = ctx->c;
+    if (c.pool.empty()) {
+      c.pool.resize(16384);
+      for (auto& e : c.pool) DCSD_HIP(hipEventCreate(&e));
+    }
+    DCSD_HIP(hipStreamSynchronize(c.s));
+    c.recs.clear();
+    c.pool_next = 0;
+    c.timing = true;
+    return DCSD_OK;
+  });
+}
+
+dcsd_status dcsd_timing_stop(dcsd_ctx* ctx, dcsd_timing* out) {
+  return guarded(ctx, [&] {
+    dcsd::Ctx& c = ctx->c;
+    DCSD_HIP(hipStreamSynchronize(c.s));
+    c.timing = false;
+    dcsd_timing t{};
+    dcsd_kernel_time* k[3] = {&t.assembly, &t.contraction, &t.residual};
+    for (const auto& r : c.recs) {
+      float ms = 0.f;
+      DCSD_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      k[r.cls]->ms += ms;
+      k[r.cls]->launches += 1;
+      k[r.cls]->flops += r.flops;
+    }
+    c.recs.clear();
+    c.pool_next = 0;
+    if (out) *out = t;
+    return DCSD_OK;
+  });
+}
+
+const char* dcsd_last_error(const dcsd_ctx* ctx) {
+  if (!ctx) return g_init_error.c_str();
+  return ctx->c.err.c_str();
+}
+
+void dcsd_destroy(dcsd_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->c.s);
+  for (auto& e : ctx->c.pool) (void)hipEventDestroy(e);
+  ctx->c.release();
+  delete ctx;
+}
+
+dcsd_status dcsd_selftest_gemm(int64_t M, int64_t N, int64_t K, const double* A_dev, const double* B_dev,
+                               double* C_dev, void* hip_stream) {
+  if (M <= 0 || N <= 0 || K <= 0 || !A_dev || !B_dev || !C_dev) return DCSD_ERR_ARG;
+  try {
+    dcsd::GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A_dev; g.lda = K; g.a_mc = false;
+    g.B = B_dev; g.ldb = N; g.b_nc = true;
+    g.C = C_dev; g.ldc = N; g.c_nc = true;
+    dcsd::gemm_f64(g, (hipStream_t)hip_stream);
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return DCSD_ERR_HIP;
+  } catch (...) {
+    return DCSD_ERR_HIP;
+  }
+  return DCSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,300 @@
+// FP64 GEMM on the CDNA4 matrix cores (v_mfma_f64_16x16x4f64), LDS-staged.
+//
+// Workgroup = 4 waves of 64 lanes in a 2x2 arrangement; a BM x BN output tile
+// per workgroup, BK = 16 per K step, double-buffered LDS, one barrier per K
+// step.  Operand tiles are stored in LDS as [k][m] / [k][n] rows padded so
+// that the 16-lane groups of a 64-bit LDS read fall in disjoint bank halves.
+// Ragged M, N, K edges are zero-filled on load and masked on store.
+#include "kernels.h"
+
+namespace dcsd {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int BK = 16;
+constexpr int NT = 256;
+
+struct KArgs {
+  int64_t M, N, K;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double alpha, beta;
+  int64_t sA, sB, sC;
+  int64_t kchunk;      // K range per split (multiple of BK)
+  int64_t tiles_n;
+  int64_t split_stride;  // element stride between split partial outputs
+  int64_t vu, nq;        // pair-blocked output (EPI = 1)
+};
+
+template <int BM, int BN, bool A_MC, bool B_NC, bool C_NC, bool SPLIT, int EPI = 0>
+__global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
+  constexpr int PAD = 16;
+  constexpr int LDA_S = BM + PAD;
+  constexpr int LDB_S = BN + PAD;
+  constexpr int LA = BM * BK / NT;
+  constexpr int LB = BN * BK / NT;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  __shared__ double sA[2][BK * LDA_S];
+  __shared__ double sB[2][BK * LDB_S];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t bid = blockIdx.x;
+  const int64_t m0 = (bid / g.tiles_n) * BM;
+  const int64_t n0 = (bid % g.tiles_n) * BN;
+  const int64_t batch = blockIdx.y;
+  const double* A = g.A + batch * g.sA;
+  const double* B = g.B + batch * g.sB;
+
+  int64_t kbeg = 0, kend = g.K;
+  if (SPLIT) {
+    kbeg = (int64_t)blockIdx.z * g.kchunk;
+    kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  }
+
+  double ra[LA], rb[LB];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = tid + i * NT;
+      int k, m;
+      if (A_MC) { k = e / BM; m = e % BM; } else { k = e % BK; m = e / BK; }
+      const int64_t gm = m0 + m, gk = k0 + k;
+      double v = 0.0;
+      if (gm < g.M && gk < kend) v = A_MC ? A[gm + gk * g.lda] : A[gm * g.lda + gk];
+      ra[i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = tid + i * NT;
+      int k, n;
+      if (B_NC) { k = e / BN; n = e % BN; } else { k = e % BK; n = e / BK; }
+      const int64_t gn = n0 + n, gk = k0 + k;
+      double v = 0.0;
+      if (gn < g.N && gk < kend) v = B_NC ? B[gn + gk * g.ldb] : B[gn * g.ldb + gk];
+      rb[i] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < LA; ++i) {
+      const int e = tid + i * NT;
+      int k, m;
+      if (A_MC) { k = e / BM; m = e % BM; } else { k = e % BK; m = e / BK; }
+      sA[buf][k * LDA_S + m] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < LB; ++i) {
+      const int e = tid + i * NT;
+      int k, n;
+      if (B_NC) { k = e / BN; n = e % BN; } else { k = e % BK; n = e / BK; }
+      sB[buf][k * LDB_S + n] = rb[i];
+    }
+  };
+
+  dbl4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nk = (kend - kbeg + BK - 1) / BK;
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  const int lrow = lane >> 4, lcol = lane & 15;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nk) load(kbeg + (kt + 1) * BK);
+    const double* a_s = sA[buf];
+    const double* b_s = sB[buf];
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      double af[TM], bf[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = a_s[(ks * 4 + lrow) * LDA_S + wm * WM + i * 16 + lcol];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[j] = b_s[(ks * 4 + lrow) * LDB_S + wn * WN + j * 16 + lcol];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // epilogue: for the FP64 16x16x4 MFMA, lane holds D[lane/16 + 4*r][lane%16] of each 16x16 tile
+  double* C = g.C + batch * g.sC;
+  if (SPLIT) C += (int64_t)blockIdx.z * g.split_stride;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 16 + lrow + 4 * r;
+        const int64_t gn = n0 + wn * WN + j * 16 + lcol;
+        if (gm < g.M && gn < g.N) {
+          if (EPI == 1) {
+            // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]
+            const int64_t p = gm / g.vu, c = gm % g.vu, q = gn / g.vu, d = gn % g.vu;
+            C[((p * g.nq + q) * g.vu + c) * g.vu + d] = acc[i][j][r];
+            continue;
+          }
+          const int64_t off = C_NC ? gm * g.ldc + gn : gm + gn * g.ldc;
+          if (SPLIT) {
+            C[off] = acc[i][j][r];
+          } else {
+            double v = g.alpha * acc[i][j][r];
+            if (g.beta != 0.0) v += g.beta * C[off];
+            C[off] = v;
+          }
+        }
+      }
+}
+
+// C = alpha * sum_z W[z] + beta * C, W[z] laid out like C (same ldc/c_nc/batch strides).
+__global__ void split_reduce(const double* W, double* C, int64_t M, int64_t N, int64_t ldc, bool c_nc,
+                             int64_t batch, int64_t sC, int nsplit, int64_t split_stride, double alpha,
+                             double beta) {
+  const int64_t total = M * N * batch;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = idx / (M * N);
+    const int64_t r = idx % (M * N);
+    const int64_t m = c_nc ? r / N : r % M;
+    const int64_t n = c_nc ? r % N : r / M;
+    const int64_t off = b * sC + (c_nc ? m * ldc + n : m + n * ldc);
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += W[z * split_stride + off];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * C[off];
+    C[off] = v;
+  }
+}
+
+template <int BM, int BN, bool A_MC, bool B_NC, bool C_NC>
+void launch(const GemmArgs& g, KArgs& k, hipStream_t s) {
+  const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  k.tiles_n = tn;
+  dim3 grid((unsigned)(tm * tn), (unsigned)g.batch, (unsigned)g.ksplit);
+  if (g.ksplit > 1)
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, A_MC, B_NC, C_NC, true>), grid, dim3(NT), 0, s, k);
+  else
+    hipLaunchKernelGGL((gemm_kernel<BM, BN, A_MC, B_NC, C_NC, false>), grid, dim3(NT), 0, s, k);
+}
+
+template <int BM, int BN>
+void dispatch(const GemmArgs& g, KArgs& k, hipStream_t s) {
+  const int code = (g.a_mc ? 4 : 0) | (g.b_nc ? 2 : 0) | (g.c_nc ? 1 : 0);
+  switch (code) {
+    case 0: launch<BM, BN, false, false, false>(g, k, s); break;
+    case 1: launch<BM, BN, false, false, true>(g, k, s); break;
+    case 2: launch<BM, BN, false, true, false>(g, k, s); break;
+    case 3: launch<BM, BN, false, true, true>(g, k, s); break;
+    case 4: launch<BM, BN, true, false, false>(g, k, s); break;
+    case 5: launch<BM, BN, true, false, true>(g, k, s); break;
+    case 6: launch<BM, BN, true, true, false>(g, k, s); break;
+    default: launch<BM, BN, true, true, true>(g, k, s); break;
+  }
+}
+
+}  // namespace
+
+void gemm_f64(const GemmArgs& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+  if (g.batch > 65535 || g.ksplit > 65535 || g.ksplit < 1) throw ArgError("gemm_f64: grid too large");
+  KArgs k{};
+  k.M = g.M; k.N = g.N; k.K = g.K;
+  k.A = g.A; k.lda = g.lda; k.B = g.B; k.ldb = g.ldb;
+  k.C = g.C; k.ldc = g.ldc; k.alpha = g.alpha; k.beta = g.beta;
+  k.sA = g.sA; k.sB = g.sB; k.sC = g.sC;
+  if (g.ksplit > 1) {
+    if (!g.work) throw ArgError("gemm_f64: split-K needs a workspace");
+    int64_t chunk = (g.K + g.ksplit - 1) / g.ksplit;
+    chunk = (chunk + BK - 1) / BK * BK;
+    k.kchunk = chunk;
+    k.C = g.work;
+    // partials use the same C addressing with sC, plus a per-split stride
+    int64_t span = (g.batch - 1) * g.sC + (g.c_nc ? (g.M - 1) * g.ldc + g.N : (g.N - 1) * g.ldc + g.M);
+    k.split_stride = span;
+  } else {
+    k.kchunk = g.K;
+    k.split_stride = 0;
+  }
+  const int64_t tiles128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
+  if (g.M >= 128 && g.N >= 128 && tiles128 >= 128)
+    dispatch<128, 128>(g, k, s);
+  else
+    dispatch<64, 64>(g, k, s);
+  DCSD_CHECK_LAUNCH();
+  if (g.ksplit > 1) {
+    const int64_t total = g.M * g.N * g.batch;
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(split_reduce, dim3(blocks), dim3(256), 0, s, (const double*)g.work, g.C, g.M, g.N,
+                       g.ldc, g.c_nc, g.batch, g.sC, g.ksplit, k.split_stride, g.alpha, g.beta);
+    DCSD_CHECK_LAUNCH();
+  }
+}
+
+// Ladder integral batch: V2[(p*nq + q)][c][d] = sum_P Bl[P][p0+p][c] Bl[P][q0+q][d]
+// with Bl laid out [P][row][c] (row stride vu, P stride ld).
+void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int64_t p0, int64_t np, int64_t q0,
+                    int64_t nq, double* V2, hipStream_t s) {
+  KArgs k{};
+  k.M = np * vu; k.N = nq * vu; k.K = naux;
+  k.A = Bl + p0 * vu; k.lda = ld;
+  k.B = Bl + q0 * vu; k.ldb = ld;
+  k.C = V2; k.ldc = 0; k.alpha = 1.0; k.beta = 0.0;
+  k.kchunk = naux; k.vu = vu; k.nq = nq;
+  const int64_t tm = (k.M + 127) / 128, tn = (k.N + 127) / 128;
+  k.tiles_n = tn;
+  hipLaunchKernelGGL((gemm_kernel<128, 128, true, true, true, false, 1>), dim3((unsigned)(tm * tn)), dim3(NT), 0, s, k);
+  DCSD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+__global__ void strided_copy_kernel(double* dst, const double* src, Strided st, int64_t total, double alpha,
+                                    double beta) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = idx, od = 0, os = 0;
+    for (int d = st.nd - 1; d >= 0; --d) {
+      const int64_t i = r % st.dims[d];
+      r /= st.dims[d];
+      od += i * st.ds[d];
+      os += i * st.ss[d];
+    }
+    double v = alpha * src[os];
+    if (beta != 0.0) v += beta * dst[od];
+    dst[od] = v;
+  }
+}
+
+void strided_copy(double* dst, const double* src, const Strided& st, double alpha, double beta,
+                  hipStream_t s) {
+  int64_t total = 1;
+  for (int d = 0; d < st.nd; ++d) total *= st.dims[d];
+  if (total <= 0) return;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 1 << 20) blocks = 1 << 20;
+  hipLaunchKernelGGL(strided_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, st, total, alpha,
+                     beta);
+  DCSD_CHECK_LAUNCH();
+}
+
+}  // namespace dcsd

@@ -1,0 +1,38 @@
+// Launchers of the libdcsd device kernels (internal).
+#pragma once
+
+#include "common.h"
+
+namespace dcsd {
+
+void fill(double* p, double v, int64_t n, hipStream_t s);
+void axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
+void swap_tu(double* dst, const double* src, int64_t batch, int n, int nc, hipStream_t s);
+void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s);
+void batch_reduce(double* dst, const double* src, int64_t nb, int64_t bstride, int rows, int cols, int64_t ld,
+                  int64_t ldd, bool transpose, double alpha, hipStream_t s);
+
+// ladder
+void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int64_t p0, int64_t np, int64_t q0,
+                    int64_t nq, double* V2, hipStream_t s);
+void ladder_stack(double* S, const double* t2aa, const double* t2bb, const double* t2ab, const int* pair_i,
+                  const int* pair_j, int o, int v, int vu, int npair, int64_t rows, hipStream_t s);
+void ladder_scatter(double* Rp, const double* Rb, int64_t rows_used, int64_t nrow_main, int64_t nsame_begin, int n,
+                    int p0, int np, int q0, int nq, bool diag, hipStream_t s);
+void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, const double* Rp, const double* t1a,
+                       const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
+                       int64_t npair, int n, int nc, int o, int v, hipStream_t s);
+
+// coupling between the two determinants: R -= K(T) * W, R at the A->B double set to 0
+void coupling_apply(const double* T, double* R, const double* W_dev, int nc, int nv, hipStream_t s);
+
+// reductions (deterministic); `part` needs 1024 doubles
+void dot(const double* x, const double* y, int64_t n, double* out_dev, double* part, hipStream_t s);
+void maxabs(const double* x, int64_t n, double* out_dev, int* nonfinite_dev, double* part, hipStream_t s);
+void energy(const double* T, const double* Isc, const double* fa, const double* fb, int nc, int o, int v, int n,
+            double* out_dev, double* part, hipStream_t s);
+void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb, int o, int v,
+            int n, double shift, int64_t total, hipStream_t s);
+void combine(double* T, const double* V, int64_t stride, const double* c, int m, int64_t n, hipStream_t s);
+
+}  // namespace dcsd

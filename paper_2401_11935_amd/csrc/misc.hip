@@ -1,0 +1,287 @@
+// Element-wise, reduction and ladder bookkeeping kernels of the residual.
+// All arithmetic is FP64; reductions use a fixed grid and a fixed summation
+// order, so repeated calls give bitwise identical results.
+#include "kernels.h"
+
+namespace dcsd {
+
+namespace {
+__device__ inline int occ_sp(int spin, int i, int nc) { return i < nc ? i : nc + spin; }
+__device__ inline int vir_sp(int spin, int a, int nc) { return a > 0 ? nc + 1 + a : nc + 1 - spin; }
+
+inline unsigned nblocks(int64_t total, int threads, int64_t cap = 1 << 20) {
+  int64_t b = (total + threads - 1) / threads;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
+__global__ void fill_kernel(double* p, double v, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+void fill(double* p, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, p, v, n);
+  DCSD_CHECK_LAUNCH();
+}
+
+__global__ void axpby_kernel(double* y, const double* x, double a, double b, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+void axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(axpby_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, y, x, a, b, n);
+  DCSD_CHECK_LAUNCH();
+}
+
+// J[P] = sum_k Bt_a[P,k,k] + sum_k Bt_b[P,k,k] over the o occupied of each spin.
+__global__ void jvec_kernel(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o) {
+  const int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (P >= naux) return;
+  const double* a = Ba + P * n * n;
+  const double* b = Bb + P * n * n;
+  double s = 0.0;
+  for (int k = 0; k < o; ++k) s += a[k * n + k];
+  for (int k = 0; k < o; ++k) s += b[k * n + k];
+  J[P] = s;
+}
+void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s) {
+  hipLaunchKernelGGL(jvec_kernel, dim3(nblocks(naux, 256)), dim3(256), 0, s, J, Ba, Bb, naux, n, o);
+  DCSD_CHECK_LAUNCH();
+}
+
+// dst(r,c) += alpha * sum_b src[b*bstride + r*ld + c]   (dst(r,c) at dst[r*ldd + c], or transposed)
+__global__ void batch_reduce_kernel(double* dst, const double* src, int64_t nb, int64_t bstride, int rows, int cols,
+                                    int64_t ld, int64_t ldd, int transpose, double alpha) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)rows * cols) return;
+  const int r = (int)(idx / cols), c = (int)(idx % cols);
+  double s = 0.0;
+  for (int64_t b = 0; b < nb; ++b) s += src[b * bstride + r * ld + c];
+  const int64_t od = transpose ? (int64_t)c * ldd + r : (int64_t)r * ldd + c;
+  dst[od] += alpha * s;
+}
+void batch_reduce(double* dst, const double* src, int64_t nb, int64_t bstride, int rows, int cols, int64_t ld,
+                  int64_t ldd, bool transpose, double alpha, hipStream_t s) {
+  const int64_t total = (int64_t)rows * cols;
+  hipLaunchKernelGGL(batch_reduce_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, dst, src, nb, bstride, rows,
+                     cols, ld, ldd, transpose ? 1 : 0, alpha);
+  DCSD_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------------------------
+// Ladder: amplitude stack.  Row r of the stack is a Vu x Vu matrix over the
+// union virtual space [t, u, virt] (spatial orbitals nc..n-1).  Row order:
+// [ab (o*o) | aa pairs i<j | bb pairs i<j | ab transposed (o*o)].
+__device__ inline int inv_alpha(int u) { return u >= 1 ? u - 1 : -1; }             // union pos -> alpha vir
+__device__ inline int inv_beta(int u) { return u == 0 ? 0 : (u == 1 ? -1 : u - 1); }  // union pos -> beta vir
+
+__global__ void ladder_stack_kernel(double* S, const double* t2aa, const double* t2bb, const double* t2ab,
+                                    const int* pair_i, const int* pair_j, int o, int v, int vu, int npair,
+                                    int64_t rows) {
+  const int64_t vu2 = (int64_t)vu * vu;
+  const int64_t total = rows * vu2;
+  const int64_t s2 = (int64_t)o * o * v * v;
+  (void)s2;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / vu2;
+    const int cu = (int)((idx % vu2) / vu), du = (int)(idx % vu);
+    double val = 0.0;
+    const int64_t o2 = (int64_t)o * o;
+    if (r < o2) {  // ab: tau[c,d] = t2ab[i,J,c(alpha), D(beta)]
+      const int c = inv_alpha(cu), d = inv_beta(du);
+      if (c >= 0 && d >= 0) val = t2ab[(r * v + c) * v + d];
+    } else if (r < o2 + npair) {
+      const int64_t q = r - o2;
+      const int c = inv_alpha(cu), d = inv_alpha(du);
+      if (c >= 0 && d >= 0) val = t2aa[(((int64_t)pair_i[q] * o + pair_j[q]) * v + c) * v + d];
+    } else if (r < o2 + 2 * npair) {
+      const int64_t q = r - o2 - npair;
+      const int c = inv_beta(cu), d = inv_beta(du);
+      if (c >= 0 && d >= 0) val = t2bb[(((int64_t)pair_i[q] * o + pair_j[q]) * v + c) * v + d];
+    } else {  // ab transposed: tau^T[c,d] = tau[d,c]
+      const int64_t q = r - o2 - 2 * npair;
+      const int c = inv_alpha(du), d = inv_beta(cu);
+      if (c >= 0 && d >= 0) val = t2ab[(q * v + c) * v + d];
+    }
+    S[idx] = val;
+  }
+}
+void ladder_stack(double* S, const double* t2aa, const double* t2bb, const double* t2ab, const int* pair_i,
+                  const int* pair_j, int o, int v, int vu, int npair, int64_t rows, hipStream_t s) {
+  const int64_t total = rows * (int64_t)vu * vu;
+  hipLaunchKernelGGL(ladder_stack_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, S, t2aa, t2bb, t2ab, pair_i,
+                     pair_j, o, v, vu, npair, rows);
+  DCSD_CHECK_LAUNCH();
+}
+
+// Scatter one batch result Rb[row][pl*nq + ql] into Rp[row'][p][q] (n x n per row).
+__global__ void ladder_scatter_kernel(double* Rp, const double* Rb, int64_t rows_used, int64_t nrow_main,
+                                      int64_t nsame_begin, int n, int p0, int np, int q0, int nq, int diag) {
+  const int64_t npq = (int64_t)np * nq;
+  const int64_t total = rows_used * npq;
+  const int64_t n2 = (int64_t)n * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / npq;
+    const int pl = (int)((idx % npq) / nq), ql = (int)(idx % nq);
+    const int p = p0 + pl, q = q0 + ql;
+    const double val = Rb[idx];
+    if (r < nrow_main) {
+      Rp[r * n2 + (int64_t)p * n + q] = val;
+      if (!diag && r >= nsame_begin) Rp[r * n2 + (int64_t)q * n + p] = -val;
+    } else {
+      Rp[(r - nrow_main) * n2 + (int64_t)q * n + p] = val;  // ab transposed rows
+    }
+  }
+}
+void ladder_scatter(double* Rp, const double* Rb, int64_t rows_used, int64_t nrow_main, int64_t nsame_begin, int n,
+                    int p0, int np, int q0, int nq, bool diag, hipStream_t s) {
+  const int64_t total = rows_used * (int64_t)np * nq;
+  hipLaunchKernelGGL(ladder_scatter_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Rp, Rb, rows_used, nrow_main,
+                     nsame_begin, n, p0, np, q0, nq, diag ? 1 : 0);
+  DCSD_CHECK_LAUNCH();
+}
+
+// T1 back-transformation of the spatial ladder result (the dressed vv block is
+// B_vv - t1^T B_ov, so (ac|bd)~ = sum_pq M_ap M_bq (pc|qd)):
+//   step 1: S[row][p][b] = Rp[row][p][vir(b)] - sum_l t1[l,b] Rp[row][p][occ(l)]   (second-index spin)
+//   step 2: out[row][a][b] = S[row][vir(a)][b] - sum_k t1[k,a] S[row][occ(k)][b]   (first-index spin)
+__device__ inline void row_spins(int64_t r, int64_t o2, int64_t npair, int& s1, int& s2) {
+  if (r < o2) { s1 = 0; s2 = 1; }
+  else if (r < o2 + npair) { s1 = 0; s2 = 0; }
+  else { s1 = 1; s2 = 1; }
+}
+__global__ void ladder_mt1_kernel(double* S, const double* Rp, const double* t1a, const double* t1b, int64_t rows,
+                                  int64_t o2, int64_t npair, int n, int nc, int o, int v) {
+  const int64_t total = rows * n * v;
+  const int64_t n2 = (int64_t)n * n;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / ((int64_t)n * v);
+    const int p = (int)((idx / v) % n), b = (int)(idx % v);
+    int s1, s2;
+    row_spins(r, o2, npair, s1, s2);
+    const double* t1 = s2 == 0 ? t1a : t1b;
+    const double* row = Rp + r * n2 + (int64_t)p * n;
+    double val = row[vir_sp(s2, b, nc)];
+    for (int l = 0; l < o; ++l) val -= t1[l * v + b] * row[occ_sp(s2, l, nc)];
+    S[idx] = val;
+  }
+}
+__global__ void ladder_mt2_kernel(double* R2aa, double* R2bb, double* R2ab, const double* S, const double* t1a,
+                                  const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
+                                  int64_t npair, int n, int nc, int o, int v) {
+  const int64_t total = rows * v * v;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = idx / ((int64_t)v * v);
+    const int a = (int)((idx / v) % v), b = (int)(idx % v);
+    int s1, s2;
+    row_spins(r, o2, npair, s1, s2);
+    const double* t1 = s1 == 0 ? t1a : t1b;
+    const double* Sr = S + r * (int64_t)n * v;
+    double val = Sr[(int64_t)vir_sp(s1, a, nc) * v + b];
+    for (int k = 0; k < o; ++k) val -= t1[k * v + a] * Sr[(int64_t)occ_sp(s1, k, nc) * v + b];
+    if (r < o2) {
+      R2ab[(r * v + a) * v + b] += val;
+    } else {
+      const int64_t q = r < o2 + npair ? r - o2 : r - o2 - npair;
+      double* R2 = r < o2 + npair ? R2aa : R2bb;
+      const int i = pair_i[q], j = pair_j[q];
+      R2[((((int64_t)i * o + j) * v) + a) * v + b] += val;
+      R2[((((int64_t)j * o + i) * v) + a) * v + b] -= val;
+    }
+  }
+}
+void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, const double* Rp, const double* t1a,
+                       const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
+                       int64_t npair, int n, int nc, int o, int v, hipStream_t s) {
+  const int64_t t1tot = rows * n * v;
+  hipLaunchKernelGGL(ladder_mt1_kernel, dim3(nblocks(t1tot, 256)), dim3(256), 0, s, S, Rp, t1a, t1b, rows, o2, npair,
+                     n, nc, o, v);
+  DCSD_CHECK_LAUNCH();
+  const int64_t t2tot = rows * v * v;
+  hipLaunchKernelGGL(ladder_mt2_kernel, dim3(nblocks(t2tot, 256)), dim3(256), 0, s, R2aa, R2bb, R2ab, S, t1a, t1b,
+                     pair_i, pair_j, rows, o2, npair, n, nc, o, v);
+  DCSD_CHECK_LAUNCH();
+}
+
+// Jacobi step with orbital-energy denominators from the diagonal of the
+// reference Fock matrix (spin order): Tn = T + R / (D - shift), e = Tn - T.
+__global__ void jacobi_kernel(double* Tn, double* E, const double* T, const double* R, const double* fa,
+                              const double* fb, int o, int v, int n, double shift) {
+  const int64_t ov = (int64_t)o * v, s2 = ov * ov;
+  const int64_t total = 2 * ov + 3 * s2;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    double D;
+    if (x < 2 * ov) {
+      const double* f = x < ov ? fa : fb;
+      const int i = (int)((x % ov) / v), a = (int)(x % v);
+      D = f[(int64_t)i * n + i] - f[(int64_t)(o + a) * n + o + a];
+    } else {
+      const int64_t y = x - 2 * ov;
+      const int blk = (int)(y / s2);
+      int64_t r = y % s2;
+      const int b = (int)(r % v); r /= v;
+      const int a = (int)(r % v); r /= v;
+      const int j = (int)(r % o);
+      const int i = (int)(r / o);
+      const double* fi = blk == 1 ? fb : fa;
+      const double* fj = blk == 0 ? fa : fb;
+      D = fi[(int64_t)i * n + i] + fj[(int64_t)j * n + j] - fi[(int64_t)(o + a) * n + o + a] -
+          fj[(int64_t)(o + b) * n + o + b];
+    }
+    const double step = R[x] / (D - shift);
+    Tn[x] = T[x] + step;
+    if (E) E[x] = step;
+  }
+}
+void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb, int o, int v,
+            int n, double shift, int64_t total, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Tn, E, T, R, fa, fb, o, v, n, shift);
+  DCSD_CHECK_LAUNCH();
+}
+
+// T = sum_i c_i V_i (DIIS extrapolation; c on the device).
+__global__ void combine_kernel(double* T, const double* V, int64_t stride, const double* c, int m, int64_t n) {
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += c[i] * V[i * stride + x];
+    T[x] = s;
+  }
+}
+void combine(double* T, const double* V, int64_t stride, const double* c, int m, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel, dim3(nblocks(n, 256)), dim3(256), 0, s, T, V, stride, c, m, n);
+  DCSD_CHECK_LAUNCH();
+}
+
+}  // namespace dcsd
+
+namespace dcsd {
+// dst[P][p][q] = src[P][pi(p)][pi(q)] with pi exchanging orbitals nc (t) and nc+1 (u).
+__global__ void swap_tu_kernel(double* dst, const double* src, int64_t batch, int n, int nc) {
+  const int64_t n2 = (int64_t)n * n, total = batch * n2;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t P = idx / n2;
+    int p = (int)((idx % n2) / n), q = (int)(idx % n);
+    p = p == nc ? nc + 1 : (p == nc + 1 ? nc : p);
+    q = q == nc ? nc + 1 : (q == nc + 1 ? nc : q);
+    dst[idx] = src[P * n2 + (int64_t)p * n + q];
+  }
+}
+void swap_tu(double* dst, const double* src, int64_t batch, int n, int nc, hipStream_t s) {
+  const int64_t total = batch * (int64_t)n * n;
+  int64_t b = (total + 255) / 256;
+  if (b > 1 << 20) b = 1 << 20;
+  hipLaunchKernelGGL(swap_tu_kernel, dim3((unsigned)b), dim3(256), 0, s, dst, src, batch, n, nc);
+  DCSD_CHECK_LAUNCH();
+}
+}  // namespace dcsd

@@ -1,0 +1,576 @@
+// Context set-up and the 2D-DCSD / 2D-CCSD residual.
+//
+// Formulation (Theory section of the paper, implemented MI355X-first):
+//  * Spin-blocked amplitudes of Phi_A (alpha and beta orbital orders differ
+//    only by exchanging t and u).
+//  * Singles enter through T1-dressed DF factors B~ = (1 - t1) B (1 + t1)
+//    per spin and a dressed Fock matrix; the doubles residual is the CCD-like
+//    expression of the dressed Hamiltonian plus the T2*T2 terms, in which the
+//    distinguishable-cluster selection is applied (DCSD keeps the direct ring
+//    and half of the two Fock-like terms, drops the rest).
+//  * The particle-particle ladder is assembled from undressed spatial DF
+//    factors in batches of orbital pairs, with the row index running over all
+//    orbitals, so one assembly serves the alpha-alpha, beta-beta and
+//    alpha-beta blocks and the T1 dressing of the ladder becomes a cheap back
+//    transformation.
+//  * Ring terms are particle-hole matrix products (spin-conserving 2ov x 2ov
+//    and spin-flip ov x ov blocks).
+//  * The coupling of the two determinants, R_x -= K_x W, is applied last.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <initializer_list>
+
+#include "ctx.h"
+
+namespace dcsd {
+
+namespace {
+
+void copyN(double* dst, const double* src, std::initializer_list<int64_t> dims, std::initializer_list<int64_t> ds,
+           std::initializer_list<int64_t> ss, double alpha, double beta, hipStream_t s) {
+  Strided st;
+  st.nd = (int)dims.size();
+  int d = 0;
+  for (auto x : dims) st.dims[d++] = x;
+  d = 0;
+  for (auto x : ds) st.ds[d++] = x;
+  d = 0;
+  for (auto x : ss) st.ss[d++] = x;
+  strided_copy(dst, src, st, alpha, beta, s);
+}
+
+struct G {
+  GemmArgs a;
+  G(int64_t M, int64_t N, int64_t K) {
+    a.M = M;
+    a.N = N;
+    a.K = K;
+  }
+  G& A(const double* p, int64_t ld, bool mc) { a.A = p; a.lda = ld; a.a_mc = mc; return *this; }
+  G& B(const double* p, int64_t ld, bool nc) { a.B = p; a.ldb = ld; a.b_nc = nc; return *this; }
+  G& C(double* p, int64_t ld, bool nc = true) { a.C = p; a.ldc = ld; a.c_nc = nc; return *this; }
+  G& ab(double al, double be) { a.alpha = al; a.beta = be; return *this; }
+  G& batch(int64_t b, int64_t sA, int64_t sB, int64_t sC) { a.batch = b; a.sA = sA; a.sB = sB; a.sC = sC; return *this; }
+  G& split(int k, double* w) { a.ksplit = k; a.work = w; return *this; }
+  void run(hipStream_t s) { gemm_f64(a, s); }
+};
+
+}  // namespace
+
+double* Ctx::alloc(int64_t count) {
+  void* p = nullptr;
+  const size_t b = (size_t)std::max<int64_t>(count, 1) * sizeof(double);
+  if (hipMalloc(&p, b) != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  allocs.push_back(p);
+  bytes += b;
+  return (double*)p;
+}
+
+int* Ctx::alloc_int(int64_t count) {
+  void* p = nullptr;
+  const size_t b = (size_t)std::max<int64_t>(count, 1) * sizeof(int);
+  if (hipMalloc(&p, b) != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  allocs.push_back(p);
+  bytes += b;
+  return (int*)p;
+}
+
+void Ctx::release() {
+  for (void* p : allocs) (void)hipFree(p);
+  allocs.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Fock matrix of Phi_A from (possibly dressed) factors:
+//   f^s += sum_P J_P B^s[P] - sum_P sum_{k<o} B^s[P,:,k] B^s[P,k,:],
+//   J_P = sum_{s'} sum_{k<o} B^{s'}[P,k,k].   fout must already hold h^s.
+static void add_two_electron_fock(Ctx& c, double* const fout[2], double* const Bsrc[2]) {
+  const int n = c.n, o = c.o;
+  const int64_t naux = c.naux, n2 = c.n2;
+  jvector(c.Jv, Bsrc[0], Bsrc[1], naux, n, o, c.s);
+  for (int sp = 0; sp < 2; ++sp) {
+    G(1, n2, naux).A(c.Jv, naux, false).B(Bsrc[sp], n2, true).C(fout[sp], n2).ab(1.0, 1.0).run(c.s);
+    copyN(c.Xk, Bsrc[sp], {n, naux, o}, {naux * o, o, 1}, {n, n2, 1}, 1.0, 0.0, c.s);
+    copyN(c.Yk, Bsrc[sp], {naux, o, n}, {(int64_t)o * n, n, 1}, {n2, n, 1}, 1.0, 0.0, c.s);
+    G(n, n, naux * o).A(c.Xk, naux * o, false).B(c.Yk, n, true).C(fout[sp], n).ab(-1.0, 1.0).run(c.s);
+  }
+}
+
+// X <- (1 - t1^T) X (1 + t1) for a batch of n x n matrices in spin order
+// (t1 is o x v; rows/cols 0..o-1 occupied, o..n-1 virtual).
+static void dress(Ctx& c, double* X, const double* t1, int64_t batch) {
+  const int n = c.n, o = c.o, v = c.v;
+  const int64_t n2 = c.n2;
+  // X[:, 0:o] += X[:, o:n] t1^T
+  G(n, o, v).A(X + o, n, false).B(t1, v, false).C(X, n).ab(1.0, 1.0).batch(batch, n2, 0, n2).run(c.s);
+  // X[o:n, :] -= t1^T X[0:o, :]
+  G(v, n, o).A(t1, v, true).B(X, n, true).C(X + (int64_t)o * n, n).ab(-1.0, 1.0).batch(batch, 0, n2, n2).run(c.s);
+}
+
+void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipStream_t stream) {
+  cfg = cf;
+  s = stream;
+  if (cfg.nc < 0 || cfg.nv < 1 || cfg.naux < 1) throw ArgError("nc >= 0, nv >= 1 and naux >= 1 are required");
+  if (cfg.method != DCSD_METHOD_DCSD && cfg.method != DCSD_METHOD_CCSD) throw ArgError("unknown method");
+  if (cfg.precision != DCSD_PREC_FP64) throw ArgError("only FP64 precision is available");
+  if (cfg.diis_dim < 0 || cfg.diis_dim > 64) throw ArgError("diis_dim must be in [0, 64]");
+  if (cfg.max_iter < 1) throw ArgError("max_iter must be >= 1");
+  if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
+  if (!(cfg.level_shift >= 0.0)) throw ArgError("level_shift must be >= 0");
+  if (!Bin || !Fin) throw ArgError("B and F must be device pointers");
+  B = Bin;
+  F = Fin;
+  nc = cfg.nc;
+  nv = cfg.nv;
+  naux = cfg.naux;
+  n = nc + 2 + nv;
+  o = nc + 1;
+  v = nv + 1;
+  vu = nv + 2;
+  npair = o * (o - 1) / 2;
+  ov = (int64_t)o * v;
+  tov = 2 * ov;
+  s2 = ov * ov;
+  n2 = (int64_t)n * n;
+  total = 2 * ov + 3 * s2;
+  if ((int64_t)naux * n2 > (int64_t)1 << 40) throw ArgError("problem too large");
+  DCSD_HIP(hipGetDevice(&device));
+
+  const int64_t NA = naux;
+  const int64_t o2 = (int64_t)o * o;
+  // ---- allocations ------------------------------------------------------------
+  Bs[0] = const_cast<double*>(B);
+  Bs[1] = alloc(NA * n2);
+  for (int sp = 0; sp < 2; ++sp) {
+    h[sp] = alloc(n2);
+    f[sp] = alloc(n2);
+    Bt[sp] = alloc(NA * n2);
+    ft[sp] = alloc(n2);
+    Xv[sp] = alloc((int64_t)v * v);
+    Fvv[sp] = alloc((int64_t)v * v);
+    Yo[sp] = alloc(o2);
+    Foo[sp] = alloc(o2);
+    QX1[sp] = alloc(s2);
+    QX2[sp] = alloc(s2);
+    QY1[sp] = alloc(s2);
+    QY2[sp] = alloc(s2);
+    KJPQ[sp] = alloc(2 * o2 * n2);
+  }
+  Bl = alloc(NA * n * vu);
+  Isc = alloc(tov * tov);
+  if (cfg.method == DCSD_METHOD_CCSD) {
+    Icc = alloc(tov * tov);
+    Isf1 = alloc(s2);
+    Isf2 = alloc(s2);
+  }
+  for (int k = 0; k < 3; ++k) Ikl[k] = alloc(s2);
+  Tw = alloc(total);
+  Jv = alloc(NA);
+  Xk = alloc((int64_t)n * NA * std::max(o, nc + 2));
+  Yk = alloc((int64_t)n * NA * std::max(o, nc + 2));
+  Bov = alloc(NA * tov);
+  Bvo = alloc(NA * tov);
+  Boo = alloc(NA * 2 * o2);
+  Tsc = alloc(tov * tov);
+  Tsf1 = alloc(s2);
+  Z = alloc(NA * tov);
+  out1 = alloc(NA * ov);
+  out2 = alloc(NA * ov);
+  fvec = alloc(tov);
+  KCBJ = alloc(tov * tov);
+  Dvo = alloc(tov * tov);
+  OOOO = alloc(4 * o2 * o2);
+  Tmp = alloc(tov * tov);
+  Ring = alloc(tov * tov);
+  Wsf1 = alloc(s2);
+  Wsf2 = alloc(s2);
+  Rsf1 = alloc(s2);
+  Rsf2 = alloc(s2);
+  P1 = alloc(s2);
+  P2 = alloc(s2);
+  Whh = alloc(o2 * o2);
+  lb = cfg.ladder_block > 0 ? std::min(cfg.ladder_block, n) : std::min(32, n);
+  rows_main = o2 + 2 * (int64_t)npair;
+  rows_all = rows_main + o2;
+  const int64_t vu2 = (int64_t)vu * vu;
+  Tstack = alloc(rows_all * vu2);
+  V2 = alloc((int64_t)lb * lb * vu2);
+  Rb = alloc(rows_all * (int64_t)lb * lb);
+  Rp = alloc(rows_main * n2);
+  Smt = alloc(rows_main * (int64_t)n * v);
+  split_cap = 32;
+  split = alloc(split_cap * rows_all * (int64_t)lb * lb);
+  part = alloc(1024);
+  scal = alloc(8 + 64);
+  flag = alloc_int(4);
+  Rw = alloc(total);
+  if (cfg.diis_dim > 0) {
+    histT = alloc((int64_t)cfg.diis_dim * total);
+    histE = alloc((int64_t)cfg.diis_dim * total);
+    coef = alloc(cfg.diis_dim);
+  }
+  Tn = alloc(total);
+  Ev = alloc(total);
+  {
+    std::vector<int> pi, pj;
+    for (int i = 0; i < o; ++i)
+      for (int j = i + 1; j < o; ++j) {
+        pi.push_back(i);
+        pj.push_back(j);
+      }
+    pair_i = alloc_int(std::max(npair, 1));
+    pair_j = alloc_int(std::max(npair, 1));
+    if (npair > 0) {
+      DCSD_HIP(hipMemcpyAsync(pair_i, pi.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
+      DCSD_HIP(hipMemcpyAsync(pair_j, pj.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
+      DCSD_HIP(hipStreamSynchronize(s));  // host sources go out of scope
+    }
+  }
+
+  // ---- beta-order factors: exchange t and u in both orbital indices ---------------
+  swap_tu(Bs[1], Bs[0], NA, n, nc, s);
+
+  // ---- one-electron Hamiltonian h = F - G_avg ---------------------------------------
+  // G_avg = sum_core [2 J_k - K_k] + sum_{t,u} [J_x - K_x / 2]
+  {
+    const int K2 = nc + 2;
+    // weighted Coulomb vector jw[P] = sum_{k<nc} 2 B[P,k,k] + B[P,t,t] + B[P,u,u]
+    copyN(Xk, B, {NA, K2}, {K2, 1}, {n2, n + 1}, 1.0, 0.0, s);
+    std::vector<double> w(K2, 1.0);
+    for (int k = 0; k < nc; ++k) w[k] = 2.0;
+    DCSD_HIP(hipMemcpyAsync(fvec, w.data(), K2 * sizeof(double), hipMemcpyHostToDevice, s));
+    DCSD_HIP(hipStreamSynchronize(s));
+    G(NA, 1, K2).A(Xk, K2, false).B(fvec, 1, true).C(Jv, 1).run(s);
+    DCSD_HIP(hipMemcpyAsync(h[0], F, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    G(1, n2, NA).A(Jv, NA, false).B(B, n2, true).C(h[0], n2).ab(-1.0, 1.0).run(s);
+    // exchange: X[p][(P,k)] = c_k B[P,p,k] (c = 1 core, 1/2 open), Y[(P,k)][q] = B[P,k,q]
+    copyN(Xk, B, {n, NA, K2}, {NA * K2, K2, 1}, {n, n2, 1}, 1.0, 0.0, s);
+    copyN(Xk + nc, B + nc, {n, NA, 2}, {NA * K2, K2, 1}, {n, n2, 1}, 0.5, 0.0, s);
+    copyN(Yk, B, {NA, K2, n}, {(int64_t)K2 * n, n, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    G(n, n, NA * K2).A(Xk, NA * K2, false).B(Yk, n, true).C(h[0], n).ab(1.0, 1.0).run(s);
+    swap_tu(h[1], h[0], 1, n, nc, s);
+  }
+  // ---- Fock matrices of Phi_A (undressed) ------------------------------------------
+  for (int sp = 0; sp < 2; ++sp)
+    DCSD_HIP(hipMemcpyAsync(f[sp], h[sp], n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  add_two_electron_fock(*this, f, Bs);
+
+  // ---- (kc|ld) in the spin-conserving particle-hole layout --------------------------
+  for (int sp = 0; sp < 2; ++sp)
+    copyN(Bov + sp * ov, Bs[sp] + o, {NA, o, v}, {tov, v, 1}, {n2, n, 1}, 1.0, 0.0, s);
+  G(tov, tov, NA).A(Bov, tov, true).B(Bov, tov, true).C(Isc, tov).run(s);
+
+  // Permuted copies used by the X, Y and hole-hole intermediates.
+  const int64_t vt = (int64_t)v * tov;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int64_t base = sp * ov * (tov + 1);
+    // QX1[(k,l,c)][d] = (kc|ld)_ss
+    copyN(QX1[sp], Isc + base, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+    // QY1[l][(k,c,d)] = (kc|ld)_ss
+    copyN(QY1[sp], Isc + base, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {v, vt, tov, 1}, 1.0, 0.0, s);
+    // Ikl[(k,l),(c,d)] = (kc|ld)_ss
+    copyN(Ikl[sp], Isc + base, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+  }
+  // QX2a[(k,L,C)][d] = (kd|LC);  QX2b[(l,K,c)][D] = (KD|lc)
+  copyN(QX2[0], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, 1, tov}, 1.0, 0.0, s);
+  copyN(QX2[1], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+  // QY2a[l][(K,d,C)] = (KC|ld);  QY2b[L][(k,c,D)] = (kc|LD)
+  copyN(QY2[0], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+  copyN(QY2[1], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {v, vt, tov, 1}, 1.0, 0.0, s);
+  // Ikl_ab[(k,L),(c,D)] = (kc|LD)
+  copyN(Ikl[2], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+  if (cfg.method == DCSD_METHOD_CCSD) {
+    // <kl||cd> = (kc|ld) - (kd|lc): exchange part on the equal-spin blocks
+    DCSD_HIP(hipMemcpyAsync(Icc, Isc, tov * tov * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (int sp = 0; sp < 2; ++sp) {
+      const int64_t base = sp * ov * (tov + 1);
+      copyN(Icc + base, Isc + base, {o, v, o, v}, {vt, tov, v, 1}, {vt, 1, v, tov}, -1.0, 1.0, s);
+    }
+    // spin-flip blocks: Isf1[(K,c),(l,D)] = -(KD|lc), Isf2[(k,C),(L,d)] = -(kd|LC)
+    copyN(Isf1, Isc + ov * tov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
+    copyN(Isf2, Isc + ov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
+  }
+  // ---- ladder factor Bl[P][p][c] = B[P][p][nc + c], c over [t, u, virt] ------------
+  copyN(Bl, B + nc, {NA, n, vu}, {(int64_t)n * vu, vu, 1}, {n2, n, 1}, 1.0, 0.0, s);
+
+  // ---- reference energy E_ref = 1/2 sum_s sum_{k<o} (h_kk + f_kk) --------------------
+  {
+    std::vector<double> hd(n2), fd(n2);
+    double e = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+      DCSD_HIP(hipMemcpyAsync(hd.data(), h[sp], n2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      DCSD_HIP(hipMemcpyAsync(fd.data(), f[sp], n2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      DCSD_HIP(hipStreamSynchronize(s));
+      for (int k = 0; k < o; ++k) e += 0.5 * (hd[(int64_t)k * n + k] + fd[(int64_t)k * n + k]);
+    }
+    e_ref = e;
+  }
+  DCSD_HIP(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+void Ctx::residual(const double* T, double* R, double* W_host) {
+  const uint32_t mask = cfg.term_mask;
+  const int64_t NA = naux, o2 = (int64_t)o * o, vv = (int64_t)v * v, ov2 = o * vv;
+  const bool cc = cfg.method == DCSD_METHOD_CCSD;
+  const double sdc = cc ? 1.0 : 0.5;  // weight of the Fock-like T2*T2 terms (Q_c, Q_d)
+  hipEvent_t ev_res;
+  const int rec_res = tbegin(&ev_res);
+
+  // amplitudes with the Phi_A -> Phi_B double forced to zero
+  DCSD_HIP(hipMemcpyAsync(Tw, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
+  fill(Tw + ab_pos, 0.0, 1, s);
+  const double* t1[2] = {Tw, Tw + ov};
+  const double* t2aa = Tw + 2 * ov;
+  const double* t2bb = t2aa + s2;
+  const double* t2ab = t2bb + s2;
+  const double* t2ss[2] = {t2aa, t2bb};
+  double* R1 = R;
+  double* R2ss[2] = {R + 2 * ov, R + 2 * ov + s2};
+  double* R2ab = R + 2 * ov + 2 * s2;
+  fill(R, 0.0, total, s);
+
+  // ---- T1 dressing of the DF factors and of the Fock matrix ------------------------
+  for (int sp = 0; sp < 2; ++sp) {
+    DCSD_HIP(hipMemcpyAsync(Bt[sp], Bs[sp], NA * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dress(*this, Bt[sp], t1[sp], NA);
+    DCSD_HIP(hipMemcpyAsync(ft[sp], h[sp], n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    dress(*this, ft[sp], t1[sp], 1);
+  }
+  add_two_electron_fock(*this, ft, Bt);
+
+  // ---- dressed factor blocks -----------------------------------------------------
+  for (int sp = 0; sp < 2; ++sp) {
+    copyN(Bov + sp * ov, Bt[sp] + o, {NA, o, v}, {tov, v, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    copyN(Bvo + sp * ov, Bt[sp] + (int64_t)o * n, {NA, o, v}, {tov, v, 1}, {n2, 1, n}, 1.0, 0.0, s);
+    copyN(Boo + sp * o2, Bt[sp], {NA, o, o}, {2 * o2, o, 1}, {n2, n, 1}, 1.0, 0.0, s);
+  }
+
+  // ---- particle-hole amplitude matrices ------------------------------------------
+  // Tsc[(s,i,a),(s',k,c)] = t_ik^ac (spin-orbital), spin-conserving excitations
+  const int64_t vt = (int64_t)v * tov;
+  copyN(Tsc, t2aa, {o, v, o, v}, {vt, tov, v, 1}, {ov2, v, vv, 1}, 1.0, 0.0, s);
+  copyN(Tsc + ov, t2ab, {o, v, o, v}, {vt, tov, v, 1}, {ov2, v, vv, 1}, 1.0, 0.0, s);
+  copyN(Tsc + ov * tov, t2ab, {o, v, o, v}, {vt, tov, v, 1}, {vv, 1, ov2, v}, 1.0, 0.0, s);
+  copyN(Tsc + ov * tov + ov, t2bb, {o, v, o, v}, {vt, tov, v, 1}, {ov2, v, vv, 1}, 1.0, 0.0, s);
+  // Tsf1[(i,A),(K,c)] = t_{i K}^{A c} = -t2ab[i,K,c,A]   (Tsf2 = Tsf1^T)
+  copyN(Tsf1, t2ab, {o, v, o, v}, {v * ov, ov, v, 1}, {ov2, 1, vv, v}, -1.0, 0.0, s);
+
+  // ---- singles residual -------------------------------------------------------------
+  if (mask & DCSD_TERM_SINGLES) {
+    for (int sp = 0; sp < 2; ++sp) {
+      copyN(R1 + sp * ov, ft[sp] + (int64_t)o * n, {o, v}, {v, 1}, {1, n}, 1.0, 0.0, s);   // f~_ai
+      copyN(fvec + sp * ov, ft[sp] + o, {o, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);             // f~_kc
+    }
+    // sum_kc f~_kc t_ik^ac
+    G(tov, 1, tov).A(Tsc, tov, false).B(fvec, 1, true).C(R1, 1).ab(1.0, 1.0).run(s);
+    // Z[P][(s,i,c)] = sum_{(s',k,d)} B~_ov[P][(s',k,d)] t_ik^cd
+    G(NA, tov, tov).A(Bov, tov, false).B(Tsc, tov, true).C(Z, tov).run(s);
+    for (int sp = 0; sp < 2; ++sp) {
+      // + sum_P sum_c B~[P][a][c] Z[P][i][c]
+      G(v, o, v).A(Bt[sp] + (int64_t)o * n + o, n, false).B(Z + sp * ov, v, false).C(out1, o)
+          .batch(NA, n2, tov, ov).run(s);
+      batch_reduce(R1 + sp * ov, out1, NA, ov, v, o, o, v, true, 1.0, s);
+      // - sum_P sum_k B~[P][k][i] Z[P][k][a]
+      G(o, v, o).A(Bt[sp], n, true).B(Z + sp * ov, v, true).C(out2, v).batch(NA, n2, tov, ov).run(s);
+      batch_reduce(R1 + sp * ov, out2, NA, ov, o, v, v, v, false, -1.0, s);
+    }
+  }
+
+  // ---- driver and ring terms (particle-hole layout) -------------------------------
+  // Dvo[(s,i,a),(s',j,b)] = (ai|bj)~
+  if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING))
+    G(tov, tov, NA).A(Bvo, tov, true).B(Bvo, tov, true).C(Dvo, tov).run(s);
+  if (!(mask & DCSD_TERM_DRIVER)) fill(Dvo, 0.0, tov * tov, s);
+  if (mask & (DCSD_TERM_RING | DCSD_TERM_HH)) {
+    // OOOO[(s,k,i),(s',l,j)] = (ki|lj)~
+    G(2 * o2, 2 * o2, NA).A(Boo, 2 * o2, true).B(Boo, 2 * o2, true).C(OOOO, 2 * o2).run(s);
+  }
+  if (mask & DCSD_TERM_RING) {
+    // KCBJ[(s,k,c),(s',j,b)] = (kc|bj)~ ; KJPQ[s'][(s,k,j)][(p,q)] = (kj|pq)~
+    G(tov, tov, NA).A(Bov, tov, true).B(Bvo, tov, true).C(KCBJ, tov).run(s);
+    for (int sp = 0; sp < 2; ++sp)
+      G(2 * o2, n2, NA).A(Boo, 2 * o2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).run(s);
+    // W_sc = <kb||cj>~ = (kc|bj)~ - (kj|bc)~ (equal spins)
+    for (int sp = 0; sp < 2; ++sp) {
+      const int64_t base = sp * ov * (tov + 1);
+      copyN(KCBJ + base, KJPQ[sp] + sp * o2 * n2 + (int64_t)o * n + o, {o, v, o, v}, {vt, tov, v, 1},
+            {o * n2, 1, n2, n}, -1.0, 1.0, s);
+    }
+    // + 1/2 <kl||cd> t_jl^bd  (DCSD: direct (kc|ld) only)
+    G(tov, tov, tov).A(cc ? Icc : Isc, tov, false).B(Tsc, tov, true).C(KCBJ, tov).ab(0.5, 1.0).run(s);
+    // Ring_sc = T_sc W_sc
+    G(tov, tov, tov).A(Tsc, tov, false).B(KCBJ, tov, true).C(Ring, tov).run(s);
+    // spin-flip: Wsf1[(K,c),(J,b)] = -(KJ|bc)~, Wsf2[(k,C),(j,B)] = -(kj|BC)~
+    copyN(Wsf1, KJPQ[0] + o2 * n2 + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0,
+          0.0, s);
+    copyN(Wsf2, KJPQ[1] + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0, 0.0, s);
+    if (cc) {
+      // + 1/2 I_sf1 Tsf1 and + 1/2 I_sf2 Tsf1^T
+      G(ov, ov, ov).A(Isf1, ov, false).B(Tsf1, ov, true).C(Wsf1, ov).ab(0.5, 1.0).run(s);
+      G(ov, ov, ov).A(Isf2, ov, false).B(Tsf1, ov, false).C(Wsf2, ov).ab(0.5, 1.0).run(s);
+    }
+    G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).run(s);
+    G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).run(s);
+  } else {
+    fill(Ring, 0.0, tov * tov, s);
+    fill(Rsf1, 0.0, s2, s);
+    fill(Rsf2, 0.0, s2, s);
+  }
+  if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING)) {
+    // equal spins: R2 += P(ij)P(ab) [ 1/2 Dvo + Ring ]
+    for (int sp = 0; sp < 2; ++sp) {
+      const int64_t base = sp * ov * (tov + 1);
+      const double* src[2] = {Dvo + base, Ring + base};
+      const double fac[2] = {0.5, 1.0};
+      for (int q = 0; q < 2; ++q) {
+        std::initializer_list<int64_t> dst = {ov2, vv, v, 1};
+        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {vt, v, tov, 1}, fac[q], 1.0, s);
+        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {v, vt, tov, 1}, -fac[q], 1.0, s);
+        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {vt, v, 1, tov}, -fac[q], 1.0, s);
+        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {v, vt, 1, tov}, fac[q], 1.0, s);
+      }
+    }
+    // alpha-beta: D + Ring[(ia),(JB)] + Ring[(JB),(ia)] - Rsf2[(J,a),(i,B)] - Rsf1[(i,B),(J,a)]
+    std::initializer_list<int64_t> dab = {ov2, vv, v, 1};
+    copyN(R2ab, Dvo + ov, {o, o, v, v}, dab, {vt, v, tov, 1}, 1.0, 1.0, s);
+    copyN(R2ab, Ring + ov, {o, o, v, v}, dab, {vt, v, tov, 1}, 1.0, 1.0, s);
+    copyN(R2ab, Ring + ov * tov, {o, o, v, v}, dab, {v, vt, 1, tov}, 1.0, 1.0, s);
+    copyN(R2ab, Rsf2, {o, o, v, v}, dab, {v, v * ov, ov, 1}, -1.0, 1.0, s);
+    copyN(R2ab, Rsf1, {o, o, v, v}, dab, {v * ov, v, 1, ov}, -1.0, 1.0, s);
+  }
+
+  // ---- Fock-like terms with the X (vv) and Y (oo) T2*T2 intermediates --------------
+  if (mask & DCSD_TERM_FOCK) {
+    const double* t2p[2] = {t2aa, t2bb};
+    for (int sp = 0; sp < 2; ++sp) {
+      // X[b][d] = sum (kc|ld)_ss t2ss[k,l,b,c] - sum (kd|L C) t2ab[k,L,b,C]   (alpha)
+      copyN(P1, t2p[sp], {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {v, ov2, vv, 1}, 1.0, 0.0, s);
+      G(v, v, o2 * v).A(P1, o2 * v, false).B(QX1[sp], v, true).C(Xv[sp], v).run(s);
+      if (sp == 0)
+        copyN(P2, t2ab, {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {v, ov2, vv, 1}, 1.0, 0.0, s);
+      else  // t2ab[l,K,c,B] -> [B][l][K][c]
+        copyN(P2, t2ab, {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {1, ov2, vv, v}, 1.0, 0.0, s);
+      G(v, v, o2 * v).A(P2, o2 * v, false).B(QX2[sp], v, true).C(Xv[sp], v).ab(-1.0, 1.0).run(s);
+      // Y[l][j] = -sum (kc|ld) t2ss[j,k,c,d] + sum (KC|ld) t2ab[j,K,d,C]   (alpha)
+      G(o, o, ov2).A(QY1[sp], ov2, false).B(t2p[sp], ov2, false).C(Yo[sp], o).ab(-1.0, 0.0).run(s);
+      if (sp == 0) {
+        G(o, o, ov2).A(QY2[0], ov2, false).B(t2ab, ov2, false).C(Yo[0], o).ab(1.0, 1.0).run(s);
+      } else {
+        copyN(P2, t2ab, {o, o, v, v}, {ov2, vv, v, 1}, {vv, ov2, v, 1}, 1.0, 0.0, s);  // [J][k][c][D]
+        G(o, o, ov2).A(QY2[1], ov2, false).B(P2, ov2, false).C(Yo[1], o).ab(1.0, 1.0).run(s);
+      }
+      // F~vv = f~_vv + s X,  F~oo = f~_oo + s Y
+      copyN(Fvv[sp], ft[sp] + (int64_t)o * n + o, {v, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);
+      axpby(Fvv[sp], Xv[sp], sdc, 1.0, vv, s);
+      copyN(Foo[sp], ft[sp], {o, o}, {o, 1}, {n, 1}, 1.0, 0.0, s);
+      axpby(Foo[sp], Yo[sp], sdc, 1.0, o2, s);
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+      // P(ab) sum_d t_ij^ad F_bd
+      G(o2 * v, v, v).A(t2ss[sp], v, false).B(Fvv[sp], v, false).C(P1, v).run(s);
+      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, v, 1}, 1.0, 1.0, s);
+      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, 1, v}, -1.0, 1.0, s);
+      // -P(ij) sum_l t_il^ab F_lj
+      G(o, vv, o).A(Foo[sp], o, true).B(t2ss[sp], vv, true).C(P1, vv).batch(o, 0, ov2, ov2).run(s);
+      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, v, 1}, -1.0, 1.0, s);
+      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {vv, ov2, v, 1}, 1.0, 1.0, s);
+    }
+    // alpha-beta
+    G(o2 * v, v, v).A(t2ab, v, false).B(Fvv[1], v, false).C(R2ab, v).ab(1.0, 1.0).run(s);
+    G(v, v, v).A(Fvv[0], v, false).B(t2ab, v, true).C(R2ab, v).ab(1.0, 1.0).batch(o2, 0, vv, vv).run(s);
+    G(o, vv, o).A(Foo[1], o, true).B(t2ab, vv, true).C(R2ab, vv).ab(-1.0, 1.0).batch(o, 0, ov2, ov2).run(s);
+    G(o, ov2, o).A(Foo[0], o, true).B(t2ab, ov2, true).C(R2ab, ov2).ab(-1.0, 1.0).run(s);
+  }
+
+  // ---- hole-hole ladder -----------------------------------------------------------
+  if (mask & DCSD_TERM_HH) {
+    const int64_t to2 = 2 * o2;
+    for (int blk = 0; blk < 3; ++blk) {
+      const int s1 = blk == 1 ? 1 : 0, s3 = blk == 0 ? 0 : 1;
+      // Whh[(k,l),(i,j)] = (ki|lj)~
+      copyN(Whh, OOOO + (s1 * o2) * to2 + s3 * o2, {o, o, o, o}, {o * o2, o2, o, 1}, {o * to2, o, to2, 1}, 1.0, 0.0,
+            s);
+      const double* t2b = blk == 0 ? t2aa : (blk == 1 ? t2bb : t2ab);
+      double* Rb2 = blk == 0 ? R2ss[0] : (blk == 1 ? R2ss[1] : R2ab);
+      if (cc)  // + 1/2 <kl||cd> t_ij^cd  ->  sum_cd (kc|ld) t_ij^cd (x 1/2 for equal spins)
+        G(o2, o2, vv).A(Ikl[blk], vv, false).B(t2b, vv, false).C(Whh, o2).ab(blk == 2 ? 1.0 : 0.5, 1.0).run(s);
+      G(o2, vv, o2).A(Whh, o2, true).B(t2b, vv, true).C(Rb2, vv).ab(1.0, 1.0).run(s);
+    }
+  }
+
+  // ---- particle-particle ladder (DF-assembled, T1 back-transformed) -----------------
+  if (mask & DCSD_TERM_PP) {
+    const int64_t vu2 = (int64_t)vu * vu;
+    ladder_stack(Tstack, t2aa, t2bb, t2ab, pair_i, pair_j, o, v, vu, npair, rows_all, s);
+    for (int p0 = 0; p0 < n; p0 += lb) {
+      const int np = std::min(lb, n - p0);
+      for (int q0 = p0; q0 < n; q0 += lb) {
+        const int nq = std::min(lb, n - q0);
+        const bool diag = q0 == p0;
+        hipEvent_t ev0;
+        int rec = tbegin(&ev0);
+        gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
+        if (rec) tend(ev0, 2.0 * (double)np * vu * (double)nq * vu * (double)NA, 0);
+        const int64_t M = diag ? rows_main : rows_all;
+        const int64_t N = (int64_t)np * nq;
+        const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+        int ks = (int)std::min<int64_t>(split_cap, std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1)));
+        ks = (int)std::min<int64_t>(ks, std::max<int64_t>(1, vu2 / 1024));
+        rec = tbegin(&ev0);
+        G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(s);
+        if (rec) tend(ev0, 2.0 * (double)M * (double)N * (double)vu2, 1);
+        ladder_scatter(Rp, Rb, M, rows_main, o2, n, p0, np, q0, nq, diag, s);
+      }
+    }
+    ladder_mtransform(R2ss[0], R2ss[1], R2ab, Smt, Rp, t1[0], t1[1], pair_i, pair_j, rows_main, o2, npair, n, nc, o,
+                      v, s);
+  }
+
+  // ---- coupling of the two determinants ---------------------------------------------
+  DCSD_HIP(hipMemcpyAsync(scal, R + ab_pos, sizeof(double), hipMemcpyDeviceToDevice, s));  // W
+  if (mask & DCSD_TERM_COUPLING) {
+    coupling_apply(Tw, R, scal, nc, nv, s);
+  } else {
+    fill(R + ab_pos, 0.0, 1, s);
+  }
+  if (rec_res) tend(ev_res, 0.0, 2);
+  if (W_host) {
+    DCSD_HIP(hipMemcpyAsync(W_host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    DCSD_HIP(hipStreamSynchronize(s));
+  }
+}
+
+int Ctx::tbegin(hipEvent_t* ev) {
+  if (!timing || pool_next + 2 > pool.size()) return 0;
+  *ev = pool[pool_next++];
+  DCSD_HIP(hipEventRecord(*ev, s));
+  return 1;
+}
+
+void Ctx::tend(hipEvent_t a, double flops, int cls) {
+  hipEvent_t b = pool[pool_next++];
+  DCSD_HIP(hipEventRecord(b, s));
+  recs.push_back({a, b, flops, cls});
+}
+
+double Ctx::energy_A(const double* T) {
+  DCSD_HIP(hipMemcpyAsync(Tw, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
+  fill(Tw + ab_pos, 0.0, 1, s);
+  energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
+  double e = 0.0;
+  DCSD_HIP(hipMemcpyAsync(&e, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+  DCSD_HIP(hipStreamSynchronize(s));
+  return e;
+}
+
+}  // namespace dcsd

@@ -1,0 +1,123 @@
+// Amplitude solver: Jacobi steps with orbital-energy denominators and Pulay
+// DIIS.  All vectors stay on the device in FP64; only the (m+1)^2 DIIS system,
+// the residual max-norm and the energies cross to the host (one
+// synchronisation per iteration).
+#include <cmath>
+#include <vector>
+
+#include "ctx.h"
+
+namespace dcsd {
+
+namespace {
+// Solves A x = b (dense, partial pivoting); A is overwritten.
+bool solve_dense(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const double f = A[r * n + c] / A[c * n + c];
+      for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A[r * n + k] * b[k];
+    b[r] = s / A[r * n + r];
+  }
+  return true;
+}
+}  // namespace
+
+int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
+  const int m = cfg.diis_dim;
+  std::vector<double> gram((size_t)std::max(m, 1) * std::max(m, 1), 0.0);
+  std::vector<int> order;  // slots from oldest to newest
+  int count = 0;
+  dcsd_report r{};
+  for (int it = 0; it < cfg.max_iter; ++it) {
+    residual(T, Rw, nullptr);
+    int zero = 0;
+    DCSD_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    DCSD_HIP(hipStreamSynchronize(s));
+    maxabs(Rw, total, scal + 1, flag, part, s);
+    energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
+    double host[3];
+    int bad = 0;
+    DCSD_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    DCSD_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DCSD_HIP(hipStreamSynchronize(s));
+    r.iterations = it + 1;
+    r.res_max = host[1];
+    r.e.W = host[0];
+    r.e.dE_A = host[2];
+    r.e.E_S = host[2] + host[0];
+    r.e.E_T = host[2] - host[0];
+    r.e.E_ref_A = e_ref;
+    r.converged = (!bad && host[1] <= cfg.tol_residual) ? 1 : 0;
+    if (cb) cb(&r, user);
+    if (bad || !std::isfinite(host[0]) || !std::isfinite(host[2])) {
+      if (rep) *rep = r;
+      return DCSD_ERR_NONFINITE;
+    }
+    if (r.converged) {
+      if (rep) *rep = r;
+      return DCSD_OK;
+    }
+    jacobi(Tn, Ev, T, Rw, f[0], f[1], o, v, n, cfg.level_shift, total, s);
+    if (m > 0) {
+      const int slot = count % m;
+      ++count;
+      DCSD_HIP(hipMemcpyAsync(histT + (int64_t)slot * total, Tn, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+      DCSD_HIP(hipMemcpyAsync(histE + (int64_t)slot * total, Ev, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+      for (size_t k = 0; k < order.size(); ++k)
+        if (order[k] == slot) {
+          order.erase(order.begin() + k);
+          break;
+        }
+      order.push_back(slot);
+      const int nh = (int)order.size();
+      for (int j = 0; j < nh; ++j)
+        dot(histE + (int64_t)slot * total, histE + (int64_t)order[j] * total, total, scal + 4 + j, part, s);
+      std::vector<double> d(nh);
+      DCSD_HIP(hipMemcpyAsync(d.data(), scal + 4, nh * sizeof(double), hipMemcpyDeviceToHost, s));
+      DCSD_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < nh; ++j) {
+        gram[slot * m + order[j]] = d[j];
+        gram[order[j] * m + slot] = d[j];
+      }
+      if (it >= cfg.diis_start && nh >= 2) {
+        const int N = nh + 1;
+        std::vector<double> A((size_t)N * N, 0.0), b(N, 0.0);
+        for (int i = 0; i < nh; ++i)
+          for (int j = 0; j < nh; ++j) A[i * N + j] = gram[order[i] * m + order[j]];
+        for (int i = 0; i < nh; ++i) {
+          A[i * N + nh] = -1.0;
+          A[nh * N + i] = -1.0;
+        }
+        b[nh] = -1.0;
+        if (solve_dense(A, b, N)) {
+          // coefficients in slot order for the device combination
+          std::vector<double> c(m, 0.0);
+          for (int i = 0; i < nh; ++i) c[order[i]] = b[i];
+          DCSD_HIP(hipMemcpyAsync(coef, c.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+          DCSD_HIP(hipStreamSynchronize(s));
+          combine(T, histT, total, coef, std::min(count, m), total, s);
+          continue;
+        }
+      }
+    }
+    DCSD_HIP(hipMemcpyAsync(T, Tn, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (rep) *rep = r;
+  return DCSD_ERR_NOCONV;
+}
+
+}  // namespace dcsd

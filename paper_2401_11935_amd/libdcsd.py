@@ -1,0 +1,215 @@
+"""ctypes binding of libdcsd (argument marshalling only).
+
+Every function mirrors a call of ``include/libdcsd.h``; arrays are passed as
+raw device pointers (``torch.Tensor.data_ptr()`` of contiguous float64 CUDA
+tensors).  The compute runs entirely in the HIP kernels of ``libdcsd.so``;
+there is no fallback: if the library is missing, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "lib", "libdcsd.so")
+
+DCSD_OK, DCSD_ERR_ARG, DCSD_ERR_OOM, DCSD_ERR_HIP, DCSD_ERR_NOCONV, DCSD_ERR_NONFINITE, DCSD_ERR_STATE = range(7)
+STATUS_NAMES = ["OK", "ERR_ARG", "ERR_OOM", "ERR_HIP", "ERR_NOCONV", "ERR_NONFINITE", "ERR_STATE"]
+METHODS = {"dcsd": 0, "ccsd": 1}
+TERM = {"driver": 1, "fock": 2, "hh": 4, "pp": 8, "ring": 16, "singles": 32, "coupling": 64}
+TERM_ALL = 0x7F
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("nc", ctypes.c_int32), ("nv", ctypes.c_int32), ("naux", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("diis_dim", ctypes.c_int32),
+                ("diis_start", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("tol_residual", ctypes.c_double), ("level_shift", ctypes.c_double),
+                ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32)]
+
+
+class Energies(ctypes.Structure):
+    _fields_ = [("dE_A", ctypes.c_double), ("W", ctypes.c_double), ("E_S", ctypes.c_double),
+                ("E_T", ctypes.c_double), ("E_ref_A", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("res_max", ctypes.c_double),
+                ("e", Energies)]
+
+    def as_dict(self) -> dict:
+        d = {"iterations": self.iterations, "converged": bool(self.converged), "res_max": self.res_max}
+        d.update(self.e.as_dict())
+        return d
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double), ("launches", ctypes.c_int64), ("flops", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"ms": self.ms, "launches": self.launches, "flops": self.flops}
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("assembly", KernelTime), ("contraction", KernelTime), ("residual", KernelTime)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k).as_dict() for k, _ in self._fields_}
+
+
+ITER_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(Report), ctypes.c_void_p)
+
+_lib = None
+
+
+class DcsdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"libdcsd {STATUS_NAMES[status] if 0 <= status < 7 else status}: {message}")
+        self.status = status
+
+
+def load(path: str | None = None):
+    """Load libdcsd.so (built by ``paper_2401_11935_amd.build``); raises if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or os.environ.get("LIBDCSD_PATH", DEFAULT_PATH)
+    if not os.path.exists(p):
+        raise FileNotFoundError(f"libdcsd not built: {p} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    vp, dp = ctypes.c_void_p, ctypes.c_void_p
+    lib.dcsd_amplitude_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.dcsd_amplitude_count.restype = ctypes.c_int64
+    lib.dcsd_default_config.argtypes = [ctypes.POINTER(Config)]
+    lib.dcsd_default_config.restype = None
+    lib.dcsd_init.argtypes = [ctypes.POINTER(Config), dp, dp, vp, ctypes.POINTER(vp)]
+    lib.dcsd_init.restype = ctypes.c_int
+    lib.dcsd_residual.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_double)]
+    lib.dcsd_residual.restype = ctypes.c_int
+    lib.dcsd_energy.argtypes = [vp, dp, ctypes.c_double, ctypes.POINTER(Energies)]
+    lib.dcsd_energy.restype = ctypes.c_int
+    lib.dcsd_solve.argtypes = [vp, dp, ctypes.POINTER(Report), ITER_CB, vp]
+    lib.dcsd_solve.restype = ctypes.c_int
+    lib.dcsd_last_error.argtypes = [vp]
+    lib.dcsd_last_error.restype = ctypes.c_char_p
+    lib.dcsd_destroy.argtypes = [vp]
+    lib.dcsd_destroy.restype = None
+    lib.dcsd_update_config.argtypes = [vp, ctypes.POINTER(Config)]
+    lib.dcsd_update_config.restype = ctypes.c_int
+    lib.dcsd_timing_start.argtypes = [vp]
+    lib.dcsd_timing_start.restype = ctypes.c_int
+    lib.dcsd_timing_stop.argtypes = [vp, ctypes.POINTER(Timing)]
+    lib.dcsd_timing_stop.restype = ctypes.c_int
+    lib.dcsd_selftest_gemm.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, dp, dp, vp]
+    lib.dcsd_selftest_gemm.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def amplitude_count(nc: int, nv: int, lib=None) -> int:
+    return int((lib or load()).dcsd_amplitude_count(nc, nv))
+
+
+def default_config(lib=None, **kw) -> Config:
+    c = Config()
+    (lib or load()).dcsd_default_config(ctypes.byref(c))
+    for k, v in kw.items():
+        if k == "method" and isinstance(v, str):
+            v = METHODS[v]
+        setattr(c, k, v)
+    return c
+
+
+@dataclass
+class Pointers:
+    """Raw device (or, for host builds, host) addresses of B and F."""
+    B: int
+    F: int
+
+
+class Context:
+    """One problem (B, F, sizes) bound to one HIP stream.
+
+    B_ptr, F_ptr, T_ptr, R_ptr are integer addresses; use ``torch_context``
+    for torch tensors."""
+
+    def __init__(self, cfg: Config, B_ptr: int, F_ptr: int, stream: int = 0, lib=None):
+        self.lib = lib or load()
+        self.cfg = cfg
+        h = ctypes.c_void_p()
+        st = self.lib.dcsd_init(ctypes.byref(cfg), B_ptr, F_ptr, stream or None, ctypes.byref(h))
+        if st != DCSD_OK:
+            raise DcsdError(st, self.lib.dcsd_last_error(None).decode())
+        self.h = h
+        self.size = amplitude_count(cfg.nc, cfg.nv, self.lib)
+
+    def _check(self, st: int):
+        if st not in (DCSD_OK,):
+            raise DcsdError(st, self.lib.dcsd_last_error(self.h).decode())
+
+    def residual(self, T_ptr: int, R_ptr: int, want_W: bool = True):
+        W = ctypes.c_double(0.0)
+        self._check(self.lib.dcsd_residual(self.h, T_ptr, R_ptr, ctypes.byref(W) if want_W else None))
+        return W.value if want_W else None
+
+    def energy(self, T_ptr: int, W: float) -> dict:
+        e = Energies()
+        self._check(self.lib.dcsd_energy(self.h, T_ptr, W, ctypes.byref(e)))
+        return e.as_dict()
+
+    def solve(self, T_ptr: int, callback=None) -> dict:
+        rep = Report()
+        records = []
+
+        def cb(rp, _user):
+            d = rp.contents.as_dict()
+            records.append(d)
+            if callback is not None:
+                callback(d)
+
+        cfun = ITER_CB(cb)
+        st = self.lib.dcsd_solve(self.h, T_ptr, ctypes.byref(rep), cfun, None)
+        out = rep.as_dict()
+        out["status"] = STATUS_NAMES[st]
+        out["records"] = records
+        if st not in (DCSD_OK, DCSD_ERR_NOCONV):
+            raise DcsdError(st, self.lib.dcsd_last_error(self.h).decode())
+        return out
+
+    def update_config(self, **kw):
+        c = Config()
+        ctypes.pointer(c)[0] = self.cfg
+        for k, v in kw.items():
+            setattr(c, k, v)
+        self._check(self.lib.dcsd_update_config(self.h, ctypes.byref(c)))
+        self.cfg = c
+
+    def timing_start(self):
+        self._check(self.lib.dcsd_timing_start(self.h))
+
+    def timing_stop(self) -> dict:
+        t = Timing()
+        self._check(self.lib.dcsd_timing_stop(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dcsd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def selftest_gemm(M: int, N: int, K: int, A_ptr: int, B_ptr: int, C_ptr: int, stream: int = 0, lib=None):
+    st = (lib or load()).dcsd_selftest_gemm(M, N, K, A_ptr, B_ptr, C_ptr, stream or None)
+    if st != DCSD_OK:
+        raise DcsdError(st, "selftest_gemm")
