@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nc", type=int, default=12)
     ap.add_argument("--nv", type=int, default=400)
@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--method", default="dcsd", choices=["dcsd", "ccsd"])
     ap.add_argument("--ladder-block", type=int, default=0)
+    ap.add_argument("--precond", default="en", choices=["en", "orbital"])
+    ap.add_argument("--level-shift", type=float, default=1.0)
     ap.add_argument("--cpu-slabs", type=int, default=6, help="oracle ladder slabs timed for cpu_baseline (0 = skip)")
     ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per assembly launch")
     return ap.parse_args()
@@ -127,7 +129,7 @@ def main():
     del B
     stream = torch.cuda.current_stream(dev).cuda_stream
     cfg = L.default_config(nc=nc, nv=nv, naux=naux, method=args.method, max_iter=max(args.warmup, 1),
-                           ladder_block=args.ladder_block)
+                           ladder_block=args.ladder_block, precond=args.precond, level_shift=args.level_shift)
     t0 = time.perf_counter()
     ctx = L.Context(cfg, Bd.data_ptr(), Fd.data_ptr(), stream)
     torch.cuda.synchronize()

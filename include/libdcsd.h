@@ -60,6 +60,9 @@ typedef enum {
 
 enum { DCSD_METHOD_DCSD = 0, DCSD_METHOD_CCSD = 1 };
 enum { DCSD_PREC_FP64 = 0 };
+/* Jacobi preconditioner: orbital-energy denominators D, or D minus the
+ * two-electron (Epstein-Nesbet) part of the diagonal of dR/dT at T = 0. */
+enum { DCSD_PRECOND_ORBITAL = 0, DCSD_PRECOND_EN = 1 };
 
 /* Residual term selection (all bits set in production). */
 enum {
@@ -84,6 +87,7 @@ typedef struct {
   double level_shift;     /* Jacobi step R/(D - shift), shift >= 0              */
   int32_t ladder_block;   /* orbitals per ladder batch side (0 = automatic)    */
   uint32_t term_mask;     /* DCSD_TERM_* bits                                   */
+  int32_t precond;        /* DCSD_PRECOND_ORBITAL or DCSD_PRECOND_EN            */
 } dcsd_config;
 
 typedef struct {
@@ -138,7 +142,7 @@ dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energ
 dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user);
 
 /* Changes the solver settings of an existing context (max_iter,
- * tol_residual, level_shift, diis_start, term_mask).  Sizes, method,
+ * tol_residual, level_shift, diis_start, term_mask, precond).  Sizes, method,
  * precision, diis_dim and ladder_block must equal those given to dcsd_init;
  * otherwise DCSD_ERR_ARG and nothing changes. */
 dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg);

@@ -5,8 +5,10 @@ to zero reaches the same amplitudes.  The one used on both sides:
 
 * start from T = 0;
 * iteration k: R = residual(T); stop if max|R| <= tol;
-  T_new = T + R / (D - shift)   (D = f_ii + f_jj - f_aa - f_bb from the
-  diagonal of the reference Fock matrix; shift >= 0 only damps the step);
+  T_new = T + R / (D - s - shift)   (D = f_ii + f_jj - f_aa - f_bb from the
+  diagonal of the reference Fock matrix; s = 0, or with
+  ``precond="en"`` the two-electron (Epstein-Nesbet) part of the diagonal of
+  dR/dT at T = 0; shift >= 0 only damps the step);
 * Pulay DIIS on (T_new, e = T_new - T) with at most ``diis_dim`` vectors,
   used once ``k >= diis_start``: minimise |sum c_i e_i| with sum c_i = 1 and
   take T = sum c_i T_new_i.
@@ -33,8 +35,10 @@ def diis_coefficients(errors) -> np.ndarray:
 
 
 def solve(model, tol: float = 1e-10, max_iter: int = 200, diis_dim: int = 8,
-          diis_start: int = 2, shift: float = 0.0, T0=None, callback=None) -> dict:
+          diis_start: int = 2, shift: float = 0.0, precond: str = "mp", T0=None, callback=None) -> dict:
     D = model.denominators() - shift
+    if precond == "en":
+        D = D - model.en_shift()
     T = np.zeros(model.size) if T0 is None else np.array(T0, dtype=np.float64)
     hist_T, hist_e, records = [], [], []
     converged = False

@@ -81,6 +81,25 @@ class TwoDet:
         dEA = self.energy_A(vec)
         return {"dE_A": dEA, "W": W, "E_S": dEA + W, "E_T": dEA - W, "E_ref_A": self.ham.e_ref()}
 
+    def en_shift(self) -> np.ndarray:
+        """Two-electron part of the diagonal of the residual's Jacobian at T=0
+        (Epstein-Nesbet), packed: with P(p,q) = <pq||pq>,
+        singles s_ia = -P(i,a); doubles s_ijab = P(a,b) + P(i,j) - P(i,a)
+        - P(i,b) - P(j,a) - P(j,b).  Used only to precondition the Jacobi step."""
+        B = self.ham.B
+        J = np.einsum("Ppp,Pqq->pq", B, B)
+        K = np.einsum("Ppq,Ppq->pq", B, B)
+        O, V = self.ham.O, self.ham.V
+
+        def P(X, Y):
+            (xs, xm), (ys, ym) = X, Y
+            return J[np.ix_(xs, ys)] - (xm[:, None] == ym[None, :]) * K[np.ix_(xs, ys)]
+        Poo, Pvv, Pov = P(O, O), P(V, V), P(O, V)
+        s1 = -Pov
+        s2 = (Pvv[None, None, :, :] + Poo[:, :, None, None] - Pov[:, None, :, None] - Pov[:, None, None, :]
+              - Pov[None, :, :, None] - Pov[None, :, None, :])
+        return self.ham.from_so(s1, s2)
+
     def denominators(self) -> np.ndarray:
         """D_x = sum f_ii - sum f_aa from the spin-orbital Fock diagonal (packed)."""
         o, v = self.ham.o, self.ham.v

@@ -57,6 +57,7 @@ void dcsd_default_config(dcsd_config* c) {
   c->level_shift = 0.0;
   c->ladder_block = 0;
   c->term_mask = DCSD_TERM_ALL;
+  c->precond = DCSD_PRECOND_ORBITAL;
 }
 
 dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
@@ -131,7 +132,8 @@ dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg) {
     if (cfg->nc != c.nc || cfg->nv != c.nv || cfg->naux != c.naux || cfg->method != c.method ||
         cfg->precision != c.precision || cfg->diis_dim != c.diis_dim || cfg->ladder_block != c.ladder_block)
       throw dcsd::ArgError("only solver settings may change after dcsd_init");
-    if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0))
+    if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0) ||
+        (cfg->precond != DCSD_PRECOND_ORBITAL && cfg->precond != DCSD_PRECOND_EN))
       throw dcsd::ArgError("invalid solver settings");
     ctx->c.cfg = *cfg;
     return DCSD_OK;

@@ -126,11 +126,25 @@ __device__ double cluster_coef(const Amp& A, const Orb* L, const int* H, const i
     case 3: perms = &kPerm3[0][0]; signs = kPermSign3; match = &kMatch3[0][0]; nperm = 6; nmatch = 4; break;
     default: perms = &kPerm4[0][0]; signs = kPermSign4; match = &kMatch4[0][0]; nperm = 24; nmatch = 10; break;
   }
+  // spins of the holes and particles: a factor conserves spin, so most
+  // (matching, permutation) pairs vanish and are skipped before any lookup
+  int hs[4], ps[4];
+  for (int k = 0; k < r; ++k) {
+    hs[k] = L[H[k]].spin;
+    ps[k] = L[P[k]].spin;
+  }
   double sum = 0.0;
   for (int m = 0; m < nmatch; ++m) {
     const signed char* mt = match + m * r;
     for (int s = 0; s < nperm; ++s) {
       const signed char* pm = perms + s * r;
+      bool ok = true;
+      for (int k = 0; k < r && ok; ++k) {
+        const int partner = mt[k];
+        if (partner < 0) ok = hs[k] == ps[pm[k]];
+        else if (partner > k) ok = hs[k] + hs[partner] == ps[pm[k]] + ps[pm[partner]];
+      }
+      if (!ok) continue;
       double prod = (double)signs[s];
       for (int k = 0; k < r && prod != 0.0; ++k) {
         const int partner = mt[k];

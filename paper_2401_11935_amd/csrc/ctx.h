@@ -35,6 +35,10 @@ struct Ctx {
   double* h[2] = {nullptr, nullptr};   // one-electron Hamiltonian in spin order
   double* f[2] = {nullptr, nullptr};   // reference Fock matrices of Phi_A in spin order
   double* Bl = nullptr;                // ladder factor [P][p][c], c over [t,u,virt]
+  double* Jpq = nullptr;               // (pp|qq), spatial
+  double* Kpq = nullptr;               // (pq|qp), spatial
+  double* gws = nullptr;               // split-K workspace
+  int64_t gws_cap = 0;
   double* Isc = nullptr;               // undressed (kc|ld), spin-conserving ph matrix (2ov x 2ov)
   double* Icc = nullptr;               // antisymmetrised <kl||cd> ph matrix (CCSD only)
   double* Isf1 = nullptr;              // spin-flip <kl||cd> blocks (CCSD only)

@@ -34,15 +34,22 @@ struct KArgs {
 
 template <int BM, int BN, bool A_MC, bool B_NC, bool C_NC, bool SPLIT, int EPI = 0>
 __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
+  // LDS layouts: an operand whose M (N) index is contiguous in memory is kept
+  // as [k][m] rows padded by 16 doubles (the 16-lane groups of an MFMA
+  // fragment read fall in disjoint bank halves); an operand whose K index is
+  // contiguous is kept as [m][k] rows of BK+1 doubles (odd stride: both the
+  // row-wise stores and the fragment reads are free of bank conflicts).
   constexpr int PAD = 16;
-  constexpr int LDA_S = BM + PAD;
-  constexpr int LDB_S = BN + PAD;
+  constexpr int LDA_S = A_MC ? BM + PAD : BK + 1;
+  constexpr int LDB_S = B_NC ? BN + PAD : BK + 1;
+  constexpr int SA = A_MC ? BK * LDA_S : BM * LDA_S;
+  constexpr int SB = B_NC ? BK * LDB_S : BN * LDB_S;
   constexpr int LA = BM * BK / NT;
   constexpr int LB = BN * BK / NT;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  __shared__ double sA[2][BK * LDA_S];
-  __shared__ double sB[2][BK * LDB_S];
+  __shared__ double sA[2][SA];
+  __shared__ double sB[2][SB];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -90,14 +97,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
       const int e = tid + i * NT;
       int k, m;
       if (A_MC) { k = e / BM; m = e % BM; } else { k = e % BK; m = e / BK; }
-      sA[buf][k * LDA_S + m] = ra[i];
+      sA[buf][A_MC ? k * LDA_S + m : m * LDA_S + k] = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
       const int e = tid + i * NT;
       int k, n;
       if (B_NC) { k = e / BN; n = e % BN; } else { k = e % BK; n = e / BK; }
-      sB[buf][k * LDB_S + n] = rb[i];
+      sB[buf][B_NC ? k * LDB_S + n : n * LDB_S + k] = rb[i];
     }
   };
 
@@ -123,9 +130,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
     for (int ks = 0; ks < BK / 4; ++ks) {
       double af[TM], bf[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) af[i] = a_s[(ks * 4 + lrow) * LDA_S + wm * WM + i * 16 + lcol];
+      for (int i = 0; i < TM; ++i) {
+        const int mm = wm * WM + i * 16 + lcol, kk = ks * 4 + lrow;
+        af[i] = a_s[A_MC ? kk * LDA_S + mm : mm * LDA_S + kk];
+      }
 #pragma unroll
-      for (int j = 0; j < TN; ++j) bf[j] = b_s[(ks * 4 + lrow) * LDB_S + wn * WN + j * 16 + lcol];
+      for (int j = 0; j < TN; ++j) {
+        const int nn = wn * WN + j * 16 + lcol, kk = ks * 4 + lrow;
+        bf[j] = b_s[B_NC ? kk * LDB_S + nn : nn * LDB_S + kk];
+      }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll

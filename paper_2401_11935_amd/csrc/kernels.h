@@ -31,8 +31,12 @@ void dot(const double* x, const double* y, int64_t n, double* out_dev, double* p
 void maxabs(const double* x, int64_t n, double* out_dev, int* nonfinite_dev, double* part, hipStream_t s);
 void energy(const double* T, const double* Isc, const double* fa, const double* fb, int nc, int o, int v, int n,
             double* out_dev, double* part, hipStream_t s);
-void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb, int o, int v,
-            int n, double shift, int64_t total, hipStream_t s);
+// Jacobi step Tn = T + R/(D - s - shift); J, K (spatial (pp|qq), (pq|qp)) enable the
+// Epstein-Nesbet diagonal s (NULL: s = 0).  E (may be NULL) receives Tn - T.
+void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb,
+            const double* J, const double* K, int nc, int o, int v, int n, double shift, int64_t total,
+            hipStream_t s);
+void sumsq_batch(double* K, const double* B, int64_t nb, int64_t n2, hipStream_t s);
 void combine(double* T, const double* V, int64_t stride, const double* c, int m, int64_t n, hipStream_t s);
 
 }  // namespace dcsd

@@ -214,8 +214,14 @@ void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, cons
 
 // Jacobi step with orbital-energy denominators from the diagonal of the
 // reference Fock matrix (spin order): Tn = T + R / (D - shift), e = Tn - T.
+// <pq||pq> for spin-orbitals p, q (spin, spatial): J_pq - [same spin] K_pq.
+__device__ inline double pq_pq(const double* J, const double* K, int n, int sp, int p, int sq, int q) {
+  return J[(int64_t)p * n + q] - (sp == sq ? K[(int64_t)p * n + q] : 0.0);
+}
+
 __global__ void jacobi_kernel(double* Tn, double* E, const double* T, const double* R, const double* fa,
-                              const double* fb, int o, int v, int n, double shift) {
+                              const double* fb, const double* J, const double* K, int nc, int o, int v, int n,
+                              double shift) {
   const int64_t ov = (int64_t)o * v, s2 = ov * ov;
   const int64_t total = 2 * ov + 3 * s2;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
@@ -225,6 +231,10 @@ __global__ void jacobi_kernel(double* Tn, double* E, const double* T, const doub
       const double* f = x < ov ? fa : fb;
       const int i = (int)((x % ov) / v), a = (int)(x % v);
       D = f[(int64_t)i * n + i] - f[(int64_t)(o + a) * n + o + a];
+      if (J) {
+        const int sp = x < ov ? 0 : 1;
+        D += pq_pq(J, K, n, sp, occ_sp(sp, i, nc), sp, vir_sp(sp, a, nc));  // D - s, s = -<ia||ia>
+      }
     } else {
       const int64_t y = x - 2 * ov;
       const int blk = (int)(y / s2);
@@ -237,15 +247,41 @@ __global__ void jacobi_kernel(double* Tn, double* E, const double* T, const doub
       const double* fj = blk == 0 ? fa : fb;
       D = fi[(int64_t)i * n + i] + fj[(int64_t)j * n + j] - fi[(int64_t)(o + a) * n + o + a] -
           fj[(int64_t)(o + b) * n + o + b];
+      if (J) {
+        const int si = blk == 1 ? 1 : 0, sj = blk == 0 ? 0 : 1;
+        const int pi = occ_sp(si, i, nc), pj = occ_sp(sj, j, nc), pa = vir_sp(si, a, nc), pb = vir_sp(sj, b, nc);
+        const double sEN = pq_pq(J, K, n, si, pa, sj, pb) + pq_pq(J, K, n, si, pi, sj, pj) -
+                           pq_pq(J, K, n, si, pi, si, pa) - pq_pq(J, K, n, si, pi, sj, pb) -
+                           pq_pq(J, K, n, sj, pj, si, pa) - pq_pq(J, K, n, sj, pj, sj, pb);
+        D -= sEN;
+      }
     }
     const double step = R[x] / (D - shift);
     Tn[x] = T[x] + step;
     if (E) E[x] = step;
   }
 }
-void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb, int o, int v,
-            int n, double shift, int64_t total, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Tn, E, T, R, fa, fb, o, v, n, shift);
+void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb,
+            const double* J, const double* K, int nc, int o, int v, int n, double shift, int64_t total,
+            hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Tn, E, T, R, fa, fb, J, K, nc, o, v,
+                     n, shift);
+  DCSD_CHECK_LAUNCH();
+}
+
+// K[pq] = sum_P B[P][pq]^2 (exchange integrals (pq|qp) of a symmetric factor).
+__global__ void sumsq_kernel(double* K, const double* B, int64_t nb, int64_t n2) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= n2) return;
+  double s = 0.0;
+  for (int64_t P = 0; P < nb; ++P) {
+    const double b = B[P * n2 + idx];
+    s += b * b;
+  }
+  K[idx] = s;
+}
+void sumsq_batch(double* K, const double* B, int64_t nb, int64_t n2, hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nblocks(n2, 256)), dim3(256), 0, s, K, B, nb, n2);
   DCSD_CHECK_LAUNCH();
 }
 

@@ -53,7 +53,26 @@ struct G {
   G& ab(double al, double be) { a.alpha = al; a.beta = be; return *this; }
   G& batch(int64_t b, int64_t sA, int64_t sB, int64_t sC) { a.batch = b; a.sA = sA; a.sB = sB; a.sC = sC; return *this; }
   G& split(int k, double* w) { a.ksplit = k; a.work = w; return *this; }
-  void run(hipStream_t s) { gemm_f64(a, s); }
+  // Few output tiles and a long K: split K across workgroups into the context's
+  // workspace (fixed-order reduction, deterministic).
+  void run(Ctx& c) {
+    const double* g_ws = c.gws;
+    const int64_t g_ws_cap = c.gws_cap;
+    if (a.ksplit == 1 && g_ws && a.K >= 2048) {
+      const int64_t tiles = ((a.M + 63) / 64) * ((a.N + 63) / 64) * a.batch;
+      if (tiles < 256) {
+        int64_t ks = std::min<int64_t>(256, std::max<int64_t>(1, 1024 / tiles));
+        ks = std::min<int64_t>(ks, a.K / 512);
+        const int64_t span = (a.batch - 1) * a.sC + (a.c_nc ? (a.M - 1) * a.ldc + a.N : (a.N - 1) * a.ldc + a.M);
+        while (ks > 1 && ks * span > g_ws_cap) ks /= 2;
+        if (ks > 1) {
+          a.ksplit = (int)ks;
+          a.work = c.gws;
+        }
+      }
+    }
+    gemm_f64(a, c.s);
+  }
 };
 
 }  // namespace
@@ -96,10 +115,10 @@ static void add_two_electron_fock(Ctx& c, double* const fout[2], double* const B
   const int64_t naux = c.naux, n2 = c.n2;
   jvector(c.Jv, Bsrc[0], Bsrc[1], naux, n, o, c.s);
   for (int sp = 0; sp < 2; ++sp) {
-    G(1, n2, naux).A(c.Jv, naux, false).B(Bsrc[sp], n2, true).C(fout[sp], n2).ab(1.0, 1.0).run(c.s);
+    G(1, n2, naux).A(c.Jv, naux, false).B(Bsrc[sp], n2, true).C(fout[sp], n2).ab(1.0, 1.0).run(c);
     copyN(c.Xk, Bsrc[sp], {n, naux, o}, {naux * o, o, 1}, {n, n2, 1}, 1.0, 0.0, c.s);
     copyN(c.Yk, Bsrc[sp], {naux, o, n}, {(int64_t)o * n, n, 1}, {n2, n, 1}, 1.0, 0.0, c.s);
-    G(n, n, naux * o).A(c.Xk, naux * o, false).B(c.Yk, n, true).C(fout[sp], n).ab(-1.0, 1.0).run(c.s);
+    G(n, n, naux * o).A(c.Xk, naux * o, false).B(c.Yk, n, true).C(fout[sp], n).ab(-1.0, 1.0).run(c);
   }
 }
 
@@ -109,9 +128,9 @@ static void dress(Ctx& c, double* X, const double* t1, int64_t batch) {
   const int n = c.n, o = c.o, v = c.v;
   const int64_t n2 = c.n2;
   // X[:, 0:o] += X[:, o:n] t1^T
-  G(n, o, v).A(X + o, n, false).B(t1, v, false).C(X, n).ab(1.0, 1.0).batch(batch, n2, 0, n2).run(c.s);
+  G(n, o, v).A(X + o, n, false).B(t1, v, false).C(X, n).ab(1.0, 1.0).batch(batch, n2, 0, n2).run(c);
   // X[o:n, :] -= t1^T X[0:o, :]
-  G(v, n, o).A(t1, v, true).B(X, n, true).C(X + (int64_t)o * n, n).ab(-1.0, 1.0).batch(batch, 0, n2, n2).run(c.s);
+  G(v, n, o).A(t1, v, true).B(X, n, true).C(X + (int64_t)o * n, n).ab(-1.0, 1.0).batch(batch, 0, n2, n2).run(c);
 }
 
 void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipStream_t stream) {
@@ -124,6 +143,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   if (cfg.max_iter < 1) throw ArgError("max_iter must be >= 1");
   if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
   if (!(cfg.level_shift >= 0.0)) throw ArgError("level_shift must be >= 0");
+  if (cfg.precond != DCSD_PRECOND_ORBITAL && cfg.precond != DCSD_PRECOND_EN) throw ArgError("unknown precond");
   if (!Bin || !Fin) throw ArgError("B and F must be device pointers");
   B = Bin;
   F = Fin;
@@ -164,6 +184,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     KJPQ[sp] = alloc(2 * o2 * n2);
   }
   Bl = alloc(NA * n * vu);
+  Jpq = alloc(n2);
+  Kpq = alloc(n2);
   Isc = alloc(tov * tov);
   if (cfg.method == DCSD_METHOD_CCSD) {
     Icc = alloc(tov * tov);
@@ -207,6 +229,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   Smt = alloc(rows_main * (int64_t)n * v);
   split_cap = 32;
   split = alloc(split_cap * rows_all * (int64_t)lb * lb);
+  gws_cap = std::max<int64_t>(1 << 22, 64 * (int64_t)v * v);
+  gws = alloc(gws_cap);
   part = alloc(1024);
   scal = alloc(8 + 64);
   flag = alloc_int(4);
@@ -247,14 +271,14 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     for (int k = 0; k < nc; ++k) w[k] = 2.0;
     DCSD_HIP(hipMemcpyAsync(fvec, w.data(), K2 * sizeof(double), hipMemcpyHostToDevice, s));
     DCSD_HIP(hipStreamSynchronize(s));
-    G(NA, 1, K2).A(Xk, K2, false).B(fvec, 1, true).C(Jv, 1).run(s);
+    G(NA, 1, K2).A(Xk, K2, false).B(fvec, 1, true).C(Jv, 1).run(*this);
     DCSD_HIP(hipMemcpyAsync(h[0], F, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-    G(1, n2, NA).A(Jv, NA, false).B(B, n2, true).C(h[0], n2).ab(-1.0, 1.0).run(s);
+    G(1, n2, NA).A(Jv, NA, false).B(B, n2, true).C(h[0], n2).ab(-1.0, 1.0).run(*this);
     // exchange: X[p][(P,k)] = c_k B[P,p,k] (c = 1 core, 1/2 open), Y[(P,k)][q] = B[P,k,q]
     copyN(Xk, B, {n, NA, K2}, {NA * K2, K2, 1}, {n, n2, 1}, 1.0, 0.0, s);
     copyN(Xk + nc, B + nc, {n, NA, 2}, {NA * K2, K2, 1}, {n, n2, 1}, 0.5, 0.0, s);
     copyN(Yk, B, {NA, K2, n}, {(int64_t)K2 * n, n, 1}, {n2, n, 1}, 1.0, 0.0, s);
-    G(n, n, NA * K2).A(Xk, NA * K2, false).B(Yk, n, true).C(h[0], n).ab(1.0, 1.0).run(s);
+    G(n, n, NA * K2).A(Xk, NA * K2, false).B(Yk, n, true).C(h[0], n).ab(1.0, 1.0).run(*this);
     swap_tu(h[1], h[0], 1, n, nc, s);
   }
   // ---- Fock matrices of Phi_A (undressed) ------------------------------------------
@@ -265,7 +289,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   // ---- (kc|ld) in the spin-conserving particle-hole layout --------------------------
   for (int sp = 0; sp < 2; ++sp)
     copyN(Bov + sp * ov, Bs[sp] + o, {NA, o, v}, {tov, v, 1}, {n2, n, 1}, 1.0, 0.0, s);
-  G(tov, tov, NA).A(Bov, tov, true).B(Bov, tov, true).C(Isc, tov).run(s);
+  G(tov, tov, NA).A(Bov, tov, true).B(Bov, tov, true).C(Isc, tov).run(*this);
 
   // Permuted copies used by the X, Y and hole-hole intermediates.
   const int64_t vt = (int64_t)v * tov;
@@ -297,6 +321,10 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     copyN(Isf1, Isc + ov * tov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
     copyN(Isf2, Isc + ov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
   }
+  // ---- Coulomb/exchange matrices J_pq = (pp|qq), K_pq = (pq|qp) for the Epstein-Nesbet diagonal
+  copyN(Xk, B, {NA, n}, {n, 1}, {n2, n + 1}, 1.0, 0.0, s);  // B[P][p][p]
+  G(n, n, NA).A(Xk, n, true).B(Xk, n, true).C(Jpq, n).run(*this);
+  sumsq_batch(Kpq, B, NA, n2, s);
   // ---- ladder factor Bl[P][p][c] = B[P][p][nc + c], c over [t, u, virt] ------------
   copyN(Bl, B + nc, {NA, n, vu}, {(int64_t)n * vu, vu, 1}, {n2, n, 1}, 1.0, 0.0, s);
 
@@ -371,16 +399,16 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
       copyN(fvec + sp * ov, ft[sp] + o, {o, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);             // f~_kc
     }
     // sum_kc f~_kc t_ik^ac
-    G(tov, 1, tov).A(Tsc, tov, false).B(fvec, 1, true).C(R1, 1).ab(1.0, 1.0).run(s);
+    G(tov, 1, tov).A(Tsc, tov, false).B(fvec, 1, true).C(R1, 1).ab(1.0, 1.0).run(*this);
     // Z[P][(s,i,c)] = sum_{(s',k,d)} B~_ov[P][(s',k,d)] t_ik^cd
-    G(NA, tov, tov).A(Bov, tov, false).B(Tsc, tov, true).C(Z, tov).run(s);
+    G(NA, tov, tov).A(Bov, tov, false).B(Tsc, tov, true).C(Z, tov).run(*this);
     for (int sp = 0; sp < 2; ++sp) {
       // + sum_P sum_c B~[P][a][c] Z[P][i][c]
       G(v, o, v).A(Bt[sp] + (int64_t)o * n + o, n, false).B(Z + sp * ov, v, false).C(out1, o)
-          .batch(NA, n2, tov, ov).run(s);
+          .batch(NA, n2, tov, ov).run(*this);
       batch_reduce(R1 + sp * ov, out1, NA, ov, v, o, o, v, true, 1.0, s);
       // - sum_P sum_k B~[P][k][i] Z[P][k][a]
-      G(o, v, o).A(Bt[sp], n, true).B(Z + sp * ov, v, true).C(out2, v).batch(NA, n2, tov, ov).run(s);
+      G(o, v, o).A(Bt[sp], n, true).B(Z + sp * ov, v, true).C(out2, v).batch(NA, n2, tov, ov).run(*this);
       batch_reduce(R1 + sp * ov, out2, NA, ov, o, v, v, v, false, -1.0, s);
     }
   }
@@ -388,17 +416,17 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
   // ---- driver and ring terms (particle-hole layout) -------------------------------
   // Dvo[(s,i,a),(s',j,b)] = (ai|bj)~
   if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING))
-    G(tov, tov, NA).A(Bvo, tov, true).B(Bvo, tov, true).C(Dvo, tov).run(s);
+    G(tov, tov, NA).A(Bvo, tov, true).B(Bvo, tov, true).C(Dvo, tov).run(*this);
   if (!(mask & DCSD_TERM_DRIVER)) fill(Dvo, 0.0, tov * tov, s);
   if (mask & (DCSD_TERM_RING | DCSD_TERM_HH)) {
     // OOOO[(s,k,i),(s',l,j)] = (ki|lj)~
-    G(2 * o2, 2 * o2, NA).A(Boo, 2 * o2, true).B(Boo, 2 * o2, true).C(OOOO, 2 * o2).run(s);
+    G(2 * o2, 2 * o2, NA).A(Boo, 2 * o2, true).B(Boo, 2 * o2, true).C(OOOO, 2 * o2).run(*this);
   }
   if (mask & DCSD_TERM_RING) {
     // KCBJ[(s,k,c),(s',j,b)] = (kc|bj)~ ; KJPQ[s'][(s,k,j)][(p,q)] = (kj|pq)~
-    G(tov, tov, NA).A(Bov, tov, true).B(Bvo, tov, true).C(KCBJ, tov).run(s);
+    G(tov, tov, NA).A(Bov, tov, true).B(Bvo, tov, true).C(KCBJ, tov).run(*this);
     for (int sp = 0; sp < 2; ++sp)
-      G(2 * o2, n2, NA).A(Boo, 2 * o2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).run(s);
+      G(2 * o2, n2, NA).A(Boo, 2 * o2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).run(*this);
     // W_sc = <kb||cj>~ = (kc|bj)~ - (kj|bc)~ (equal spins)
     for (int sp = 0; sp < 2; ++sp) {
       const int64_t base = sp * ov * (tov + 1);
@@ -406,20 +434,20 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
             {o * n2, 1, n2, n}, -1.0, 1.0, s);
     }
     // + 1/2 <kl||cd> t_jl^bd  (DCSD: direct (kc|ld) only)
-    G(tov, tov, tov).A(cc ? Icc : Isc, tov, false).B(Tsc, tov, true).C(KCBJ, tov).ab(0.5, 1.0).run(s);
+    G(tov, tov, tov).A(cc ? Icc : Isc, tov, false).B(Tsc, tov, true).C(KCBJ, tov).ab(0.5, 1.0).run(*this);
     // Ring_sc = T_sc W_sc
-    G(tov, tov, tov).A(Tsc, tov, false).B(KCBJ, tov, true).C(Ring, tov).run(s);
+    G(tov, tov, tov).A(Tsc, tov, false).B(KCBJ, tov, true).C(Ring, tov).run(*this);
     // spin-flip: Wsf1[(K,c),(J,b)] = -(KJ|bc)~, Wsf2[(k,C),(j,B)] = -(kj|BC)~
     copyN(Wsf1, KJPQ[0] + o2 * n2 + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0,
           0.0, s);
     copyN(Wsf2, KJPQ[1] + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0, 0.0, s);
     if (cc) {
       // + 1/2 I_sf1 Tsf1 and + 1/2 I_sf2 Tsf1^T
-      G(ov, ov, ov).A(Isf1, ov, false).B(Tsf1, ov, true).C(Wsf1, ov).ab(0.5, 1.0).run(s);
-      G(ov, ov, ov).A(Isf2, ov, false).B(Tsf1, ov, false).C(Wsf2, ov).ab(0.5, 1.0).run(s);
+      G(ov, ov, ov).A(Isf1, ov, false).B(Tsf1, ov, true).C(Wsf1, ov).ab(0.5, 1.0).run(*this);
+      G(ov, ov, ov).A(Isf2, ov, false).B(Tsf1, ov, false).C(Wsf2, ov).ab(0.5, 1.0).run(*this);
     }
-    G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).run(s);
-    G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).run(s);
+    G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).run(*this);
+    G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).run(*this);
   } else {
     fill(Ring, 0.0, tov * tov, s);
     fill(Rsf1, 0.0, s2, s);
@@ -454,19 +482,19 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
     for (int sp = 0; sp < 2; ++sp) {
       // X[b][d] = sum (kc|ld)_ss t2ss[k,l,b,c] - sum (kd|L C) t2ab[k,L,b,C]   (alpha)
       copyN(P1, t2p[sp], {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {v, ov2, vv, 1}, 1.0, 0.0, s);
-      G(v, v, o2 * v).A(P1, o2 * v, false).B(QX1[sp], v, true).C(Xv[sp], v).run(s);
+      G(v, v, o2 * v).A(P1, o2 * v, false).B(QX1[sp], v, true).C(Xv[sp], v).run(*this);
       if (sp == 0)
         copyN(P2, t2ab, {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {v, ov2, vv, 1}, 1.0, 0.0, s);
       else  // t2ab[l,K,c,B] -> [B][l][K][c]
         copyN(P2, t2ab, {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {1, ov2, vv, v}, 1.0, 0.0, s);
-      G(v, v, o2 * v).A(P2, o2 * v, false).B(QX2[sp], v, true).C(Xv[sp], v).ab(-1.0, 1.0).run(s);
+      G(v, v, o2 * v).A(P2, o2 * v, false).B(QX2[sp], v, true).C(Xv[sp], v).ab(-1.0, 1.0).run(*this);
       // Y[l][j] = -sum (kc|ld) t2ss[j,k,c,d] + sum (KC|ld) t2ab[j,K,d,C]   (alpha)
-      G(o, o, ov2).A(QY1[sp], ov2, false).B(t2p[sp], ov2, false).C(Yo[sp], o).ab(-1.0, 0.0).run(s);
+      G(o, o, ov2).A(QY1[sp], ov2, false).B(t2p[sp], ov2, false).C(Yo[sp], o).ab(-1.0, 0.0).run(*this);
       if (sp == 0) {
-        G(o, o, ov2).A(QY2[0], ov2, false).B(t2ab, ov2, false).C(Yo[0], o).ab(1.0, 1.0).run(s);
+        G(o, o, ov2).A(QY2[0], ov2, false).B(t2ab, ov2, false).C(Yo[0], o).ab(1.0, 1.0).run(*this);
       } else {
         copyN(P2, t2ab, {o, o, v, v}, {ov2, vv, v, 1}, {vv, ov2, v, 1}, 1.0, 0.0, s);  // [J][k][c][D]
-        G(o, o, ov2).A(QY2[1], ov2, false).B(P2, ov2, false).C(Yo[1], o).ab(1.0, 1.0).run(s);
+        G(o, o, ov2).A(QY2[1], ov2, false).B(P2, ov2, false).C(Yo[1], o).ab(1.0, 1.0).run(*this);
       }
       // F~vv = f~_vv + s X,  F~oo = f~_oo + s Y
       copyN(Fvv[sp], ft[sp] + (int64_t)o * n + o, {v, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);
@@ -476,19 +504,19 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
     }
     for (int sp = 0; sp < 2; ++sp) {
       // P(ab) sum_d t_ij^ad F_bd
-      G(o2 * v, v, v).A(t2ss[sp], v, false).B(Fvv[sp], v, false).C(P1, v).run(s);
+      G(o2 * v, v, v).A(t2ss[sp], v, false).B(Fvv[sp], v, false).C(P1, v).run(*this);
       copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, v, 1}, 1.0, 1.0, s);
       copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, 1, v}, -1.0, 1.0, s);
       // -P(ij) sum_l t_il^ab F_lj
-      G(o, vv, o).A(Foo[sp], o, true).B(t2ss[sp], vv, true).C(P1, vv).batch(o, 0, ov2, ov2).run(s);
+      G(o, vv, o).A(Foo[sp], o, true).B(t2ss[sp], vv, true).C(P1, vv).batch(o, 0, ov2, ov2).run(*this);
       copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, v, 1}, -1.0, 1.0, s);
       copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {vv, ov2, v, 1}, 1.0, 1.0, s);
     }
     // alpha-beta
-    G(o2 * v, v, v).A(t2ab, v, false).B(Fvv[1], v, false).C(R2ab, v).ab(1.0, 1.0).run(s);
-    G(v, v, v).A(Fvv[0], v, false).B(t2ab, v, true).C(R2ab, v).ab(1.0, 1.0).batch(o2, 0, vv, vv).run(s);
-    G(o, vv, o).A(Foo[1], o, true).B(t2ab, vv, true).C(R2ab, vv).ab(-1.0, 1.0).batch(o, 0, ov2, ov2).run(s);
-    G(o, ov2, o).A(Foo[0], o, true).B(t2ab, ov2, true).C(R2ab, ov2).ab(-1.0, 1.0).run(s);
+    G(o2 * v, v, v).A(t2ab, v, false).B(Fvv[1], v, false).C(R2ab, v).ab(1.0, 1.0).run(*this);
+    G(v, v, v).A(Fvv[0], v, false).B(t2ab, v, true).C(R2ab, v).ab(1.0, 1.0).batch(o2, 0, vv, vv).run(*this);
+    G(o, vv, o).A(Foo[1], o, true).B(t2ab, vv, true).C(R2ab, vv).ab(-1.0, 1.0).batch(o, 0, ov2, ov2).run(*this);
+    G(o, ov2, o).A(Foo[0], o, true).B(t2ab, ov2, true).C(R2ab, ov2).ab(-1.0, 1.0).run(*this);
   }
 
   // ---- hole-hole ladder -----------------------------------------------------------
@@ -502,8 +530,8 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
       const double* t2b = blk == 0 ? t2aa : (blk == 1 ? t2bb : t2ab);
       double* Rb2 = blk == 0 ? R2ss[0] : (blk == 1 ? R2ss[1] : R2ab);
       if (cc)  // + 1/2 <kl||cd> t_ij^cd  ->  sum_cd (kc|ld) t_ij^cd (x 1/2 for equal spins)
-        G(o2, o2, vv).A(Ikl[blk], vv, false).B(t2b, vv, false).C(Whh, o2).ab(blk == 2 ? 1.0 : 0.5, 1.0).run(s);
-      G(o2, vv, o2).A(Whh, o2, true).B(t2b, vv, true).C(Rb2, vv).ab(1.0, 1.0).run(s);
+        G(o2, o2, vv).A(Ikl[blk], vv, false).B(t2b, vv, false).C(Whh, o2).ab(blk == 2 ? 1.0 : 0.5, 1.0).run(*this);
+      G(o2, vv, o2).A(Whh, o2, true).B(t2b, vv, true).C(Rb2, vv).ab(1.0, 1.0).run(*this);
     }
   }
 
@@ -526,7 +554,7 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
         int ks = (int)std::min<int64_t>(split_cap, std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1)));
         ks = (int)std::min<int64_t>(ks, std::max<int64_t>(1, vu2 / 1024));
         rec = tbegin(&ev0);
-        G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(s);
+        G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
         if (rec) tend(ev0, 2.0 * (double)M * (double)N * (double)vu2, 1);
         ladder_scatter(Rp, Rb, M, rows_main, o2, n, p0, np, q0, nq, diag, s);
       }

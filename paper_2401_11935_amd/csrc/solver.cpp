@@ -71,7 +71,8 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
       if (rep) *rep = r;
       return DCSD_OK;
     }
-    jacobi(Tn, Ev, T, Rw, f[0], f[1], o, v, n, cfg.level_shift, total, s);
+    const bool en = cfg.precond == DCSD_PRECOND_EN;
+    jacobi(Tn, Ev, T, Rw, f[0], f[1], en ? Jpq : nullptr, en ? Kpq : nullptr, nc, o, v, n, cfg.level_shift, total, s);
     if (m > 0) {
       const int slot = count % m;
       ++count;

@@ -26,7 +26,7 @@ class Config(ctypes.Structure):
                 ("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("diis_dim", ctypes.c_int32),
                 ("diis_start", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_residual", ctypes.c_double), ("level_shift", ctypes.c_double),
-                ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32)]
+                ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32), ("precond", ctypes.c_int32)]
 
 
 class Energies(ctypes.Structure):
@@ -121,6 +121,8 @@ def default_config(lib=None, **kw) -> Config:
     for k, v in kw.items():
         if k == "method" and isinstance(v, str):
             v = METHODS[v]
+        if k == "precond" and isinstance(v, str):
+            v = {"mp": 0, "orbital": 0, "en": 1}[v]
         setattr(c, k, v)
     return c
 

@@ -6,6 +6,8 @@ CPU oracle (``oracle/``) on the seeded synthetic inputs of ``dcsd_synth``.
 
 tiny:   converged 2D-DCSD and 2D-CCSD energies (tol 1e-10) at nc=3, nv=16,
         naux=60, seed 0, plus the per-iteration trajectory.
+small:  converged energies at nc=8, nv=20, naux=60, seed 1 (the largest of
+        these synthetic inputs on which the iterations converge from zero).
 medium: nc=8, nv=200, naux=600, seed 1: residual at seeded random amplitudes
         sampled at 4096 seeded positions (for both methods), and the converged
         energies of both methods.
@@ -57,13 +59,16 @@ def sampled_residual(cfg, method):
             "res_norm2": float(np.dot(R, R)), "seconds": time.time() - t0}
 
 
+SMALL = synth.Config("small", nc=8, nv=20, naux=60, seed=1)
+
+
 def main(which):
-    cfg = synth.TINY if which == "tiny" else synth.MEDIUM
+    cfg = {"tiny": synth.TINY, "small": SMALL, "medium": synth.MEDIUM}[which]
     out = {"config": {"nc": cfg.nc, "nv": cfg.nv, "naux": cfg.naux, "seed": cfg.seed}}
     for method in ("dcsd", "ccsd"):
         out[method] = {"residual": sampled_residual(cfg, method)}
-        if which == "tiny" or "--no-solve" not in sys.argv:
-            out[method]["solve"] = converged(cfg, method, 1e-10 if which == "tiny" else 1e-9)
+        if which != "medium" or "--no-solve" not in sys.argv:
+            out[method]["solve"] = converged(cfg, method, 1e-9 if which == "medium" else 1e-10)
         path = os.path.join(HERE, f"{which}.json")
         with open(path, "w") as f:
             json.dump(out, f, indent=1)

@@ -45,7 +45,7 @@ def test_amplitude_count_and_defaults(lib):
     assert L.amplitude_count(-1, 3, L.load(LIB)) == -1
     c = L.default_config(L.load(LIB))
     assert c.method == 0 and c.diis_dim == 8 and c.max_iter == 200 and c.term_mask == L.TERM_ALL
-    assert ctypes.sizeof(L.Config) == 56
+    assert ctypes.sizeof(L.Config) == 64
 
 
 def test_init_rejects_bad_arguments_without_touching_the_gpu(lib):

@@ -122,3 +122,43 @@ def test_residual_symmetries():
         assert np.abs(blk[k] + blk[k].transpose(1, 0, 2, 3)).max() < 1e-15
         assert np.abs(blk[k] + blk[k].transpose(0, 1, 3, 2)).max() < 1e-15
     assert blk["t2ab"][2, 2, 0, 0] == 0.0
+
+
+def _antisym_unit(model, x):
+    """Unit perturbation of packed element x respecting the antisymmetry of
+    same-spin doubles."""
+    nc, nv = model.nc, model.nv
+    blk = synth.block_offsets(nc, nv)
+    e = np.zeros(model.size)
+    for name in ("t2aa", "t2bb"):
+        off, shp = blk[name]
+        if off <= x < off + int(np.prod(shp)):
+            i, j, a, b = np.unravel_index(x - off, shp)
+            for (p, q, r, s_, sg) in ((i, j, a, b, 1), (j, i, a, b, -1), (i, j, b, a, -1), (j, i, b, a, 1)):
+                e[off + np.ravel_multi_index((p, q, r, s_), shp)] = sg
+            return e
+    e[x] = 1.0
+    return e
+
+
+@pytest.mark.parametrize("method", ["ccsd", "dcsd"])
+def test_en_shift_is_the_jacobian_diagonal(method):
+    """The Epstein-Nesbet preconditioner equals the diagonal of dR/dT at T = 0
+    (coupling and DC terms are quadratic or higher there), checked by central
+    differences on random elements of every block."""
+    B, F = synth.make_inputs(2, 4, 12, 3)
+    m = TwoDet(B, F, 2, method)
+    D, s = m.denominators(), m.en_shift()
+    rng = np.random.default_rng(0)
+    h = 1e-5
+    for name, (off, shp) in synth.block_offsets(2, 4).items():
+        for x in off + rng.choice(int(np.prod(shp)), 8, replace=False):
+            if x == m.ab:
+                continue
+            if name in ("t2aa", "t2bb"):
+                i, j, a, b = np.unravel_index(x - off, shp)
+                if i == j or a == b:
+                    continue
+            e = _antisym_unit(m, x) * h
+            d = (m.connected(e)[x] - m.connected(-e)[x]) / (2 * h)
+            assert abs(d - (-D[x] + s[x])) < 1e-8
