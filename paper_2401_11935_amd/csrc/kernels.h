@@ -1,6 +1,8 @@
 // Launchers of the libdcsd device kernels (internal).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace dcsd {
@@ -23,8 +25,12 @@ void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, cons
                        const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
                        int64_t npair, int n, int nc, int o, int v, hipStream_t s);
 
-// coupling between the two determinants: R -= K(T) * W, R at the A->B double set to 0
-void coupling_apply(const double* T, double* R, const double* W_dev, int nc, int nv, hipStream_t s);
+// Coupling between the two determinants: R -= K(T) * W, R at the A->B double set to 0.
+// coupling_prepare expands the per-pattern term tables on the host (once);
+// the term blob is copied to device memory and passed to coupling_apply.
+void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vector<char>& term_blob);
+void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* R,
+                    const double* W_dev, int nc, int nv, hipStream_t s);
 
 // reductions (deterministic); `part` needs 1024 doubles
 void dot(const double* x, const double* y, int64_t n, double* out_dev, double* part, hipStream_t s);

@@ -258,6 +258,16 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     }
   }
 
+  // ---- coupling term tables (host expansion, one upload) ------------------------
+  {
+    std::vector<char> blob;
+    coupling_prepare(nc, nv, coup_launch, blob);
+    coup_terms = alloc(((int64_t)blob.size() + 7) / 8);
+    if (!blob.empty()) {
+      DCSD_HIP(hipMemcpyAsync(coup_terms, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+      DCSD_HIP(hipStreamSynchronize(s));
+    }
+  }
   // ---- beta-order factors: exchange t and u in both orbital indices ---------------
   swap_tu(Bs[1], Bs[0], NA, n, nc, s);
 
@@ -566,7 +576,7 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
   // ---- coupling of the two determinants ---------------------------------------------
   DCSD_HIP(hipMemcpyAsync(scal, R + ab_pos, sizeof(double), hipMemcpyDeviceToDevice, s));  // W
   if (mask & DCSD_TERM_COUPLING) {
-    coupling_apply(Tw, R, scal, nc, nv, s);
+    coupling_apply(coup_launch, coup_terms, Tw, R, scal, nc, nv, s);
   } else {
     fill(R + ab_pos, 0.0, 1, s);
   }
