@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "2D-DCSD residual evals/s & TFLOP/s, FP64 vs mixed at 1 µEh, nc=12 nv=400"
 FP64_PEAK_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA peaks of MI355X
 HBM_PEAK_GBS = 8000.0
 
 
@@ -40,6 +41,9 @@ def parse():
     ap.add_argument("--level-shift", type=float, default=1.0)
     ap.add_argument("--cpu-slabs", type=int, default=6, help="oracle ladder slabs timed for cpu_baseline (0 = skip)")
     ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per assembly launch")
+    ap.add_argument("--precisions", default="fp32,bf16",
+                    help="low precisions compared with FP64 (residual evals at the same amplitudes; '' = skip)")
+    ap.add_argument("--evals", type=int, default=3, help="timed residual evaluations per precision")
     return ap.parse_args()
 
 
@@ -107,6 +111,90 @@ def cpu_baseline(nc, nv, naux, seed, slabs):
             "sample": f"oracle pp-ladder (vvvv term) on {len(pick)} of {len(sp_all)} spatial virtual slabs, "
                       f"{dt:.1f} s, scaled linearly to all slabs; other oracle terms not timed",
             "seconds_sampled": dt}
+
+
+def residual_rate(L, torch, cfg, Bd, Fd, stream, T, evals):
+    """Times `evals` dcsd_residual calls (after one untimed call) at amplitudes T
+    and returns the residual, W, wall-clock and HIP-event kernel timings."""
+    ctx = L.Context(cfg, Bd.data_ptr(), Fd.data_ptr(), stream)
+    R = torch.empty_like(T)
+    W = ctx.residual(T.data_ptr(), R.data_ptr())
+    torch.cuda.synchronize()
+    ctx.timing_start()
+    t0 = time.perf_counter()
+    for _ in range(evals):
+        ctx.residual(T.data_ptr(), R.data_ptr(), want_W=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / evals
+    tim = ctx.timing_stop()
+    ctx.close()
+    return R, W, dt, tim
+
+
+def precision_comparison(L, torch, args, Bd, Fd, stream, fm):
+    """FP64 against low-precision ladder/ring GEMMs on the same amplitudes: the
+    first Jacobi iterate from T = 0 (first-order amplitudes), where the
+    solver spends its first step."""
+    nc, nv, naux = args.nc, args.nv, args.naux
+    base = dict(nc=nc, nv=nv, naux=naux, method=args.method, ladder_block=args.ladder_block, precond=args.precond,
+                level_shift=args.level_shift)
+    ctx = L.Context(L.default_config(max_iter=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
+    T = torch.zeros(ctx.size, dtype=torch.float64, device=Bd.device)
+    ctx.solve(T.data_ptr())
+    ctx.close()
+    out = {"amplitudes": "first Jacobi iterate from T = 0 (first-order doubles)", "evals_timed": args.evals}
+    R64, W64, dt64, tim64 = residual_rate(L, torch, L.default_config(**base), Bd, Fd, stream, T, args.evals)
+    rmax = float(R64.abs().max())
+    out["fp64"] = {"residual_evals_per_s": 1.0 / dt64, "ms_per_eval": 1e3 * dt64, "max_abs_R": rmax, "W": W64,
+                   "kernels": tim64}
+    for prec in [p for p in args.precisions.split(",") if p]:
+        print(f"bench: residual evals in {prec}", file=sys.stderr, flush=True)
+        R, W, dt, tim = residual_rate(L, torch, L.default_config(precision=prec, **base), Bd, Fd, stream, T,
+                                      args.evals)
+        asm = tim["assembly"]
+        ach = asm["flops"] / (asm["ms"] * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
+        con = tim["contraction"]
+        ring = tim["ring"]
+        out[prec] = {
+            "residual_evals_per_s": 1.0 / dt, "ms_per_eval": 1e3 * dt, "speedup_vs_fp64": dt64 / dt,
+            "tflops": sum(fm.values()) / dt / 1e12,
+            "max_abs_dR": float((R - R64).abs().max()), "rel_dR": float((R - R64).abs().max()) / max(rmax, 1e-300),
+            "abs_dW": abs(W - W64),
+            "note": "dE_A is FP64 in every mode, so |dE_S| = |dE_T| = |dW| at the same amplitudes",
+            "roofline_assembly": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                                  "frac": ach / PEAK_TFLOPS[prec],
+                                  "avg_launch_ms": asm["ms"] / max(asm["launches"], 1)},
+            "contraction_tflops": con["flops"] / (con["ms"] * 1e-3) / 1e12 if con["ms"] > 0 else 0.0,
+            "ring_tflops": ring["flops"] / (ring["ms"] * 1e-3) / 1e12 if ring["ms"] > 0 else 0.0,
+            "kernels": tim,
+        }
+    return out
+
+
+def tiny_convergence(L, torch, stream):
+    """Mixed-precision solves of the tiny configuration (nc=3, nv=16, naux=60)
+    to max|R| <= 1e-10 beside the FP64 solve."""
+    import dcsd_synth as synth
+    cfg = synth.TINY
+    B, F = synth.make_config_inputs(cfg)
+    dev = torch.device("cuda:0")
+    Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
+    res = {"config": "nc=3 nv=16 naux=60 seed=0, 2D-DCSD, tol 1e-10"}
+    for prec in ("fp64", "fp32", "bf16"):
+        ctx = L.Context(L.default_config(nc=cfg.nc, nv=cfg.nv, naux=cfg.naux, precision=prec, tol_residual=1e-10),
+                        Bd.data_ptr(), Fd.data_ptr(), stream)
+        T = torch.zeros(ctx.size, dtype=torch.float64, device=dev)
+        t0 = time.perf_counter()
+        rep = ctx.solve(T.data_ptr())
+        torch.cuda.synchronize()
+        ctx.close()
+        res[prec] = {"status": rep["status"], "iterations": rep["iterations"],
+                     "fp64_evals": sum(r["fp64"] for r in rep["records"]), "E_S": rep["E_S"], "E_T": rep["E_T"],
+                     "seconds": time.perf_counter() - t0}
+    for prec in ("fp32", "bf16"):
+        res[prec]["abs_dE_S_vs_fp64"] = abs(res[prec]["E_S"] - res["fp64"]["E_S"])
+        res[prec]["abs_dE_T_vs_fp64"] = abs(res[prec]["E_T"] - res["fp64"]["E_T"])
+    return res
 
 
 def main():
@@ -184,6 +272,9 @@ def main():
         "E_S": rep["E_S"], "E_T": rep["E_T"],
     }
     ctx.close()
+    if args.precisions:
+        out["precisions"] = precision_comparison(L, torch, args, Bd, Fd, stream, fm)
+        out["mixed_convergence_tiny"] = tiny_convergence(L, torch, stream)
     if args.cpu_slabs > 0:
         print("bench: timing the oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nc, nv, naux, args.seed, args.cpu_slabs)

@@ -59,7 +59,10 @@ typedef enum {
 } dcsd_status;
 
 enum { DCSD_METHOD_DCSD = 0, DCSD_METHOD_CCSD = 1 };
-enum { DCSD_PREC_FP64 = 0 };
+/* Arithmetic of the particle-particle ladder and ring GEMMs (everything else
+ * is FP64 in every mode): FP64 MFMA, or FP32 / BF16 MFMA inputs (rounded to
+ * nearest even through FP32) with FP32 accumulation, added into FP64. */
+enum { DCSD_PREC_FP64 = 0, DCSD_PREC_FP32 = 1, DCSD_PREC_BF16 = 2 };
 /* Jacobi preconditioner: orbital-energy denominators D, or D minus the
  * two-electron (Epstein-Nesbet) part of the diagonal of dR/dT at T = 0. */
 enum { DCSD_PRECOND_ORBITAL = 0, DCSD_PRECOND_EN = 1 };
@@ -79,7 +82,7 @@ enum {
 typedef struct {
   int32_t nc, nv, naux;   /* core (doubly occupied) orbitals, virtuals, DF rank */
   int32_t method;         /* DCSD_METHOD_DCSD or DCSD_METHOD_CCSD               */
-  int32_t precision;      /* DCSD_PREC_FP64                                     */
+  int32_t precision;      /* DCSD_PREC_FP64, DCSD_PREC_FP32 or DCSD_PREC_BF16   */
   int32_t diis_dim;       /* DIIS subspace size (0 = plain Jacobi)              */
   int32_t diis_start;     /* first iteration that extrapolates                  */
   int32_t max_iter;
@@ -88,6 +91,9 @@ typedef struct {
   int32_t ladder_block;   /* orbitals per ladder batch side (0 = automatic)    */
   uint32_t term_mask;     /* DCSD_TERM_* bits                                   */
   int32_t precond;        /* DCSD_PRECOND_ORBITAL or DCSD_PRECOND_EN            */
+  int32_t refresh_every;  /* low precision only: FP64 residual every k-th iteration of
+                             dcsd_solve (0 = only when the corrected residual
+                             reaches tol_residual)                               */
 } dcsd_config;
 
 typedef struct {
@@ -103,6 +109,8 @@ typedef struct {
   int32_t converged;  /* 1 if max |R| <= tol_residual                        */
   double res_max;     /* max |R| of the last residual                        */
   dcsd_energies e;    /* energies of the last amplitudes                     */
+  int32_t fp64;       /* 1 if res_max and e come from an FP64 residual (every
+                         record in FP64 mode; refresh records otherwise)     */
 } dcsd_report;
 
 typedef void (*dcsd_iter_cb)(const dcsd_report* it, void* user);
@@ -138,7 +146,21 @@ dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energ
  * vectors in FP64 on the device, until max |R| <= tol_residual.  T_inout
  * receives the final amplitudes; *out the final report; cb (may be NULL) is
  * called after every residual evaluation.  Returns DCSD_ERR_NOCONV after
- * max_iter evaluations, DCSD_ERR_NONFINITE on Inf/NaN. */
+ * max_iter evaluations, DCSD_ERR_NONFINITE on Inf/NaN.
+ *
+ * With precision FP32 or BF16 the iterations use the low-precision residual.
+ * A refresh evaluates the FP64 residual at the current amplitudes T_r, takes
+ * the step with it and records T_r: the amplitudes of the ladder with the
+ * FP64 ladder result, and the changing operands of each ring GEMM with its
+ * FP64 product.  After the first refresh, low-precision iterations evaluate
+ * L(tau) = L(tau_r) + L_low(tau - tau_r) and A B = (A B)_r + (A - A_r) B +
+ * A_r (B - B_r) with only the differences rounded, so their error shrinks
+ * with |T - T_r|.  A refresh happens when the low-precision residual reaches
+ * tol_residual, when it has set no new minimum for 3 iterations (its noise
+ * floor), and every refresh_every iterations (if > 0).  Convergence is
+ * declared only on a refresh whose FP64 residual meets tol_residual, so the
+ * converged amplitudes solve the FP64 equations to the same tolerance.  A
+ * refresh iteration costs one low-precision plus one FP64 evaluation. */
 dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user);
 
 /* Changes the solver settings of an existing context (max_iter,
@@ -150,7 +172,8 @@ dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg);
 /* Kernel timing, measured with HIP events recorded on the context's stream
  * around every launch of the ladder integral assembly (DF GEMM building
  * (pc|qd) for a batch of orbital pairs), of the ladder contraction with the
- * amplitudes, and around each whole residual evaluation.  `flops` is the
+ * amplitudes, of the ring GEMMs (with their operand rounding in low
+ * precision), and around each whole residual evaluation.  `flops` is the
  * algorithmic count (2 per multiply-add) of the launches recorded. */
 typedef struct {
   double ms;        /* summed event-to-event duration */
@@ -162,6 +185,7 @@ typedef struct {
   dcsd_kernel_time assembly;    /* ladder integral assembly (MFMA, K = naux)   */
   dcsd_kernel_time contraction; /* ladder contraction (MFMA, K = (nv+2)^2)     */
   dcsd_kernel_time residual;    /* whole dcsd_residual evaluations             */
+  dcsd_kernel_time ring;        /* ring GEMMs (2ov x 2ov and ov x ov blocks)   */
 } dcsd_timing;
 
 /* Starts recording (clears earlier records).  The first call creates the
@@ -178,11 +202,14 @@ const char* dcsd_last_error(const dcsd_ctx* ctx);
 /* Releases all device memory of the context (NULL is allowed). */
 void dcsd_destroy(dcsd_ctx* ctx);
 
-/* Diagnostic (not part of the method): C = A * B in FP64 through the
- * library's MFMA GEMM, with A (M x K) and B (K x N) row-major device arrays
- * and C (M x N) row-major.  Returns DCSD_ERR_ARG on non-positive sizes. */
-dcsd_status dcsd_selftest_gemm(int64_t M, int64_t N, int64_t K, const double* A_dev, const double* B_dev,
-                               double* C_dev, void* hip_stream);
+/* Diagnostic (not part of the method): C = A * B through the library's
+ * MFMA GEMM of the given precision (DCSD_PREC_*; FP32 and BF16 round A and B
+ * and accumulate in FP32, splitting K when the output has few tiles), with A
+ * (M x K) and B (K x N) row-major FP64 device arrays and C (M x N) row-major
+ * FP64.  Returns DCSD_ERR_ARG on non-positive sizes or an unknown precision;
+ * low precision allocates (and frees) temporary device memory. */
+dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t K, const double* A_dev,
+                               const double* B_dev, double* C_dev, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -5,7 +5,7 @@ to zero reaches the same amplitudes.  The one used on both sides:
 
 * start from T = 0;
 * iteration k: R = residual(T); stop if max|R| <= tol;
-  T_new = T + R / (D - s - shift)   (D = f_ii + f_jj - f_aa - f_bb from the
+  T_new = T + R / (D - s - shift)   (no step where R = 0 exactly; D = f_ii + f_jj - f_aa - f_bb from the
   diagonal of the reference Fock matrix; s = 0, or with
   ``precond="en"`` the two-electron (Epstein-Nesbet) part of the diagonal of
   dR/dT at T = 0; shift >= 0 only damps the step);
@@ -55,7 +55,10 @@ def solve(model, tol: float = 1e-10, max_iter: int = 200, diis_dim: int = 8,
         if rmax <= tol:
             converged = True
             break
-        Tn = T + R / D
+        # an element with R = 0 exactly takes no step: the A->B double, whose
+        # residual is zero by definition and whose Epstein-Nesbet denominator
+        # vanishes as well (both determinants have the same diagonal)
+        Tn = T + np.divide(R, D, out=np.zeros_like(R), where=R != 0.0)
         err = Tn - T
         if diis_dim > 0:
             hist_T.append(Tn)

@@ -58,6 +58,7 @@ void dcsd_default_config(dcsd_config* c) {
   c->ladder_block = 0;
   c->term_mask = DCSD_TERM_ALL;
   c->precond = DCSD_PRECOND_ORBITAL;
+  c->refresh_every = 0;
 }
 
 dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
@@ -132,7 +133,7 @@ dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg) {
     if (cfg->nc != c.nc || cfg->nv != c.nv || cfg->naux != c.naux || cfg->method != c.method ||
         cfg->precision != c.precision || cfg->diis_dim != c.diis_dim || cfg->ladder_block != c.ladder_block)
       throw dcsd::ArgError("only solver settings may change after dcsd_init");
-    if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0) ||
+    if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0) || cfg->refresh_every < 0 ||
         (cfg->precond != DCSD_PRECOND_ORBITAL && cfg->precond != DCSD_PRECOND_EN))
       throw dcsd::ArgError("invalid solver settings");
     ctx->c.cfg = *cfg;
@@ -161,7 +162,7 @@ dcsd_status dcsd_timing_stop(dcsd_ctx* ctx, dcsd_timing* out) {
     DCSD_HIP(hipStreamSynchronize(c.s));
     c.timing = false;
     dcsd_timing t{};
-    dcsd_kernel_time* k[3] = {&t.assembly, &t.contraction, &t.residual};
+    dcsd_kernel_time* k[4] = {&t.assembly, &t.contraction, &t.residual, &t.ring};
     for (const auto& r : c.recs) {
       float ms = 0.f;
       DCSD_HIP(hipEventElapsedTime(&ms, r.a, r.b));
@@ -189,21 +190,54 @@ void dcsd_destroy(dcsd_ctx* ctx) {
   delete ctx;
 }
 
-dcsd_status dcsd_selftest_gemm(int64_t M, int64_t N, int64_t K, const double* A_dev, const double* B_dev,
-                               double* C_dev, void* hip_stream) {
+dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t K, const double* A_dev,
+                               const double* B_dev, double* C_dev, void* hip_stream) {
   if (M <= 0 || N <= 0 || K <= 0 || !A_dev || !B_dev || !C_dev) return DCSD_ERR_ARG;
-  try {
-    dcsd::GemmArgs g;
-    g.M = M; g.N = N; g.K = K;
-    g.A = A_dev; g.lda = K; g.a_mc = false;
-    g.B = B_dev; g.ldb = N; g.b_nc = true;
-    g.C = C_dev; g.ldc = N; g.c_nc = true;
-    dcsd::gemm_f64(g, (hipStream_t)hip_stream);
-    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return DCSD_ERR_HIP;
-  } catch (...) {
-    return DCSD_ERR_HIP;
+  if (precision != DCSD_PREC_FP64 && precision != DCSD_PREC_FP32 && precision != DCSD_PREC_BF16) return DCSD_ERR_ARG;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  if (precision == DCSD_PREC_FP64) {
+    try {
+      dcsd::GemmArgs g;
+      g.M = M; g.N = N; g.K = K;
+      g.A = A_dev; g.lda = K; g.a_mc = false;
+      g.B = B_dev; g.ldb = N; g.b_nc = true;
+      g.C = C_dev; g.ldc = N; g.c_nc = true;
+      dcsd::gemm_f64(g, st);
+      if (hipStreamSynchronize(st) != hipSuccess) return DCSD_ERR_HIP;
+    } catch (...) {
+      return DCSD_ERR_HIP;
+    }
+    return DCSD_OK;
   }
-  return DCSD_OK;
+  const int64_t ld = dcsd::lp_ld(K);
+  const size_t es = dcsd::lp_size(precision);
+  void *a = nullptr, *b = nullptr;
+  float* w = nullptr;
+  const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+  const int ks = (tiles < 16 && K >= 256) ? 4 : 1;  // exercises the split-K path on small outputs
+  dcsd_status st_out = DCSD_OK;
+  try {
+    if (hipMalloc(&a, M * ld * es) != hipSuccess || hipMalloc(&b, N * ld * es) != hipSuccess ||
+        (ks > 1 && hipMalloc((void**)&w, ks * M * N * sizeof(float)) != hipSuccess))
+      throw dcsd::HipError("allocation failed");
+    dcsd::lp_convert(precision, a, ld, A_dev, nullptr, M, K, K, 1, st);  // a[m][k] = A[m][k]
+    dcsd::lp_convert(precision, b, ld, B_dev, nullptr, N, K, 1, N, st);  // b[n][k] = B[k][n]
+    dcsd::LpGemm q;
+    q.precision = precision;
+    q.M = M; q.N = N; q.K = K;
+    q.A = a; q.lda = ld; q.B = b; q.ldb = ld;
+    q.C = C_dev; q.ldc = N;
+    q.ks = ks; q.work = w;
+    dcsd::lp_gemm(q, st);
+    if (hipStreamSynchronize(st) != hipSuccess) st_out = DCSD_ERR_HIP;
+  } catch (...) {
+    st_out = DCSD_ERR_HIP;
+  }
+  (void)hipStreamSynchronize(st);
+  if (a) (void)hipFree(a);
+  if (b) (void)hipFree(b);
+  if (w) (void)hipFree(w);
+  return st_out;
 }
 
 }  // extern "C"

@@ -69,6 +69,28 @@ struct Ctx {
   int64_t rows_main = 0, rows_all = 0;
   double *Tstack = nullptr, *V2 = nullptr, *Rb = nullptr, *Rp = nullptr, *Smt = nullptr, *split = nullptr;
   int64_t split_cap = 0;
+  // low precision (allocated only when cfg.precision != FP64)
+  int prec_now = DCSD_PREC_FP64;      // precision of the ladder and ring GEMMs of the current evaluation
+  // How the low-precision GEMMs of an evaluation relate to the last refresh
+  // point T_r: PLAIN rounds the operands themselves; RECORD (an FP64
+  // evaluation) stores the FP64 operands and products at T_r; DELTA adds the
+  // stored FP64 products to low-precision products of the operand changes.
+  enum Mode { PLAIN = 0, RECORD = 1, DELTA = 2 };
+  int mode = PLAIN;
+  void* BlT = nullptr;                 // Bl transposed to [(p,c)][P], row stride ldk
+  void *TstackL = nullptr, *V2L = nullptr;  // rows of stride kp
+  void *lpA = nullptr, *lpB = nullptr; // rounded ring operands, lp_cap elements each
+  float* lwork = nullptr;              // FP32 split-K partials, lwork_cap floats
+  int64_t ldk = 0, kp = 0, lp_cap = 0, lwork_cap = 0;
+  double *TstackR = nullptr, *RpR = nullptr;  // ladder amplitudes and spatial ladder result at T_r
+  bool ladder_ref = false;
+  // ring GEMM sites: FP64 operands (those that change with T) and product at T_r
+  struct Site {
+    double *Ar = nullptr, *Br = nullptr, *Pr = nullptr;
+    bool valid = false;
+  };
+  static constexpr int kSites = 6;
+  Site site[kSites];
   // scalars and reductions
   double* part = nullptr;
   double* scal = nullptr;  // [0] W, [1] res max, [2] dE_A, [3] dot, ...
@@ -97,7 +119,9 @@ struct Ctx {
   void release();
 
   void init(const dcsd_config& c, const double* B, const double* F, hipStream_t stream);
-  void residual(const double* T, double* R, double* W_host);
+  // prec < 0: the configured precision; DCSD_PREC_FP64 forces an FP64 evaluation.
+  // mode: PLAIN, RECORD (FP64 only) or DELTA (low precision with a recorded reference).
+  void residual(const double* T, double* R, double* W_host, int prec = -1, int mode = PLAIN);
   double energy_A(const double* T);
   int solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user);
 };

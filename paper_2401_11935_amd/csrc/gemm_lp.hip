@@ -1,0 +1,360 @@
+// Low-precision GEMMs on the CDNA4 matrix cores with FP32 accumulation:
+// FP32 inputs (v_mfma_f32_16x16x4_f32) or BF16 inputs (v_mfma_f32_16x16x32_bf16).
+//
+// Both operands are K-contiguous in memory, A(m,k) = A[m*lda + k] and
+// B(k,n) = B[n*ldb + k], with lda and ldb multiples of 8 elements and
+// 16-byte aligned bases, so that every global load is one 16-byte vector and
+// every LDS row stays 16-byte aligned.  Tiles of 128 x 128 per workgroup of
+// four waves (2 x 2, 64 x 64 each), K staged through double-buffered LDS rows
+// padded to a bank-conflict-free stride.
+//
+// Epilogues: FP32 split-K partials (reduced into FP64 in a fixed order), the
+// pair-blocked ladder integrals V2[(p,q)][c][d] in the input precision, or a
+// direct FP64 update C = alpha*AB + beta*C.
+#include <hip/hip_bf16.h>
+
+#include "../../include/libdcsd.h"
+#include "kernels.h"
+
+namespace dcsd {
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr int NT = 256;
+constexpr int TILE = 128;
+
+enum { EPI_SPLIT = 0, EPI_PAIRS = 1, EPI_F64 = 2 };
+
+struct LArgs {
+  int64_t M, N, K;
+  const void* A;
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  void* C;
+  int64_t ldc;
+  int c_nc;
+  double alpha, beta;
+  int64_t kchunk, tiles_n, split_stride;
+  int64_t vu, nq, kp;  // pair-blocked output
+};
+
+template <class T>
+struct Traits;
+template <>
+struct Traits<float> {
+  static constexpr int VL = 4;     // elements per 16-byte load
+  static constexpr int KSTEP = 4;  // K per MFMA
+  static constexpr int BK = 16;
+  static constexpr int ROW = 20;   // LDS row stride (elements): 80 bytes
+};
+template <>
+struct Traits<__bf16> {
+  static constexpr int VL = 8;
+  static constexpr int KSTEP = 32;
+  static constexpr int BK = 64;
+  static constexpr int ROW = 72;   // 144 bytes
+};
+
+// Rounding of an FP32 value to the storage precision, nearest even, written
+// out so that the result does not depend on how the compiler lowers casts
+// (a quiet NaN stays a NaN).
+template <class T>
+__device__ inline T lp_round(float x);
+template <>
+__device__ inline float lp_round<float>(float x) { return x; }
+template <>
+__device__ inline __bf16 lp_round<__bf16>(float x) {
+  uint32_t b = __float_as_uint(x);
+  const uint16_t h = (b & 0x7fffffffu) > 0x7f800000u ? (uint16_t)0x7fc0u
+                                                      : (uint16_t)((b + 0x7fffu + ((b >> 16) & 1u)) >> 16);
+  return __builtin_bit_cast(__bf16, h);
+}
+
+template <class T>
+__device__ inline uint4 load_chunk(const T* p, int64_t kk, int64_t kend) {
+  constexpr int VL = Traits<T>::VL;
+  if (kk + VL <= kend) return *reinterpret_cast<const uint4*>(p);
+  union {
+    uint4 u;
+    T e[VL];
+  } x;
+#pragma unroll
+  for (int e = 0; e < VL; ++e) x.e[e] = (kk + e < kend) ? p[e] : (T)0.0f;
+  return x.u;
+}
+
+template <class T, int EPI, bool SPLIT>
+__global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
+  constexpr int VL = Traits<T>::VL;
+  constexpr int BK = Traits<T>::BK;
+  constexpr int KSTEP = Traits<T>::KSTEP;
+  constexpr int ROW = Traits<T>::ROW;
+  constexpr int CPR = BK / VL;               // 16-byte chunks per row
+  constexpr int CH = TILE * CPR / NT;        // chunks per thread per operand
+  constexpr int WM = TILE / 2, WN = TILE / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  __shared__ __attribute__((aligned(16))) T sA[2][TILE * ROW];
+  __shared__ __attribute__((aligned(16))) T sB[2][TILE * ROW];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = ((int64_t)blockIdx.x / g.tiles_n) * TILE;
+  const int64_t n0 = ((int64_t)blockIdx.x % g.tiles_n) * TILE;
+  int64_t kbeg = 0, kend = g.K;
+  if (SPLIT) {
+    kbeg = (int64_t)blockIdx.z * g.kchunk;
+    kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  }
+  const T* A = (const T*)g.A;
+  const T* B = (const T*)g.B;
+
+  uint4 ra[CH], rb[CH];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = tid + c * NT;
+      const int r = e / CPR, kc = (e % CPR) * VL;
+      const int64_t kk = k0 + kc;
+      const int64_t gm = m0 + r, gn = n0 + r;
+      ra[c] = (gm < g.M && kk < kend) ? load_chunk<T>(A + gm * g.lda + kk, kk, kend) : uint4{0u, 0u, 0u, 0u};
+      rb[c] = (gn < g.N && kk < kend) ? load_chunk<T>(B + gn * g.ldb + kk, kk, kend) : uint4{0u, 0u, 0u, 0u};
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = tid + c * NT;
+      const int r = e / CPR, kc = (e % CPR) * VL;
+      *reinterpret_cast<uint4*>(&sA[buf][r * ROW + kc]) = ra[c];
+      *reinterpret_cast<uint4*>(&sB[buf][r * ROW + kc]) = rb[c];
+    }
+  };
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
+  if (nk > 0) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  const int lrow = lane >> 4, lcol = lane & 15;
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nk) load(kbeg + (kt + 1) * BK);
+    const T* a_s = sA[buf];
+    const T* b_s = sB[buf];
+#pragma unroll
+    for (int ks = 0; ks < BK / KSTEP; ++ks) {
+      if constexpr (VL == 4) {
+        // lane supplies A[m = lane%16][k = lane/16] and B[k = lane/16][n = lane%16]
+        float af[TM], bf[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = a_s[(wm * WM + i * 16 + lcol) * ROW + ks * KSTEP + lrow];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bf[j] = b_s[(wn * WN + j * 16 + lcol) * ROW + ks * KSTEP + lrow];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+      } else {
+        // lane supplies A[m = lane%16][k = 8*(lane/16) + e] and B[k = 8*(lane/16) + e][n = lane%16]
+        bf8 af[TM], bf[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          af[i] = *reinterpret_cast<const bf8*>(&a_s[(wm * WM + i * 16 + lcol) * ROW + ks * KSTEP + lrow * 8]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bf[j] = *reinterpret_cast<const bf8*>(&b_s[(wn * WN + j * 16 + lcol) * ROW + ks * KSTEP + lrow * 8]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  // FP32 16 x 16 accumulators: element r of a lane is D[4*(lane/16) + r][lane%16]
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = m0 + wm * WM + i * 16 + 4 * lrow + r;
+        const int64_t gn = n0 + wn * WN + j * 16 + lcol;
+        if (gm >= g.M || gn >= g.N) continue;
+        const float val = acc[i][j][r];
+        if (EPI == EPI_PAIRS) {
+          // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]
+          const int64_t p = gm / g.vu, c = gm % g.vu, q = gn / g.vu, d = gn % g.vu;
+          ((T*)g.C)[(p * g.nq + q) * g.kp + c * g.vu + d] = lp_round<T>(val);
+        } else if (EPI == EPI_SPLIT) {
+          float* W = (float*)g.C + (SPLIT ? (int64_t)blockIdx.z * g.split_stride : 0);
+          W[gm * g.N + gn] = val;
+        } else {
+          double* C = (double*)g.C;
+          const int64_t off = g.c_nc ? gm * g.ldc + gn : gm + gn * g.ldc;
+          double out = g.alpha * (double)val;
+          if (g.beta != 0.0) out += g.beta * C[off];
+          C[off] = out;
+        }
+      }
+}
+
+// C(m,n) = alpha * sum_z W[z][m*N + n] + beta * C(m,n), summed in FP64 in z order.
+__global__ void lp_split_reduce(const float* W, double* C, int64_t M, int64_t N, int nsplit, int64_t ldc, int c_nc,
+                                double alpha, double beta) {
+  const int64_t MN = M * N;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < MN;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    double sum = 0.0;
+    for (int z = 0; z < nsplit; ++z) sum += (double)W[z * MN + idx];
+    const int64_t m = idx / N, nn = idx % N;
+    const int64_t off = c_nc ? m * ldc + nn : m + nn * ldc;
+    double out = alpha * sum;
+    if (beta != 0.0) out += beta * C[off];
+    C[off] = out;
+  }
+}
+
+// dst[r*ldd + c] = round(src[i] - sub[i]), i = r*sr + c*sc (sub may be NULL),
+// through a 64 x 64 LDS tile; the source is read along whichever of its axes
+// is contiguous.
+template <class T>
+__global__ __launch_bounds__(256) void lp_convert_kernel(T* dst, int64_t ldd, const double* src, const double* sub,
+                                                         int64_t rows, int64_t cols, int64_t sr, int64_t sc,
+                                                         int64_t tiles_c) {
+  __shared__ double tile[64][65];
+  const int64_t r0 = ((int64_t)blockIdx.x / tiles_c) * 64, c0 = ((int64_t)blockIdx.x % tiles_c) * 64;
+  const int tid = threadIdx.x;
+  const bool row_major_src = sc == 1;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int a = e / 64, b = e % 64;  // consecutive threads vary b
+    const int rr = row_major_src ? a : b, cc = row_major_src ? b : a;
+    const int64_t r = r0 + rr, c = c0 + cc;
+    double x = 0.0;
+    if (r < rows && c < cols) {
+      const int64_t i = r * sr + c * sc;
+      x = sub ? src[i] - sub[i] : src[i];
+    }
+    tile[rr][cc] = x;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int rr = e / 64, cc = e % 64;
+    const int64_t r = r0 + rr, c = c0 + cc;
+    if (r < rows && c < cols) dst[r * ldd + c] = lp_round<T>((float)tile[rr][cc]);
+  }
+}
+
+unsigned nb(int64_t total) {
+  int64_t b = (total + 255) / 256;
+  if (b > (1 << 20)) b = 1 << 20;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+template <class T>
+void launch_convert(void* dst, int64_t ldd, const double* src, const double* sub, int64_t rows, int64_t cols,
+                    int64_t sr, int64_t sc, hipStream_t s) {
+  const int64_t tr = (rows + 63) / 64, tc = (cols + 63) / 64;
+  if (tr * tc <= 0) return;
+  if (tr * tc >= ((int64_t)1 << 31)) throw ArgError("conversion too large");
+  hipLaunchKernelGGL(lp_convert_kernel<T>, dim3((unsigned)(tr * tc)), dim3(256), 0, s, (T*)dst, ldd, src, sub, rows,
+                     cols, sr, sc, tc);
+  DCSD_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_gemm(const LpGemm& q, hipStream_t s) {
+  LArgs a{};
+  a.M = q.M; a.N = q.N; a.K = q.K;
+  a.A = q.A; a.lda = q.lda; a.B = q.B; a.ldb = q.ldb;
+  a.alpha = q.alpha; a.beta = q.beta;
+  a.tiles_n = (q.N + TILE - 1) / TILE;
+  const int64_t tiles = ((q.M + TILE - 1) / TILE) * a.tiles_n;
+  if (q.ks <= 1) {
+    a.C = q.C; a.ldc = q.ldc; a.c_nc = q.c_nc ? 1 : 0;
+    a.kchunk = q.K;
+    hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_F64, false>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+    DCSD_CHECK_LAUNCH();
+    return;
+  }
+  int64_t chunk = (q.K + q.ks - 1) / q.ks;
+  chunk = (chunk + Traits<T>::BK - 1) / Traits<T>::BK * Traits<T>::BK;
+  const int ks = (int)((q.K + chunk - 1) / chunk);
+  a.C = q.work;
+  a.kchunk = chunk;
+  a.split_stride = q.M * q.N;
+  hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_SPLIT, true>), dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
+  DCSD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(lp_split_reduce, dim3(nb(q.M * q.N)), dim3(256), 0, s, (const float*)q.work, q.C, q.M, q.N, ks,
+                     q.ldc, q.c_nc ? 1 : 0, q.alpha, q.beta);
+  DCSD_CHECK_LAUNCH();
+}
+
+template <class T>
+void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_t p0, int64_t np, int64_t q0,
+                  int64_t nq, int64_t kp, void* V2, hipStream_t s) {
+  LArgs a{};
+  a.M = np * vu; a.N = nq * vu; a.K = naux;
+  a.A = (const T*)BlT + p0 * vu * ldk; a.lda = ldk;
+  a.B = (const T*)BlT + q0 * vu * ldk; a.ldb = ldk;
+  a.C = V2; a.vu = vu; a.nq = nq; a.kp = kp;
+  a.kchunk = naux;
+  a.tiles_n = (a.N + TILE - 1) / TILE;
+  const int64_t tiles = ((a.M + TILE - 1) / TILE) * a.tiles_n;
+  hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+  DCSD_CHECK_LAUNCH();
+}
+
+void check_lp(const LpGemm& q) {
+  if (q.M <= 0 || q.N <= 0 || q.K <= 0) throw ArgError("low-precision GEMM: empty shape");
+  if (q.lda % 8 || q.ldb % 8 || q.lda < q.K || q.ldb < q.K) throw ArgError("low-precision GEMM: bad leading dimension");
+  if (((uintptr_t)q.A | (uintptr_t)q.B) & 15) throw ArgError("low-precision GEMM: operands not 16-byte aligned");
+  if (q.ks > 1 && !q.work) throw ArgError("low-precision GEMM: split-K needs a workspace");
+}
+
+}  // namespace
+
+size_t lp_size(int precision) { return precision == DCSD_PREC_BF16 ? 2 : 4; }
+
+void lp_convert(int precision, void* dst, int64_t ldd, const double* src, const double* sub, int64_t rows,
+                int64_t cols, int64_t sr, int64_t sc, hipStream_t s) {
+  if (precision == DCSD_PREC_BF16)
+    launch_convert<__bf16>(dst, ldd, src, sub, rows, cols, sr, sc, s);
+  else
+    launch_convert<float>(dst, ldd, src, sub, rows, cols, sr, sc, s);
+}
+
+void lp_gemm(const LpGemm& q, hipStream_t s) {
+  check_lp(q);
+  if (q.precision == DCSD_PREC_BF16)
+    launch_gemm<__bf16>(q, s);
+  else
+    launch_gemm<float>(q, s);
+}
+
+void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_t p0, int64_t np,
+              int64_t q0, int64_t nq, int64_t kp, void* V2, hipStream_t s) {
+  if (ldk % 8 || kp % 8) throw ArgError("low-precision ladder: bad leading dimension");
+  if (precision == DCSD_PREC_BF16)
+    launch_pairs<__bf16>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
+  else
+    launch_pairs<float>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
+}
+
+}  // namespace dcsd

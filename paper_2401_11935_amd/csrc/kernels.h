@@ -42,6 +42,38 @@ void energy(const double* T, const double* Isc, const double* fa, const double* 
 void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb,
             const double* J, const double* K, int nc, int o, int v, int n, double shift, int64_t total,
             hipStream_t s);
+// ---- low precision: FP32 or BF16 MFMA inputs, FP32 accumulation ---------------------
+// Storage element size of a low precision (4 for DCSD_PREC_FP32, 2 for DCSD_PREC_BF16).
+size_t lp_size(int precision);
+// Leading dimension of low-precision K-contiguous rows: a multiple of 8 elements.
+inline int64_t lp_ld(int64_t k) { return (k + 7) / 8 * 8; }
+// dst[r*ldd + c] = src[i] - sub[i] (i = r*sr + c*sc; sub may be NULL) rounded (through FP32)
+// to the precision, r < rows, c < cols.
+void lp_convert(int precision, void* dst, int64_t ldd, const double* src, const double* sub, int64_t rows,
+                int64_t cols, int64_t sr, int64_t sc, hipStream_t s);
+// C(m,n) = alpha * sum_k A[m*lda + k] B[n*ldb + k] + beta * C(m,n), C in FP64 with the
+// GemmArgs c_nc convention.  lda, ldb: multiples of 8; A, B: 16-byte aligned.
+// ks > 1 splits K across workgroups; `work` then holds ks*M*N floats.
+struct LpGemm {
+  int precision = 0;
+  int64_t M = 0, N = 0, K = 0;
+  const void* A = nullptr;
+  int64_t lda = 0;
+  const void* B = nullptr;
+  int64_t ldb = 0;
+  double* C = nullptr;
+  int64_t ldc = 0;
+  bool c_nc = true;
+  double alpha = 1.0, beta = 0.0;
+  int ks = 1;
+  float* work = nullptr;
+};
+void lp_gemm(const LpGemm& g, hipStream_t s);
+// Pair-blocked ladder integrals V2[(p,q)][c][d] (row stride kp) = sum_P BlT[(p,c)][P] BlT[(q,d)][P]
+// for p in [p0, p0+np), q in [q0, q0+nq), in the low precision; BlT rows have stride ldk.
+void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_t p0, int64_t np,
+              int64_t q0, int64_t nq, int64_t kp, void* V2, hipStream_t s);
+
 void sumsq_batch(double* K, const double* B, int64_t nb, int64_t n2, hipStream_t s);
 void combine(double* T, const double* V, int64_t stride, const double* c, int m, int64_t n, hipStream_t s);
 

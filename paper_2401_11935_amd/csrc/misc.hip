@@ -30,7 +30,7 @@ void fill(double* p, double v, int64_t n, hipStream_t s) {
 
 __global__ void axpby_kernel(double* y, const double* x, double a, double b, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = a * x[i] + b * y[i];
+    y[i] = b == 0.0 ? a * x[i] : a * x[i] + b * y[i];  // b == 0: y is not read
 }
 void axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
   if (n <= 0) return;
@@ -256,7 +256,9 @@ __global__ void jacobi_kernel(double* Tn, double* E, const double* T, const doub
         D -= sEN;
       }
     }
-    const double step = R[x] / (D - shift);
+    // R = 0 exactly (the A->B double, whose Epstein-Nesbet denominator also
+    // vanishes): no step
+    const double step = R[x] == 0.0 ? 0.0 : R[x] / (D - shift);
     Tn[x] = T[x] + step;
     if (E) E[x] = step;
   }

@@ -73,6 +73,70 @@ struct G {
     }
     gemm_f64(a, c.s);
   }
+  // Ring GEMMs follow the precision and mode of the current evaluation
+  // (site: index of the call site; a_var / b_var: whether the operand changes
+  // with the amplitudes).  FP64: the MFMA GEMM; RECORD also stores the
+  // changing operands and the product P = A B at the refresh point.  Low
+  // precision: operands rounded into K-contiguous FP32/BF16 copies and
+  // multiplied on the low-precision MFMA with FP32 accumulation; DELTA uses
+  // A B = P_r + (A - A_r) B + A_r (B - B_r), rounding only the differences.
+  // C must be a compact row-major M x N matrix.  Timed as class 3.
+  void ring(Ctx& c, int site, bool a_var, bool b_var) {
+    hipEvent_t ev;
+    const int rec = c.tbegin(&ev);
+    if (a.ldc != a.N || !a.c_nc || a.batch != 1 || a.lda != (a.a_mc ? a.M : a.K) || a.ldb != (a.b_nc ? a.N : a.K))
+      throw ArgError("ring GEMM site with a non-compact layout");
+    Ctx::Site& st = c.site[site];
+    const int64_t MN = a.M * a.N;
+    if (c.prec_now == DCSD_PREC_FP64) {
+      if (c.mode == Ctx::RECORD && st.Pr) {
+        if (a_var) DCSD_HIP(hipMemcpyAsync(st.Ar, a.A, a.M * a.K * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+        if (b_var) DCSD_HIP(hipMemcpyAsync(st.Br, a.B, a.K * a.N * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+        G p(a.M, a.N, a.K);
+        p.a = a;
+        p.a.C = st.Pr;
+        p.a.alpha = 1.0;
+        p.a.beta = 0.0;
+        p.run(c);
+        axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
+        st.valid = true;
+      } else {
+        run(c);
+      }
+    } else if (c.mode == Ctx::DELTA && st.valid) {
+      axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
+      if (a_var) lp_product(c, a.A, st.Ar, a.B, nullptr);
+      if (b_var) lp_product(c, a_var ? st.Ar : a.A, nullptr, a.B, st.Br);
+    } else {
+      lp_product(c, a.A, nullptr, a.B, nullptr, a.beta);
+    }
+    if (rec) c.tend(ev, 2.0 * (double)a.M * (double)a.N * (double)a.K, 3);
+  }
+  // C = alpha * lp(A - Asub) lp(B - Bsub) + beta * C (subtrahends may be NULL).
+  void lp_product(Ctx& c, const double* A, const double* Asub, const double* B, const double* Bsub,
+                  double beta = 1.0) {
+    const int pr = c.prec_now;
+    const int64_t ld = lp_ld(a.K);
+    if (a.M * ld > c.lp_cap || a.N * ld > c.lp_cap) throw ArgError("ring operand exceeds the low-precision buffer");
+    // lpA[m][k] = A(m,k), lpB[n][k] = B(k,n)
+    lp_convert(pr, c.lpA, ld, A, Asub, a.M, a.K, a.a_mc ? 1 : a.lda, a.a_mc ? a.lda : 1, c.s);
+    lp_convert(pr, c.lpB, ld, B, Bsub, a.N, a.K, a.b_nc ? 1 : a.ldb, a.b_nc ? a.ldb : 1, c.s);
+    LpGemm q;
+    q.precision = pr;
+    q.M = a.M; q.N = a.N; q.K = a.K;
+    q.A = c.lpA; q.lda = ld; q.B = c.lpB; q.ldb = ld;
+    q.C = a.C; q.ldc = a.ldc; q.c_nc = a.c_nc;
+    q.alpha = a.alpha; q.beta = beta;
+    const int64_t tiles = ((a.M + 127) / 128) * ((a.N + 127) / 128);
+    int64_t ks = 1;
+    if (tiles < 256 && a.K >= 2048) {
+      ks = std::min<int64_t>(32, std::max<int64_t>(1, 1024 / tiles));
+      while (ks > 1 && ks * a.M * a.N > c.lwork_cap) ks /= 2;
+    }
+    q.ks = (int)ks;
+    q.work = c.lwork;
+    lp_gemm(q, c.s);
+  }
 };
 
 }  // namespace
@@ -138,7 +202,9 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   s = stream;
   if (cfg.nc < 0 || cfg.nv < 1 || cfg.naux < 1) throw ArgError("nc >= 0, nv >= 1 and naux >= 1 are required");
   if (cfg.method != DCSD_METHOD_DCSD && cfg.method != DCSD_METHOD_CCSD) throw ArgError("unknown method");
-  if (cfg.precision != DCSD_PREC_FP64) throw ArgError("only FP64 precision is available");
+  if (cfg.precision != DCSD_PREC_FP64 && cfg.precision != DCSD_PREC_FP32 && cfg.precision != DCSD_PREC_BF16)
+    throw ArgError("unknown precision");
+  if (cfg.refresh_every < 0) throw ArgError("refresh_every must be >= 0");
   if (cfg.diis_dim < 0 || cfg.diis_dim > 64) throw ArgError("diis_dim must be in [0, 64]");
   if (cfg.max_iter < 1) throw ArgError("max_iter must be >= 1");
   if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
@@ -229,6 +295,31 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   Smt = alloc(rows_main * (int64_t)n * v);
   split_cap = 32;
   split = alloc(split_cap * rows_all * (int64_t)lb * lb);
+  if (cfg.precision != DCSD_PREC_FP64) {
+    const int64_t es = (int64_t)lp_size(cfg.precision);
+    auto lp_alloc = [&](int64_t elems) { return (void*)alloc((elems * es + 7) / 8); };
+    ldk = lp_ld(NA);
+    kp = lp_ld(vu2);
+    BlT = lp_alloc((int64_t)n * vu * ldk);
+    TstackL = lp_alloc(rows_all * kp);
+    V2L = lp_alloc((int64_t)lb * lb * kp);
+    lp_cap = tov * lp_ld(tov);
+    lpA = lp_alloc(lp_cap);
+    lpB = lp_alloc(lp_cap);
+    lwork_cap = std::max<int64_t>(split_cap * rows_all * (int64_t)lb * lb, (int64_t)1 << 22);
+    lwork = (float*)alloc((lwork_cap + 1) / 2);
+    TstackR = alloc(rows_all * vu2);
+    RpR = alloc(rows_main * n2);
+    // ring sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 = spin-flip I T (CCSD); 4, 5 = spin-flip rings
+    const int64_t sz[Ctx::kSites] = {tov * tov, tov * tov, s2, s2, s2, s2};
+    const bool av[Ctx::kSites] = {false, true, false, false, true, true};
+    for (int k = 0; k < Ctx::kSites; ++k) {
+      if ((k == 2 || k == 3) && cfg.method != DCSD_METHOD_CCSD) continue;
+      if (av[k]) site[k].Ar = alloc(sz[k]);
+      site[k].Br = alloc(sz[k]);
+      site[k].Pr = alloc(sz[k]);
+    }
+  }
   gws_cap = std::max<int64_t>(1 << 22, 64 * (int64_t)v * v);
   gws = alloc(gws_cap);
   part = alloc(1024);
@@ -337,6 +428,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   sumsq_batch(Kpq, B, NA, n2, s);
   // ---- ladder factor Bl[P][p][c] = B[P][p][nc + c], c over [t, u, virt] ------------
   copyN(Bl, B + nc, {NA, n, vu}, {(int64_t)n * vu, vu, 1}, {n2, n, 1}, 1.0, 0.0, s);
+  // low precision: BlT[(p,c)][P] = round(Bl[P][p][c])
+  if (BlT) lp_convert(cfg.precision, BlT, ldk, Bl, nullptr, (int64_t)n * vu, NA, 1, (int64_t)n * vu, s);
 
   // ---- reference energy E_ref = 1/2 sum_s sum_{k<o} (h_kk + f_kk) --------------------
   {
@@ -354,7 +447,16 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
 }
 
 // ---------------------------------------------------------------------------
-void Ctx::residual(const double* T, double* R, double* W_host) {
+void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md) {
+  prec_now = prec < 0 ? cfg.precision : prec;
+  if (prec_now != DCSD_PREC_FP64 && !BlT) throw ArgError("low precision was not configured at init");
+  if ((md == RECORD && (prec_now != DCSD_PREC_FP64 || !BlT)) || (md == DELTA && prec_now == DCSD_PREC_FP64))
+    throw ArgError("invalid evaluation mode");
+  mode = md;
+  if (mode == RECORD) {
+    ladder_ref = false;
+    for (auto& x : site) x.valid = false;
+  }
   const uint32_t mask = cfg.term_mask;
   const int64_t NA = naux, o2 = (int64_t)o * o, vv = (int64_t)v * v, ov2 = o * vv;
   const bool cc = cfg.method == DCSD_METHOD_CCSD;
@@ -444,20 +546,20 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
             {o * n2, 1, n2, n}, -1.0, 1.0, s);
     }
     // + 1/2 <kl||cd> t_jl^bd  (DCSD: direct (kc|ld) only)
-    G(tov, tov, tov).A(cc ? Icc : Isc, tov, false).B(Tsc, tov, true).C(KCBJ, tov).ab(0.5, 1.0).run(*this);
+    G(tov, tov, tov).A(cc ? Icc : Isc, tov, false).B(Tsc, tov, true).C(KCBJ, tov).ab(0.5, 1.0).ring(*this, 0, false, true);
     // Ring_sc = T_sc W_sc
-    G(tov, tov, tov).A(Tsc, tov, false).B(KCBJ, tov, true).C(Ring, tov).run(*this);
+    G(tov, tov, tov).A(Tsc, tov, false).B(KCBJ, tov, true).C(Ring, tov).ring(*this, 1, true, true);
     // spin-flip: Wsf1[(K,c),(J,b)] = -(KJ|bc)~, Wsf2[(k,C),(j,B)] = -(kj|BC)~
     copyN(Wsf1, KJPQ[0] + o2 * n2 + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0,
           0.0, s);
     copyN(Wsf2, KJPQ[1] + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0, 0.0, s);
     if (cc) {
       // + 1/2 I_sf1 Tsf1 and + 1/2 I_sf2 Tsf1^T
-      G(ov, ov, ov).A(Isf1, ov, false).B(Tsf1, ov, true).C(Wsf1, ov).ab(0.5, 1.0).run(*this);
-      G(ov, ov, ov).A(Isf2, ov, false).B(Tsf1, ov, false).C(Wsf2, ov).ab(0.5, 1.0).run(*this);
+      G(ov, ov, ov).A(Isf1, ov, false).B(Tsf1, ov, true).C(Wsf1, ov).ab(0.5, 1.0).ring(*this, 2, false, true);
+      G(ov, ov, ov).A(Isf2, ov, false).B(Tsf1, ov, false).C(Wsf2, ov).ab(0.5, 1.0).ring(*this, 3, false, true);
     }
-    G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).run(*this);
-    G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).run(*this);
+    G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).ring(*this, 4, true, true);
+    G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).ring(*this, 5, true, true);
   } else {
     fill(Ring, 0.0, tov * tov, s);
     fill(Rsf1, 0.0, s2, s);
@@ -548,7 +650,10 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
   // ---- particle-particle ladder (DF-assembled, T1 back-transformed) -----------------
   if (mask & DCSD_TERM_PP) {
     const int64_t vu2 = (int64_t)vu * vu;
+    const bool low = prec_now != DCSD_PREC_FP64;
+    const bool delta = low && mode == DELTA && ladder_ref;  // contract lp(tau - tau_r), add L(tau_r)
     ladder_stack(Tstack, t2aa, t2bb, t2ab, pair_i, pair_j, o, v, vu, npair, rows_all, s);
+    if (low) lp_convert(prec_now, TstackL, kp, Tstack, delta ? TstackR : nullptr, rows_all, vu2, vu2, 1, s);
     for (int p0 = 0; p0 < n; p0 += lb) {
       const int np = std::min(lb, n - p0);
       for (int q0 = p0; q0 < n; q0 += lb) {
@@ -556,7 +661,10 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
         const bool diag = q0 == p0;
         hipEvent_t ev0;
         int rec = tbegin(&ev0);
-        gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
+        if (low)
+          lp_pairs(prec_now, BlT, ldk, NA, vu, p0, np, q0, nq, kp, V2L, s);
+        else
+          gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
         if (rec) tend(ev0, 2.0 * (double)np * vu * (double)nq * vu * (double)NA, 0);
         const int64_t M = diag ? rows_main : rows_all;
         const int64_t N = (int64_t)np * nq;
@@ -564,10 +672,27 @@ void Ctx::residual(const double* T, double* R, double* W_host) {
         int ks = (int)std::min<int64_t>(split_cap, std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1)));
         ks = (int)std::min<int64_t>(ks, std::max<int64_t>(1, vu2 / 1024));
         rec = tbegin(&ev0);
-        G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
+        if (low) {
+          LpGemm q;
+          q.precision = prec_now;
+          q.M = M; q.N = N; q.K = vu2;
+          q.A = TstackL; q.lda = kp; q.B = V2L; q.ldb = kp;
+          q.C = Rb; q.ldc = N;
+          q.ks = ks; q.work = lwork;
+          lp_gemm(q, s);
+        } else {
+          G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
+        }
         if (rec) tend(ev0, 2.0 * (double)M * (double)N * (double)vu2, 1);
         ladder_scatter(Rp, Rb, M, rows_main, o2, n, p0, np, q0, nq, diag, s);
       }
+    }
+    if (mode == RECORD) {
+      DCSD_HIP(hipMemcpyAsync(TstackR, Tstack, rows_all * vu2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      DCSD_HIP(hipMemcpyAsync(RpR, Rp, rows_main * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      ladder_ref = true;
+    } else if (delta) {
+      axpby(Rp, RpR, 1.0, 1.0, rows_main * n2, s);
     }
     ladder_mtransform(R2ss[0], R2ss[1], R2ab, Smt, Rp, t1[0], t1[1], pair_i, pair_j, rows_main, o2, npair, n, nc, o,
                       v, s);

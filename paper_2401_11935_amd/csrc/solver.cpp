@@ -1,7 +1,11 @@
 // Amplitude solver: Jacobi steps with orbital-energy denominators and Pulay
 // DIIS.  All vectors stay on the device in FP64; only the (m+1)^2 DIIS system,
 // the residual max-norm and the energies cross to the host (one
-// synchronisation per iteration).
+// synchronisation per iteration).  In low precision the iterations run the
+// low-precision residual, after the first refresh point in delta form (FP64
+// products at the refresh point plus low-precision products of the operand
+// changes); refreshes are FP64 evaluations and convergence is only accepted
+// on one of them.
 #include <cmath>
 #include <vector>
 
@@ -38,22 +42,59 @@ bool solve_dense(std::vector<double>& A, std::vector<double>& b, int n) {
 
 int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
   const int m = cfg.diis_dim;
+  const bool low = cfg.precision != DCSD_PREC_FP64;
   std::vector<double> gram((size_t)std::max(m, 1) * std::max(m, 1), 0.0);
   std::vector<int> order;  // slots from oldest to newest
   int count = 0;
   dcsd_report r{};
-  for (int it = 0; it < cfg.max_iter; ++it) {
-    residual(T, Rw, nullptr);
+  bool have_ref = false;  // a refresh point has been recorded
+  int since = 0;          // low-precision iterations since the last refresh
+  double ref_res = 0.0;   // FP64 max |R| at the last refresh
+  double best = 0.0;      // smallest corrected max |R| since the last refresh, and its iteration
+  int best_it = -1;
+  // max |Rw|, energies of Tw and W; one synchronisation
+  auto measure = [&](double host[3], int& bad) {
     int zero = 0;
     DCSD_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
     DCSD_HIP(hipStreamSynchronize(s));
     maxabs(Rw, total, scal + 1, flag, part, s);
     energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
-    double host[3];
-    int bad = 0;
     DCSD_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipStreamSynchronize(s));
+  };
+  for (int it = 0; it < cfg.max_iter; ++it) {
+    residual(T, Rw, nullptr, -1, low && have_ref ? DELTA : PLAIN);
+    double host[3];
+    int bad = 0;
+    measure(host, bad);
+    bool exact = !low;
+    // refresh when the low-precision residual meets the tolerance, has dropped
+    // by kDrop since the last refresh, has made no new minimum for kStall
+    // iterations (it sits on its noise floor), or every refresh_every iterations
+    constexpr int kStall = 3;
+    const double kDrop = cfg.precision == DCSD_PREC_BF16 ? 1e-2 : 1e-5;
+    if (low && (best_it < 0 || host[1] < best)) {
+      best = host[1];
+      best_it = it;
+    }
+    const bool stalled = low && it - best_it >= kStall;
+    if (it == 0) ref_res = host[1];
+    const bool dropped = low && host[1] <= kDrop * ref_res;
+    if (low && !bad && (host[1] <= cfg.tol_residual || stalled || dropped ||
+                        (cfg.refresh_every > 0 && since + 1 >= cfg.refresh_every))) {
+      // refresh: FP64 residual at T, recorded as the new reference point
+      residual(T, Rw, nullptr, DCSD_PREC_FP64, RECORD);
+      measure(host, bad);
+      have_ref = true;
+      since = 0;
+      exact = true;
+      best = host[1];
+      best_it = it;
+      ref_res = host[1];
+    } else if (low) {
+      ++since;
+    }
     r.iterations = it + 1;
     r.res_max = host[1];
     r.e.W = host[0];
@@ -61,7 +102,8 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
     r.e.E_S = host[2] + host[0];
     r.e.E_T = host[2] - host[0];
     r.e.E_ref_A = e_ref;
-    r.converged = (!bad && host[1] <= cfg.tol_residual) ? 1 : 0;
+    r.fp64 = exact ? 1 : 0;
+    r.converged = (!bad && exact && host[1] <= cfg.tol_residual) ? 1 : 0;
     if (cb) cb(&r, user);
     if (bad || !std::isfinite(host[0]) || !std::isfinite(host[2])) {
       if (rep) *rep = r;

@@ -17,6 +17,7 @@ DEFAULT_PATH = os.path.join(HERE, "lib", "libdcsd.so")
 DCSD_OK, DCSD_ERR_ARG, DCSD_ERR_OOM, DCSD_ERR_HIP, DCSD_ERR_NOCONV, DCSD_ERR_NONFINITE, DCSD_ERR_STATE = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_OOM", "ERR_HIP", "ERR_NOCONV", "ERR_NONFINITE", "ERR_STATE"]
 METHODS = {"dcsd": 0, "ccsd": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 TERM = {"driver": 1, "fock": 2, "hh": 4, "pp": 8, "ring": 16, "singles": 32, "coupling": 64}
 TERM_ALL = 0x7F
 
@@ -26,7 +27,8 @@ class Config(ctypes.Structure):
                 ("method", ctypes.c_int32), ("precision", ctypes.c_int32), ("diis_dim", ctypes.c_int32),
                 ("diis_start", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_residual", ctypes.c_double), ("level_shift", ctypes.c_double),
-                ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32), ("precond", ctypes.c_int32)]
+                ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32), ("precond", ctypes.c_int32),
+                ("refresh_every", ctypes.c_int32)]
 
 
 class Energies(ctypes.Structure):
@@ -39,10 +41,11 @@ class Energies(ctypes.Structure):
 
 class Report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("res_max", ctypes.c_double),
-                ("e", Energies)]
+                ("e", Energies), ("fp64", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        d = {"iterations": self.iterations, "converged": bool(self.converged), "res_max": self.res_max}
+        d = {"iterations": self.iterations, "converged": bool(self.converged), "res_max": self.res_max,
+             "fp64": bool(self.fp64)}
         d.update(self.e.as_dict())
         return d
 
@@ -55,7 +58,8 @@ class KernelTime(ctypes.Structure):
 
 
 class Timing(ctypes.Structure):
-    _fields_ = [("assembly", KernelTime), ("contraction", KernelTime), ("residual", KernelTime)]
+    _fields_ = [("assembly", KernelTime), ("contraction", KernelTime), ("residual", KernelTime),
+                ("ring", KernelTime)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k).as_dict() for k, _ in self._fields_}
@@ -104,7 +108,8 @@ def load(path: str | None = None):
     lib.dcsd_timing_start.restype = ctypes.c_int
     lib.dcsd_timing_stop.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.dcsd_timing_stop.restype = ctypes.c_int
-    lib.dcsd_selftest_gemm.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, dp, dp, vp]
+    lib.dcsd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, dp, dp,
+                                       vp]
     lib.dcsd_selftest_gemm.restype = ctypes.c_int
     if path is None:
         _lib = lib
@@ -123,6 +128,8 @@ def default_config(lib=None, **kw) -> Config:
             v = METHODS[v]
         if k == "precond" and isinstance(v, str):
             v = {"mp": 0, "orbital": 0, "en": 1}[v]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISIONS[v]
         setattr(c, k, v)
     return c
 
@@ -211,7 +218,10 @@ class Context:
             pass
 
 
-def selftest_gemm(M: int, N: int, K: int, A_ptr: int, B_ptr: int, C_ptr: int, stream: int = 0, lib=None):
-    st = (lib or load()).dcsd_selftest_gemm(M, N, K, A_ptr, B_ptr, C_ptr, stream or None)
+def selftest_gemm(M: int, N: int, K: int, A_ptr: int, B_ptr: int, C_ptr: int, stream: int = 0, lib=None,
+                  precision=0):
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    st = (lib or load()).dcsd_selftest_gemm(precision, M, N, K, A_ptr, B_ptr, C_ptr, stream or None)
     if st != DCSD_OK:
         raise DcsdError(st, "selftest_gemm")
