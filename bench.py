@@ -26,6 +26,51 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}  # dense MFMA peaks 
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_ladder_assembly_fp64_nc12_nv400_naux1200.json")
+ASSEMBLY_KERNEL = "gemm_kernel<128, 128, true, true, true, false, 1>"
+ASSEMBLY_SOURCE = os.path.join(ROOT, "paper_2401_11935_amd", "csrc", "gemm.hip")
+
+
+def source_hash(path):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def traffic_from_pmc(fetch_csv, write_csv, calib_mib, out_path):
+    """Per-launch HBM traffic of the FP64 ladder assembly from rocprofv3
+    FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by the factor that
+    makes the calibration copy (the first copy kernel of calib_mib MiB) read
+    and write exactly its size."""
+    import csv
+
+    def per_kernel(path):
+        rows = list(csv.DictReader(open(path)))
+        copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        asm = [float(r["Counter_Value"]) for r in rows if ASSEMBLY_KERNEL in r["Kernel_Name"]]
+        return copy[0], asm
+    cf, af = per_kernel(fetch_csv)
+    cw, aw = per_kernel(write_csv)
+    kib = calib_mib * 1024.0
+    fs, ws = kib / cf, kib / cw
+    fetch = sum(af) / len(af) * fs * 1024.0
+    write = sum(aw) / len(aw) * ws * 1024.0
+    rec = {"kernel": ASSEMBLY_KERNEL, "source": os.path.relpath(ASSEMBLY_SOURCE, ROOT),
+           "source_sha256": source_hash(ASSEMBLY_SOURCE), "launches": len(af),
+           "calibration_copy_mib": calib_mib, "fetch_scale": fs, "write_scale": ws,
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write, "bytes_per_launch": fetch + write}
+    json.dump(rec, open(out_path, "w"), indent=1)
+    return rec
+
+
+def load_traffic(path):
+    if not path or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != source_hash(ASSEMBLY_SOURCE):
+        return None  # the kernel changed since the counters were taken
+    return rec["bytes_per_launch"]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -40,10 +85,16 @@ def parse():
     ap.add_argument("--precond", default="en", choices=["en", "orbital"])
     ap.add_argument("--level-shift", type=float, default=1.0)
     ap.add_argument("--cpu-slabs", type=int, default=6, help="oracle ladder slabs timed for cpu_baseline (0 = skip)")
-    ap.add_argument("--traffic", type=str, default="", help="JSON file with measured HBM bytes per assembly launch")
+    ap.add_argument("--traffic", type=str, default=TRAFFIC_JSON,
+                    help="JSON record of the measured HBM bytes per assembly launch (ignored if the kernel changed)")
+    ap.add_argument("--traffic-from-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic record from two rocprofv3 --pmc counter_collection CSVs "
+                         "(FETCH_SIZE, WRITE_SIZE) of a run with --copy-calibration-mib, then exit")
     ap.add_argument("--precisions", default="fp32,bf16",
                     help="low precisions compared with FP64 (residual evals at the same amplitudes; '' = skip)")
     ap.add_argument("--evals", type=int, default=3, help="timed residual evaluations per precision")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -199,6 +250,10 @@ def tiny_convergence(L, torch, stream):
 
 def main():
     args = parse()
+    if args.traffic_from_pmc:
+        rec = traffic_from_pmc(*args.traffic_from_pmc, args.copy_calibration_mib or 1024, args.traffic)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus > 1 is not supported"}))
         sys.exit(2)
@@ -216,6 +271,15 @@ def main():
     Fd = torch.from_numpy(F).to(dev)
     del B
     stream = torch.cuda.current_stream(dev).cuda_stream
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"bench: calibration copy of {args.copy_calibration_mib} MiB done", file=sys.stderr, flush=True)
+        del src, dst
     cfg = L.default_config(nc=nc, nv=nv, naux=naux, method=args.method, max_iter=max(args.warmup, 1),
                            ladder_block=args.ladder_block, precond=args.precond, level_shift=args.level_shift)
     t0 = time.perf_counter()
@@ -241,9 +305,7 @@ def main():
     flops_eval = sum(fm.values())
     asm = tim["assembly"]
     achieved = asm["flops"] / (asm["ms"] * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    traffic = load_traffic(args.traffic)
     out = {
         "metric": METRIC,
         "value": steps / elapsed,
