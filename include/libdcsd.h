@@ -163,6 +163,39 @@ dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energ
  * refresh iteration costs one low-precision plus one FP64 evaluation. */
 dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user);
 
+/* Vector-Jacobian product of one residual evaluation (hand-written reverse
+ * mode through every step of dcsd_residual and of the quantities dcsd_init
+ * builds from B and F).  The map is (T, B, F) -> (R, W, dE_A), R as returned by
+ * dcsd_residual and dE_A the energy expression of Phi_A at T (dcsd_energy);
+ * given the cotangents Rbar_dev (packed, like R), Wbar and EAbar it writes
+ *   Tbar = Rbar.dR/dT + Wbar dW/dT + EAbar ddE_A/dT   (packed; 0 at the A->B double),
+ *   Bbar = the same with respect to every entry of B[naux][n][n] as stored,
+ *   Fbar = the same with respect to F[n][n],
+ * each output optional (NULL: not computed; Bbar and Fbar NULL skips the pass
+ * through the constants).  B and F are differentiated entry by entry, not as
+ * symmetric matrices.  Always FP64.  The first call allocates the tape's
+ * cotangent arrays (kept until dcsd_destroy, about the size of the context's
+ * work memory again); every call allocates and frees operand snapshots. */
+dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* Rbar_dev, double Wbar, double EAbar,
+                              double* Tbar_dev, double* Bbar_dev, double* Fbar_dev);
+
+/* Gradient of E = ebar_S E_S + ebar_T E_T (correlation energies, E_ref
+ * excluded) at converged amplitudes T_dev with respect to B and F, through the
+ * Lagrangian L = E + lambda . R (Theory section: the 2D amplitude equations
+ * hold at T, so dE/dB = dL/dB at the lambda solving
+ * (dR/dT)^T lambda = -dE/dT, the A->B element excluded).  The lambda
+ * equations are iterated like the amplitudes (Jacobi with the configured
+ * denominators, DIIS, tol_residual, max_iter), starting from lambda_dev if not
+ * NULL (which then receives the solution) or from zero.  Bbar_dev [naux][n][n]
+ * and Fbar_dev [n][n] receive the gradient with respect to symmetric B[P] and F:
+ * (G_pq + G_qp)/2, where moving both mirrored entries by h/2 changes E by
+ * h (G_pq + G_qp)/2.  *out (may be NULL) reports the lambda iterations.
+ * Returns DCSD_ERR_NOCONV (gradient from the last lambda) or
+ * DCSD_ERR_NONFINITE like dcsd_solve.  FP64 in every precision setting;
+ * allocates like dcsd_residual_vjp. */
+dcsd_status dcsd_backward(dcsd_ctx* ctx, const double* T_dev, double ebar_S, double ebar_T, double* Bbar_dev,
+                          double* Fbar_dev, double* lambda_dev, dcsd_report* out);
+
 /* Changes the solver settings of an existing context (max_iter,
  * tol_residual, level_shift, diis_start, term_mask, precond).  Sizes, method,
  * precision, diis_dim and ladder_block must equal those given to dcsd_init;

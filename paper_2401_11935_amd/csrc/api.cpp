@@ -27,7 +27,7 @@ dcsd_status guarded(dcsd_ctx* h, Fn&& fn) {
     h->c.sticky = true;
     return DCSD_ERR_HIP;
   } catch (const std::bad_alloc&) {
-    h->c.err = "host allocation failed";
+    h->c.err = "allocation failed";
     return DCSD_ERR_OOM;
   } catch (const std::exception& e) {
     h->c.err = e.what();
@@ -122,6 +122,51 @@ dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_it
     const int rc = ctx->c.solve(T_inout, out, cb, user);
     if (rc == DCSD_ERR_NOCONV) ctx->c.err = "not converged within max_iter";
     if (rc == DCSD_ERR_NONFINITE) ctx->c.err = "non-finite residual";
+    return (dcsd_status)rc;
+  });
+}
+
+dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* Rbar_dev, double Wbar, double EAbar,
+                              double* Tbar_dev, double* Bbar_dev, double* Fbar_dev) {
+  return guarded(ctx, [&] {
+    if (!T_dev || !Rbar_dev) throw dcsd::ArgError("T and Rbar are required");
+    dcsd::Ctx& c = ctx->c;
+    c.record(T_dev);
+    c.sweep(Rbar_dev, Wbar, EAbar, Bbar_dev || Fbar_dev);
+    if (Tbar_dev) DCSD_HIP(hipMemcpyAsync(Tbar_dev, c.bar(c.Tin), c.total * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    if (Bbar_dev)
+      DCSD_HIP(hipMemcpyAsync(Bbar_dev, c.bar(c.B), (size_t)c.naux * c.n2 * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    if (Fbar_dev) DCSD_HIP(hipMemcpyAsync(Fbar_dev, c.bar(c.F), c.n2 * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    DCSD_HIP(hipStreamSynchronize(c.s));
+    return DCSD_OK;
+  });
+}
+
+dcsd_status dcsd_backward(dcsd_ctx* ctx, const double* T_dev, double ebar_S, double ebar_T, double* Bbar_dev,
+                          double* Fbar_dev, double* lambda_dev, dcsd_report* out) {
+  return guarded(ctx, [&] {
+    if (!T_dev || !Bbar_dev || !Fbar_dev) throw dcsd::ArgError("T, Bbar and Fbar are required");
+    dcsd::Ctx& c = ctx->c;
+    c.record(T_dev);
+    if (lambda_dev)
+      DCSD_HIP(hipMemcpyAsync(c.lam, lambda_dev, c.total * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    else
+      dcsd::fill(c.lam, 0.0, c.total, c.s);
+    const double a = ebar_S + ebar_T, b = ebar_S - ebar_T;
+    dcsd_report rep{};
+    const int rc = c.lambda_solve(a, b, c.lam, &rep);
+    if (out) *out = rep;
+    if (rc == DCSD_ERR_NONFINITE) {
+      c.err = "non-finite lambda residual";
+      return (dcsd_status)rc;
+    }
+    c.sweep(c.lam, b, a, true);
+    dcsd::symmetrize(Bbar_dev, c.bar(c.B), c.naux, c.n, c.s);
+    dcsd::symmetrize(Fbar_dev, c.bar(c.F), 1, c.n, c.s);
+    if (lambda_dev)
+      DCSD_HIP(hipMemcpyAsync(lambda_dev, c.lam, c.total * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+    DCSD_HIP(hipStreamSynchronize(c.s));
+    if (rc == DCSD_ERR_NOCONV) c.err = "lambda equations not converged within max_iter";
     return (dcsd_status)rc;
   });
 }

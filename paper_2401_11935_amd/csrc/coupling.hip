@@ -424,6 +424,102 @@ void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vecto
   term_blob.assign((const char*)all.data(), (const char*)(all.data() + all.size()));
 }
 
+// Adjoint of one pattern: with rb the cotangent of -K_x W gathered over the
+// element's (antisymmetric) copies, Tbar[f] += -W rb dK_x/dT_f (atomic: one
+// amplitude enters many elements) and Wbar += -sum_x K_x rb (atomic).
+__device__ inline int64_t factor_off(const Amp& A, const DFac& f, int i, int j, int a, int b, int& arr) {
+  if (f.type == 1) {
+    const int h = occ_pos(f.kind[0], slot_val(f.slot[0], i, j, a, b), A.nc);
+    const int p = vir_pos(f.kind[1], slot_val(f.slot[1], i, j, a, b));
+    arr = f.blk;
+    return (int64_t)h * A.v + p;
+  }
+  const int h1 = occ_pos(f.kind[0], slot_val(f.slot[0], i, j, a, b), A.nc);
+  const int h2 = occ_pos(f.kind[1], slot_val(f.slot[1], i, j, a, b), A.nc);
+  const int p1 = vir_pos(f.kind[2], slot_val(f.slot[2], i, j, a, b));
+  const int p2 = vir_pos(f.kind[3], slot_val(f.slot[3], i, j, a, b));
+  arr = 2 + f.blk;
+  return (((int64_t)h1 * A.o + h2) * A.v + p1) * A.v + p2;
+}
+__global__ void coupling_pattern_adj(const DTerm* __restrict__ terms, int nterms, PatternLaunch pl, Amp A,
+                                     double* Tbar, const double* __restrict__ Rbar, const double* __restrict__ Wp,
+                                     double* Wbar) {
+  const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (id < tot) {
+    int64_t r = id;
+    const int bb = (int)(r % pl.cnt[3]); r /= pl.cnt[3];
+    const int aa = (int)(r % pl.cnt[2]); r /= pl.cnt[2];
+    const int jj = (int)(r % pl.cnt[1]);
+    const int ii = (int)(r / pl.cnt[1]);
+    const bool same = pl.block == 2 || pl.block == 3;
+    const bool skip = (same && pl.kind[0] == CORE && pl.kind[1] == CORE && ii >= jj) ||
+                      (same && pl.kind[2] == VIRT && pl.kind[3] == VIRT && aa >= bb);
+    if (!skip) {
+      const int nc = A.nc, o = A.o, v = A.v;
+      const int64_t ov = (int64_t)o * v, s2 = ov * ov;
+      const int i = occ_pos(pl.kind[0], ii, nc), a = vir_pos(pl.kind[2], aa);
+      double rb;
+      if (pl.block < 2) {
+        rb = Rbar[pl.block * ov + (int64_t)i * v + a];
+      } else {
+        const int j = occ_pos(pl.kind[1], jj, nc), b = vir_pos(pl.kind[3], bb);
+        const double* Rb = Rbar + 2 * ov + (int64_t)(pl.block - 2) * s2;
+        auto at = [&](int p, int q, int c, int d) { return Rb[(((int64_t)p * o + q) * v + c) * v + d]; };
+        rb = at(i, j, a, b);
+        if (same) rb += -at(j, i, a, b) - at(i, j, b, a) + at(j, i, b, a);
+      }
+      const double W = *Wp;
+      const double g = -W * rb;
+      double K = 0.0;
+      double* bars[5] = {Tbar, Tbar + ov, Tbar + 2 * ov, Tbar + 2 * ov + s2, Tbar + 2 * ov + 2 * s2};
+      for (int t = 0; t < nterms; ++t) {
+        const DTerm& T = terms[t];
+        double fv[MAXF];
+        for (int q = 0; q < T.nf; ++q) fv[q] = factor(A, T.f[q], ii, jj, aa, bb);
+        double prod = T.coef;
+        for (int q = 0; q < T.nf; ++q) prod *= fv[q];
+        K += prod;
+        if (g != 0.0) {
+          for (int q = 0; q < T.nf; ++q) {
+            double part = T.coef;
+            for (int q2 = 0; q2 < T.nf; ++q2)
+              if (q2 != q) part *= fv[q2];
+            int arr;
+            const int64_t off = factor_off(A, T.f[q], ii, jj, aa, bb, arr);
+            atomicAdd(bars[arr] + off, g * part);
+          }
+        }
+      }
+      if (K != 0.0 && rb != 0.0) atomicAdd(Wbar, -K * rb);
+    }
+  }
+}
+
+void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* Tbar,
+                        const double* Rbar, const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s) {
+  Amp A;
+  const int o = nc + 1, v = nv + 1;
+  const int64_t ov = (int64_t)o * v, s2 = ov * ov;
+  A.nc = nc; A.o = o; A.v = v;
+  A.t1[0] = T;
+  A.t1[1] = T + ov;
+  A.t2[0] = T + 2 * ov;
+  A.t2[1] = T + 2 * ov + s2;
+  A.t2[2] = T + 2 * ov + 2 * s2;
+  const PatternLaunch* pls = (const PatternLaunch*)launch_blob.data();
+  const size_t np = launch_blob.size() / sizeof(PatternLaunch);
+  const DTerm* terms = (const DTerm*)d_terms;
+  for (size_t k = 0; k < np; ++k) {
+    const PatternLaunch& pl = pls[k];
+    const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
+    if (tot == 0 || pl.nterms == 0) continue;
+    hipLaunchKernelGGL(coupling_pattern_adj, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                       terms + pl.term_off, pl.nterms, pl, A, Tbar, Rbar, W_dev, Wbar);
+    DCSD_CHECK_LAUNCH();
+  }
+}
+
 void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* R,
                     const double* W_dev, int nc, int nv, hipStream_t s) {
   Amp A;
@@ -447,9 +543,6 @@ void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, c
                        terms + pl.term_off, pl.nterms, pl, A, R, W_dev);
     DCSD_CHECK_LAUNCH();
   }
-  // the Phi_A -> Phi_B double: its residual is W itself and is not solved for
-  const int64_t ab = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  fill(R + ab, 0.0, 1, s);
 }
 
 size_t coupling_term_size() { return sizeof(DTerm); }

@@ -6,6 +6,7 @@
 
 #include "../../include/libdcsd.h"
 #include "kernels.h"
+#include "tape.h"
 
 namespace dcsd {
 
@@ -114,6 +115,37 @@ struct Ctx {
   std::vector<void*> allocs;
   size_t bytes = 0;
 
+  // Registry of the FP64 device arrays (context buffers and the borrowed B, F)
+  // for the adjoint: tape bookkeeping (constant flag, write version) and the
+  // shadow array holding each one's cotangent.
+  struct Buf {
+    double* p;
+    int64_t n;
+    bool constant = false;
+    int version = 0;
+    bool used = false;
+    double* bar = nullptr;
+  };
+  std::vector<Buf> bufs;
+  void reg(double* p, int64_t n, bool owned);
+  int find_buf(const void* p) const;
+  double* bar(const void* p);             // shadow address of p
+  bool wants(const void* p, bool params);  // cotangent needed in this sweep?
+
+  // adjoint state (allocated by the first dcsd_backward / dcsd_residual_vjp)
+  Tape tape_init, tape_res;
+  double *Tin = nullptr, *Rt = nullptr, *temp = nullptr, *lam = nullptr;
+  int64_t temp_cap = 0;
+  std::vector<double*> adj_allocs;
+  void adj_setup();
+  void record(const double* T);
+  void sweep(const double* Rbar, double Wbar, double Ebar, bool params);
+  void adjoint_op(const TapeOp& op, bool params);
+  void gemm_adjoint(const TapeOp& op, bool params);
+  void ladder_adjoint(const TapeOp& op, bool params);
+  int lambda_solve(double a, double b, double* lam_io, dcsd_report* rep);
+  void build_constants(bool full);
+
   double* alloc(int64_t count);
   int* alloc_int(int64_t count);
   void release();
@@ -124,6 +156,8 @@ struct Ctx {
   void residual(const double* T, double* R, double* W_host, int prec = -1, int mode = PLAIN);
   double energy_A(const double* T);
   int solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user);
+  void jacobi_diis(int it, double* X, const double* R, std::vector<double>& gram, std::vector<int>& order,
+                   int& count);
 };
 
 }  // namespace dcsd

@@ -25,12 +25,39 @@ void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, cons
                        const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
                        int64_t npair, int n, int nc, int o, int v, hipStream_t s);
 
-// Coupling between the two determinants: R -= K(T) * W, R at the A->B double set to 0.
+// Coupling between the two determinants: R -= K(T) * W (the caller sets R at the A->B double to 0).
 // coupling_prepare expands the per-pattern term tables on the host (once);
 // the term blob is copied to device memory and passed to coupling_apply.
 void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vector<char>& term_blob);
 void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* R,
                     const double* W_dev, int nc, int nv, hipStream_t s);
+
+// ---- adjoints (accumulate into the cotangents of the inputs) -------------------------
+void swap_tu_adj(double* src_bar, const double* dst_bar, int64_t batch, int n, int nc, hipStream_t s);
+void jvector_adj(double* Ba_bar, double* Bb_bar, const double* J_bar, int64_t naux, int n, int o, hipStream_t s);
+void batch_reduce_adj(double* src_bar, const double* dst_bar, int64_t nb, int64_t bstride, int rows, int cols,
+                      int64_t ld, int64_t ldd, bool transpose, double alpha, hipStream_t s);
+void ladder_stack_adj(double* t2aa_bar, double* t2bb_bar, double* t2ab_bar, const double* Sbar, int o, int v, int vu,
+                      int npair, hipStream_t s);
+void ladder_scatter_adj(double* Rb_bar, const double* Rp_bar, int64_t rows_used, int64_t nrow_main,
+                        int64_t nsame_begin, int n, int p0, int np, int q0, int nq, bool diag, hipStream_t s);
+void ladder_mt1(double* S, const double* Rp, const double* t1a, const double* t1b, int64_t rows, int64_t o2,
+                int64_t npair, int n, int nc, int o, int v, hipStream_t s);
+// t1bar may be NULL (amplitude cotangent of the T1 factors not wanted); VB, S,
+// Sbar: work arrays of rows*v*v, rows*n*v, rows*n*v doubles.
+void ladder_mtransform_adj(double* Rpbar, double* t1bar, const double* R2aa_bar, const double* R2bb_bar,
+                           const double* R2ab_bar, const double* Rp, const double* t1a, const double* t1b,
+                           const int* pair_i, const int* pair_j, int64_t rows, int64_t o2, int64_t npair, int n,
+                           int nc, int o, int v, double* VB, double* S, double* Sbar, hipStream_t s);
+void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* Tbar,
+                        const double* Rbar, const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s);
+// dst = src with the equal-spin doubles blocks antisymmetrised (dst != src)
+void antisym_copy(double* dst, const double* src, int o, int v, hipStream_t s);
+// out[P][p][q] = (in[P][p][q] + in[P][q][p]) / 2 for batch n x n matrices (out != in)
+void symmetrize(double* out, const double* in, int64_t batch, int n, hipStream_t s);
+// Ibar, fabar, fbbar may be NULL (only the amplitude cotangent)
+void energy_adj(double* Tbar, double* Ibar, double* fabar, double* fbbar, const double* T, const double* Isc,
+                const double* fa, const double* fb, const double* Ebar, int o, int v, int n, hipStream_t s);
 
 // reductions (deterministic); `part` needs 1024 doubles
 void dot(const double* x, const double* y, int64_t n, double* out_dev, double* part, hipStream_t s);

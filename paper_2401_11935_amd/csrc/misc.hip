@@ -199,6 +199,12 @@ __global__ void ladder_mt2_kernel(double* R2aa, double* R2bb, double* R2ab, cons
     }
   }
 }
+void ladder_mt1(double* S, const double* Rp, const double* t1a, const double* t1b, int64_t rows, int64_t o2,
+                int64_t npair, int n, int nc, int o, int v, hipStream_t s) {
+  hipLaunchKernelGGL(ladder_mt1_kernel, dim3(nblocks(rows * n * v, 256)), dim3(256), 0, s, S, Rp, t1a, t1b, rows, o2,
+                     npair, n, nc, o, v);
+  DCSD_CHECK_LAUNCH();
+}
 void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, const double* Rp, const double* t1a,
                        const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
                        int64_t npair, int n, int nc, int o, int v, hipStream_t s) {

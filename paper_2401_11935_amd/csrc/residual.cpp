@@ -21,123 +21,141 @@
 #include <cstring>
 #include <initializer_list>
 
-#include "ctx.h"
+#include "ops.h"
 
 namespace dcsd {
 
-namespace {
-
-void copyN(double* dst, const double* src, std::initializer_list<int64_t> dims, std::initializer_list<int64_t> ds,
-           std::initializer_list<int64_t> ss, double alpha, double beta, hipStream_t s) {
-  Strided st;
-  st.nd = (int)dims.size();
-  int d = 0;
-  for (auto x : dims) st.dims[d++] = x;
-  d = 0;
-  for (auto x : ds) st.ds[d++] = x;
-  d = 0;
-  for (auto x : ss) st.ss[d++] = x;
-  strided_copy(dst, src, st, alpha, beta, s);
+// Ring GEMMs follow the precision and mode of the current evaluation
+// (site: index of the call site; a_var / b_var: whether the operand changes
+// with the amplitudes).  FP64: the MFMA GEMM; RECORD also stores the
+// changing operands and the product P = A B at the refresh point.  Low
+// precision: operands rounded into K-contiguous FP32/BF16 copies and
+// multiplied on the low-precision MFMA with FP32 accumulation; DELTA uses
+// A B = P_r + (A - A_r) B + A_r (B - B_r), rounding only the differences.
+// C must be a compact row-major M x N matrix.  Timed as class 3.
+void G::ring(Ctx& c, int site, bool a_var, bool b_var) {
+  hipEvent_t ev;
+  const int rec = c.tbegin(&ev);
+  if (a.ldc != a.N || !a.c_nc || a.batch != 1 || a.lda != (a.a_mc ? a.M : a.K) || a.ldb != (a.b_nc ? a.N : a.K))
+    throw ArgError("ring GEMM site with a non-compact layout");
+  Ctx::Site& st = c.site[site];
+  const int64_t MN = a.M * a.N;
+  if (c.prec_now == DCSD_PREC_FP64) {
+    if (c.mode == Ctx::RECORD && st.Pr) {
+      if (a_var) DCSD_HIP(hipMemcpyAsync(st.Ar, a.A, a.M * a.K * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+      if (b_var) DCSD_HIP(hipMemcpyAsync(st.Br, a.B, a.K * a.N * sizeof(double), hipMemcpyDeviceToDevice, c.s));
+      G p(a.M, a.N, a.K);
+      p.a = a;
+      p.a.C = st.Pr;
+      p.a.alpha = 1.0;
+      p.a.beta = 0.0;
+      p.run(c);
+      axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
+      st.valid = true;
+    } else {
+      run(c);
+    }
+  } else if (c.mode == Ctx::DELTA && st.valid) {
+    axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
+    if (a_var) lp_product(c, a.A, st.Ar, a.B, nullptr);
+    if (b_var) lp_product(c, a_var ? st.Ar : a.A, nullptr, a.B, st.Br);
+  } else {
+    lp_product(c, a.A, nullptr, a.B, nullptr, a.beta);
+  }
+  if (rec) c.tend(ev, 2.0 * (double)a.M * (double)a.N * (double)a.K, 3);
+}
+// C = alpha * lp(A - Asub) lp(B - Bsub) + beta * C (subtrahends may be NULL).
+void G::lp_product(Ctx& c, const double* A, const double* Asub, const double* B, const double* Bsub, double beta) {
+  const int pr = c.prec_now;
+  const int64_t ld = lp_ld(a.K);
+  if (a.M * ld > c.lp_cap || a.N * ld > c.lp_cap) throw ArgError("ring operand exceeds the low-precision buffer");
+  // lpA[m][k] = A(m,k), lpB[n][k] = B(k,n)
+  lp_convert(pr, c.lpA, ld, A, Asub, a.M, a.K, a.a_mc ? 1 : a.lda, a.a_mc ? a.lda : 1, c.s);
+  lp_convert(pr, c.lpB, ld, B, Bsub, a.N, a.K, a.b_nc ? 1 : a.ldb, a.b_nc ? a.ldb : 1, c.s);
+  LpGemm q;
+  q.precision = pr;
+  q.M = a.M; q.N = a.N; q.K = a.K;
+  q.A = c.lpA; q.lda = ld; q.B = c.lpB; q.ldb = ld;
+  q.C = a.C; q.ldc = a.ldc; q.c_nc = a.c_nc;
+  q.alpha = a.alpha; q.beta = beta;
+  const int64_t tiles = ((a.M + 127) / 128) * ((a.N + 127) / 128);
+  int64_t ks = 1;
+  if (tiles < 256 && a.K >= 2048) {
+    ks = std::min<int64_t>(32, std::max<int64_t>(1, 1024 / tiles));
+    while (ks > 1 && ks * a.M * a.N > c.lwork_cap) ks /= 2;
+  }
+  q.ks = (int)ks;
+  q.work = c.lwork;
+  lp_gemm(q, c.s);
 }
 
-struct G {
-  GemmArgs a;
-  G(int64_t M, int64_t N, int64_t K) {
-    a.M = M;
-    a.N = N;
-    a.K = K;
+namespace {
+
+// Device operations of the residual and of the constants, recorded while a
+// tape is active (the operation itself always runs).
+void rfill(double* p, double v, int64_t n, hipStream_t s) {
+  if (t_tape) tape_simple(OP_FILL, p, nullptr, n, v, 0.0);
+  fill(p, v, n, s);
+}
+void raxpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s) {
+  if (t_tape) tape_simple(OP_AXPBY, y, x, n, a, b);
+  axpby(y, x, a, b, n, s);
+}
+void rcopy(double* dst, const double* src, int64_t n, hipStream_t s) {
+  if (t_tape) tape_simple(OP_MEMCPY, dst, src, n, 0.0, 0.0);
+  DCSD_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+void rupload(double* dst, const double* host, int64_t n, hipStream_t s) {
+  if (t_tape) tape_simple(OP_UPLOAD, dst, nullptr, n, 0.0, 0.0);
+  DCSD_HIP(hipMemcpyAsync(dst, host, n * sizeof(double), hipMemcpyHostToDevice, s));
+  DCSD_HIP(hipStreamSynchronize(s));  // the host source goes out of scope
+}
+void rswap(double* dst, const double* src, int64_t batch, int n, int nc, hipStream_t s) {
+  if (t_tape) {
+    TapeOp op;
+    op.kind = OP_SWAPTU;
+    op.dst = dst;
+    op.src = src;
+    op.n = batch;
+    op.ints[0] = n;
+    op.ints[1] = nc;
+    tape_op(op);
   }
-  G& A(const double* p, int64_t ld, bool mc) { a.A = p; a.lda = ld; a.a_mc = mc; return *this; }
-  G& B(const double* p, int64_t ld, bool nc) { a.B = p; a.ldb = ld; a.b_nc = nc; return *this; }
-  G& C(double* p, int64_t ld, bool nc = true) { a.C = p; a.ldc = ld; a.c_nc = nc; return *this; }
-  G& ab(double al, double be) { a.alpha = al; a.beta = be; return *this; }
-  G& batch(int64_t b, int64_t sA, int64_t sB, int64_t sC) { a.batch = b; a.sA = sA; a.sB = sB; a.sC = sC; return *this; }
-  G& split(int k, double* w) { a.ksplit = k; a.work = w; return *this; }
-  // Few output tiles and a long K: split K across workgroups into the context's
-  // workspace (fixed-order reduction, deterministic).
-  void run(Ctx& c) {
-    const double* g_ws = c.gws;
-    const int64_t g_ws_cap = c.gws_cap;
-    if (a.ksplit == 1 && g_ws && a.K >= 2048) {
-      const int64_t tiles = ((a.M + 63) / 64) * ((a.N + 63) / 64) * a.batch;
-      if (tiles < 256) {
-        int64_t ks = std::min<int64_t>(256, std::max<int64_t>(1, 1024 / tiles));
-        ks = std::min<int64_t>(ks, a.K / 512);
-        const int64_t span = (a.batch - 1) * a.sC + (a.c_nc ? (a.M - 1) * a.ldc + a.N : (a.N - 1) * a.ldc + a.M);
-        while (ks > 1 && ks * span > g_ws_cap) ks /= 2;
-        if (ks > 1) {
-          a.ksplit = (int)ks;
-          a.work = c.gws;
-        }
-      }
-    }
-    gemm_f64(a, c.s);
+  swap_tu(dst, src, batch, n, nc, s);
+}
+void rjvec(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s) {
+  if (t_tape) {
+    TapeOp op;
+    op.kind = OP_JVEC;
+    op.dst = J;
+    op.src = Ba;
+    op.src2 = Bb;
+    op.n = naux;
+    op.ints[0] = n;
+    op.ints[1] = o;
+    tape_op(op);
   }
-  // Ring GEMMs follow the precision and mode of the current evaluation
-  // (site: index of the call site; a_var / b_var: whether the operand changes
-  // with the amplitudes).  FP64: the MFMA GEMM; RECORD also stores the
-  // changing operands and the product P = A B at the refresh point.  Low
-  // precision: operands rounded into K-contiguous FP32/BF16 copies and
-  // multiplied on the low-precision MFMA with FP32 accumulation; DELTA uses
-  // A B = P_r + (A - A_r) B + A_r (B - B_r), rounding only the differences.
-  // C must be a compact row-major M x N matrix.  Timed as class 3.
-  void ring(Ctx& c, int site, bool a_var, bool b_var) {
-    hipEvent_t ev;
-    const int rec = c.tbegin(&ev);
-    if (a.ldc != a.N || !a.c_nc || a.batch != 1 || a.lda != (a.a_mc ? a.M : a.K) || a.ldb != (a.b_nc ? a.N : a.K))
-      throw ArgError("ring GEMM site with a non-compact layout");
-    Ctx::Site& st = c.site[site];
-    const int64_t MN = a.M * a.N;
-    if (c.prec_now == DCSD_PREC_FP64) {
-      if (c.mode == Ctx::RECORD && st.Pr) {
-        if (a_var) DCSD_HIP(hipMemcpyAsync(st.Ar, a.A, a.M * a.K * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-        if (b_var) DCSD_HIP(hipMemcpyAsync(st.Br, a.B, a.K * a.N * sizeof(double), hipMemcpyDeviceToDevice, c.s));
-        G p(a.M, a.N, a.K);
-        p.a = a;
-        p.a.C = st.Pr;
-        p.a.alpha = 1.0;
-        p.a.beta = 0.0;
-        p.run(c);
-        axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
-        st.valid = true;
-      } else {
-        run(c);
-      }
-    } else if (c.mode == Ctx::DELTA && st.valid) {
-      axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
-      if (a_var) lp_product(c, a.A, st.Ar, a.B, nullptr);
-      if (b_var) lp_product(c, a_var ? st.Ar : a.A, nullptr, a.B, st.Br);
-    } else {
-      lp_product(c, a.A, nullptr, a.B, nullptr, a.beta);
-    }
-    if (rec) c.tend(ev, 2.0 * (double)a.M * (double)a.N * (double)a.K, 3);
+  jvector(J, Ba, Bb, naux, n, o, s);
+}
+void rbreduce(double* dst, const double* src, int64_t nbat, int64_t bstride, int rows, int cols, int64_t ld,
+              int64_t ldd, bool transpose, double alpha, hipStream_t s) {
+  if (t_tape) {
+    TapeOp op;
+    op.kind = OP_BREDUCE;
+    op.dst = dst;
+    op.src = src;
+    op.n = nbat;
+    op.i64[0] = bstride;
+    op.i64[1] = ld;
+    op.i64[2] = ldd;
+    op.ints[0] = rows;
+    op.ints[1] = cols;
+    op.ints[2] = transpose ? 1 : 0;
+    op.alpha = alpha;
+    tape_op(op);
   }
-  // C = alpha * lp(A - Asub) lp(B - Bsub) + beta * C (subtrahends may be NULL).
-  void lp_product(Ctx& c, const double* A, const double* Asub, const double* B, const double* Bsub,
-                  double beta = 1.0) {
-    const int pr = c.prec_now;
-    const int64_t ld = lp_ld(a.K);
-    if (a.M * ld > c.lp_cap || a.N * ld > c.lp_cap) throw ArgError("ring operand exceeds the low-precision buffer");
-    // lpA[m][k] = A(m,k), lpB[n][k] = B(k,n)
-    lp_convert(pr, c.lpA, ld, A, Asub, a.M, a.K, a.a_mc ? 1 : a.lda, a.a_mc ? a.lda : 1, c.s);
-    lp_convert(pr, c.lpB, ld, B, Bsub, a.N, a.K, a.b_nc ? 1 : a.ldb, a.b_nc ? a.ldb : 1, c.s);
-    LpGemm q;
-    q.precision = pr;
-    q.M = a.M; q.N = a.N; q.K = a.K;
-    q.A = c.lpA; q.lda = ld; q.B = c.lpB; q.ldb = ld;
-    q.C = a.C; q.ldc = a.ldc; q.c_nc = a.c_nc;
-    q.alpha = a.alpha; q.beta = beta;
-    const int64_t tiles = ((a.M + 127) / 128) * ((a.N + 127) / 128);
-    int64_t ks = 1;
-    if (tiles < 256 && a.K >= 2048) {
-      ks = std::min<int64_t>(32, std::max<int64_t>(1, 1024 / tiles));
-      while (ks > 1 && ks * a.M * a.N > c.lwork_cap) ks /= 2;
-    }
-    q.ks = (int)ks;
-    q.work = c.lwork;
-    lp_gemm(q, c.s);
-  }
-};
+  batch_reduce(dst, src, nbat, bstride, rows, cols, ld, ldd, transpose, alpha, s);
+}
 
 }  // namespace
 
@@ -150,6 +168,7 @@ double* Ctx::alloc(int64_t count) {
   }
   allocs.push_back(p);
   bytes += b;
+  reg((double*)p, std::max<int64_t>(count, 1), true);
   return (double*)p;
 }
 
@@ -166,6 +185,8 @@ int* Ctx::alloc_int(int64_t count) {
 }
 
 void Ctx::release() {
+  tape_init.clear();
+  tape_res.clear();
   for (void* p : allocs) (void)hipFree(p);
   allocs.clear();
 }
@@ -177,7 +198,7 @@ void Ctx::release() {
 static void add_two_electron_fock(Ctx& c, double* const fout[2], double* const Bsrc[2]) {
   const int n = c.n, o = c.o;
   const int64_t naux = c.naux, n2 = c.n2;
-  jvector(c.Jv, Bsrc[0], Bsrc[1], naux, n, o, c.s);
+  rjvec(c.Jv, Bsrc[0], Bsrc[1], naux, n, o, c.s);
   for (int sp = 0; sp < 2; ++sp) {
     G(1, n2, naux).A(c.Jv, naux, false).B(Bsrc[sp], n2, true).C(fout[sp], n2).ab(1.0, 1.0).run(c);
     copyN(c.Xk, Bsrc[sp], {n, naux, o}, {naux * o, o, 1}, {n, n2, 1}, 1.0, 0.0, c.s);
@@ -359,8 +380,20 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
       DCSD_HIP(hipStreamSynchronize(s));
     }
   }
+  // external inputs take part in the adjoint's buffer registry (not owned)
+  reg(const_cast<double*>(B), NA * n2, false);
+  reg(const_cast<double*>(F), n2, false);
+  build_constants(true);
+}
+
+// Quantities of Phi_A built from (B, F) once per context; re-run under a tape
+// by the adjoint (full = false skips the preconditioner matrices, the
+// low-precision copy of the ladder factor and the reference energy, which
+// carry no derivative).
+void Ctx::build_constants(bool full) {
+  const int64_t NA = naux;
   // ---- beta-order factors: exchange t and u in both orbital indices ---------------
-  swap_tu(Bs[1], Bs[0], NA, n, nc, s);
+  rswap(Bs[1], Bs[0], NA, n, nc, s);
 
   // ---- one-electron Hamiltonian h = F - G_avg ---------------------------------------
   // G_avg = sum_core [2 J_k - K_k] + sum_{t,u} [J_x - K_x / 2]
@@ -370,21 +403,20 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     copyN(Xk, B, {NA, K2}, {K2, 1}, {n2, n + 1}, 1.0, 0.0, s);
     std::vector<double> w(K2, 1.0);
     for (int k = 0; k < nc; ++k) w[k] = 2.0;
-    DCSD_HIP(hipMemcpyAsync(fvec, w.data(), K2 * sizeof(double), hipMemcpyHostToDevice, s));
-    DCSD_HIP(hipStreamSynchronize(s));
+    rupload(fvec, w.data(), K2, s);
     G(NA, 1, K2).A(Xk, K2, false).B(fvec, 1, true).C(Jv, 1).run(*this);
-    DCSD_HIP(hipMemcpyAsync(h[0], F, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rcopy(h[0], F, n2, s);
     G(1, n2, NA).A(Jv, NA, false).B(B, n2, true).C(h[0], n2).ab(-1.0, 1.0).run(*this);
     // exchange: X[p][(P,k)] = c_k B[P,p,k] (c = 1 core, 1/2 open), Y[(P,k)][q] = B[P,k,q]
     copyN(Xk, B, {n, NA, K2}, {NA * K2, K2, 1}, {n, n2, 1}, 1.0, 0.0, s);
     copyN(Xk + nc, B + nc, {n, NA, 2}, {NA * K2, K2, 1}, {n, n2, 1}, 0.5, 0.0, s);
     copyN(Yk, B, {NA, K2, n}, {(int64_t)K2 * n, n, 1}, {n2, n, 1}, 1.0, 0.0, s);
     G(n, n, NA * K2).A(Xk, NA * K2, false).B(Yk, n, true).C(h[0], n).ab(1.0, 1.0).run(*this);
-    swap_tu(h[1], h[0], 1, n, nc, s);
+    rswap(h[1], h[0], 1, n, nc, s);
   }
   // ---- Fock matrices of Phi_A (undressed) ------------------------------------------
   for (int sp = 0; sp < 2; ++sp)
-    DCSD_HIP(hipMemcpyAsync(f[sp], h[sp], n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rcopy(f[sp], h[sp], n2, s);
   add_two_electron_fock(*this, f, Bs);
 
   // ---- (kc|ld) in the spin-conserving particle-hole layout --------------------------
@@ -413,7 +445,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   copyN(Ikl[2], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
   if (cfg.method == DCSD_METHOD_CCSD) {
     // <kl||cd> = (kc|ld) - (kd|lc): exchange part on the equal-spin blocks
-    DCSD_HIP(hipMemcpyAsync(Icc, Isc, tov * tov * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rcopy(Icc, Isc, tov * tov, s);
     for (int sp = 0; sp < 2; ++sp) {
       const int64_t base = sp * ov * (tov + 1);
       copyN(Icc + base, Isc + base, {o, v, o, v}, {vt, tov, v, 1}, {vt, 1, v, tov}, -1.0, 1.0, s);
@@ -422,12 +454,13 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     copyN(Isf1, Isc + ov * tov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
     copyN(Isf2, Isc + ov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
   }
+  // ---- ladder factor Bl[P][p][c] = B[P][p][nc + c], c over [t, u, virt] ------------
+  copyN(Bl, B + nc, {NA, n, vu}, {(int64_t)n * vu, vu, 1}, {n2, n, 1}, 1.0, 0.0, s);
+  if (!full) return;
   // ---- Coulomb/exchange matrices J_pq = (pp|qq), K_pq = (pq|qp) for the Epstein-Nesbet diagonal
   copyN(Xk, B, {NA, n}, {n, 1}, {n2, n + 1}, 1.0, 0.0, s);  // B[P][p][p]
   G(n, n, NA).A(Xk, n, true).B(Xk, n, true).C(Jpq, n).run(*this);
   sumsq_batch(Kpq, B, NA, n2, s);
-  // ---- ladder factor Bl[P][p][c] = B[P][p][nc + c], c over [t, u, virt] ------------
-  copyN(Bl, B + nc, {NA, n, vu}, {(int64_t)n * vu, vu, 1}, {n2, n, 1}, 1.0, 0.0, s);
   // low precision: BlT[(p,c)][P] = round(Bl[P][p][c])
   if (BlT) lp_convert(cfg.precision, BlT, ldk, Bl, nullptr, (int64_t)n * vu, NA, 1, (int64_t)n * vu, s);
 
@@ -465,9 +498,9 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   const int rec_res = tbegin(&ev_res);
 
   // amplitudes with the Phi_A -> Phi_B double forced to zero
-  DCSD_HIP(hipMemcpyAsync(Tw, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rcopy(Tw, T, total, s);
   const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  fill(Tw + ab_pos, 0.0, 1, s);
+  rfill(Tw + ab_pos, 0.0, 1, s);
   const double* t1[2] = {Tw, Tw + ov};
   const double* t2aa = Tw + 2 * ov;
   const double* t2bb = t2aa + s2;
@@ -476,13 +509,13 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   double* R1 = R;
   double* R2ss[2] = {R + 2 * ov, R + 2 * ov + s2};
   double* R2ab = R + 2 * ov + 2 * s2;
-  fill(R, 0.0, total, s);
+  rfill(R, 0.0, total, s);
 
   // ---- T1 dressing of the DF factors and of the Fock matrix ------------------------
   for (int sp = 0; sp < 2; ++sp) {
-    DCSD_HIP(hipMemcpyAsync(Bt[sp], Bs[sp], NA * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rcopy(Bt[sp], Bs[sp], NA * n2, s);
     dress(*this, Bt[sp], t1[sp], NA);
-    DCSD_HIP(hipMemcpyAsync(ft[sp], h[sp], n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+    rcopy(ft[sp], h[sp], n2, s);
     dress(*this, ft[sp], t1[sp], 1);
   }
   add_two_electron_fock(*this, ft, Bt);
@@ -518,10 +551,10 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
       // + sum_P sum_c B~[P][a][c] Z[P][i][c]
       G(v, o, v).A(Bt[sp] + (int64_t)o * n + o, n, false).B(Z + sp * ov, v, false).C(out1, o)
           .batch(NA, n2, tov, ov).run(*this);
-      batch_reduce(R1 + sp * ov, out1, NA, ov, v, o, o, v, true, 1.0, s);
+      rbreduce(R1 + sp * ov, out1, NA, ov, v, o, o, v, true, 1.0, s);
       // - sum_P sum_k B~[P][k][i] Z[P][k][a]
       G(o, v, o).A(Bt[sp], n, true).B(Z + sp * ov, v, true).C(out2, v).batch(NA, n2, tov, ov).run(*this);
-      batch_reduce(R1 + sp * ov, out2, NA, ov, o, v, v, v, false, -1.0, s);
+      rbreduce(R1 + sp * ov, out2, NA, ov, o, v, v, v, false, -1.0, s);
     }
   }
 
@@ -529,7 +562,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   // Dvo[(s,i,a),(s',j,b)] = (ai|bj)~
   if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING))
     G(tov, tov, NA).A(Bvo, tov, true).B(Bvo, tov, true).C(Dvo, tov).run(*this);
-  if (!(mask & DCSD_TERM_DRIVER)) fill(Dvo, 0.0, tov * tov, s);
+  if (!(mask & DCSD_TERM_DRIVER)) rfill(Dvo, 0.0, tov * tov, s);
   if (mask & (DCSD_TERM_RING | DCSD_TERM_HH)) {
     // OOOO[(s,k,i),(s',l,j)] = (ki|lj)~
     G(2 * o2, 2 * o2, NA).A(Boo, 2 * o2, true).B(Boo, 2 * o2, true).C(OOOO, 2 * o2).run(*this);
@@ -561,9 +594,9 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
     G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).ring(*this, 4, true, true);
     G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).ring(*this, 5, true, true);
   } else {
-    fill(Ring, 0.0, tov * tov, s);
-    fill(Rsf1, 0.0, s2, s);
-    fill(Rsf2, 0.0, s2, s);
+    rfill(Ring, 0.0, tov * tov, s);
+    rfill(Rsf1, 0.0, s2, s);
+    rfill(Rsf2, 0.0, s2, s);
   }
   if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING)) {
     // equal spins: R2 += P(ij)P(ab) [ 1/2 Dvo + Ring ]
@@ -610,9 +643,9 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
       }
       // F~vv = f~_vv + s X,  F~oo = f~_oo + s Y
       copyN(Fvv[sp], ft[sp] + (int64_t)o * n + o, {v, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);
-      axpby(Fvv[sp], Xv[sp], sdc, 1.0, vv, s);
+      raxpby(Fvv[sp], Xv[sp], sdc, 1.0, vv, s);
       copyN(Foo[sp], ft[sp], {o, o}, {o, 1}, {n, 1}, 1.0, 0.0, s);
-      axpby(Foo[sp], Yo[sp], sdc, 1.0, o2, s);
+      raxpby(Foo[sp], Yo[sp], sdc, 1.0, o2, s);
     }
     for (int sp = 0; sp < 2; ++sp) {
       // P(ab) sum_d t_ij^ad F_bd
@@ -653,6 +686,25 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
     const bool low = prec_now != DCSD_PREC_FP64;
     const bool delta = low && mode == DELTA && ladder_ref;  // contract lp(tau - tau_r), add L(tau_r)
     ladder_stack(Tstack, t2aa, t2bb, t2ab, pair_i, pair_j, o, v, vu, npair, rows_all, s);
+    // Under a tape the whole batch loop is one operation: its adjoint
+    // recomputes each integral batch instead of storing it.
+    Tape* const tape_here = t_tape;
+    if (tape_here) {
+      TapeOp op;
+      op.kind = OP_STACK;
+      op.dst = Tstack;
+      op.src = t2aa;
+      tape_op(op);
+      if (low) throw ArgError("the adjoint runs in FP64 only");
+      op = TapeOp();
+      op.kind = OP_LADDER;
+      op.dst = Rp;
+      op.src = Tstack;
+      op.src2 = Bl;
+      op.val[0] = tape_value(Tstack, rows_all * vu2);
+      tape_op(op);
+      t_tape = nullptr;
+    }
     if (low) lp_convert(prec_now, TstackL, kp, Tstack, delta ? TstackR : nullptr, rows_all, vu2, vu2, 1, s);
     for (int p0 = 0; p0 < n; p0 += lb) {
       const int np = std::min(lb, n - p0);
@@ -688,23 +740,44 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
       }
     }
     if (mode == RECORD) {
-      DCSD_HIP(hipMemcpyAsync(TstackR, Tstack, rows_all * vu2 * sizeof(double), hipMemcpyDeviceToDevice, s));
-      DCSD_HIP(hipMemcpyAsync(RpR, Rp, rows_main * n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+      rcopy(TstackR, Tstack, rows_all * vu2, s);
+      rcopy(RpR, Rp, rows_main * n2, s);
       ladder_ref = true;
     } else if (delta) {
-      axpby(Rp, RpR, 1.0, 1.0, rows_main * n2, s);
+      raxpby(Rp, RpR, 1.0, 1.0, rows_main * n2, s);
+    }
+    t_tape = tape_here;
+    if (t_tape) {
+      TapeOp op;
+      op.kind = OP_MTRANS;
+      op.dst = R;
+      op.src = Rp;
+      op.src2 = Tw;
+      op.val[0] = tape_value(Rp, rows_main * n2);
+      op.val[1] = tape_value(Tw, 2 * ov);
+      tape_op(op);
     }
     ladder_mtransform(R2ss[0], R2ss[1], R2ab, Smt, Rp, t1[0], t1[1], pair_i, pair_j, rows_main, o2, npair, n, nc, o,
                       v, s);
   }
 
   // ---- coupling of the two determinants ---------------------------------------------
-  DCSD_HIP(hipMemcpyAsync(scal, R + ab_pos, sizeof(double), hipMemcpyDeviceToDevice, s));  // W
+  rcopy(scal, R + ab_pos, 1, s);  // W
   if (mask & DCSD_TERM_COUPLING) {
+    if (t_tape) {
+      TapeOp op;
+      op.kind = OP_COUPLING;
+      op.dst = R;
+      op.src = Tw;
+      op.src2 = scal;
+      op.val[0] = tape_value(Tw, total);
+      op.val[1] = tape_value(scal, 1);
+      tape_op(op);
+    }
     coupling_apply(coup_launch, coup_terms, Tw, R, scal, nc, nv, s);
-  } else {
-    fill(R + ab_pos, 0.0, 1, s);
   }
+  // the Phi_A -> Phi_B double: its residual is W itself and is not solved for
+  rfill(R + ab_pos, 0.0, 1, s);
   if (rec_res) tend(ev_res, 0.0, 2);
   if (W_host) {
     DCSD_HIP(hipMemcpyAsync(W_host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -726,9 +799,9 @@ void Ctx::tend(hipEvent_t a, double flops, int cls) {
 }
 
 double Ctx::energy_A(const double* T) {
-  DCSD_HIP(hipMemcpyAsync(Tw, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  rcopy(Tw, T, total, s);
   const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  fill(Tw + ab_pos, 0.0, 1, s);
+  rfill(Tw + ab_pos, 0.0, 1, s);
   energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
   double e = 0.0;
   DCSD_HIP(hipMemcpyAsync(&e, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));

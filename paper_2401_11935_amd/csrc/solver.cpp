@@ -40,6 +40,59 @@ bool solve_dense(std::vector<double>& A, std::vector<double>& b, int n) {
 }
 }  // namespace
 
+// One Jacobi step from residual R at X (Tn = X + R/(D - s - shift)) followed by
+// the DIIS extrapolation over the stored (Tn, Tn - X) pairs; X receives the
+// new vector.
+void Ctx::jacobi_diis(int it, double* X, const double* R, std::vector<double>& gram, std::vector<int>& order,
+                      int& count) {
+  const int m = cfg.diis_dim;
+  const bool en = cfg.precond == DCSD_PRECOND_EN;
+  jacobi(Tn, Ev, X, R, f[0], f[1], en ? Jpq : nullptr, en ? Kpq : nullptr, nc, o, v, n, cfg.level_shift, total, s);
+  if (m > 0) {
+    const int slot = count % m;
+    ++count;
+    DCSD_HIP(hipMemcpyAsync(histT + (int64_t)slot * total, Tn, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+    DCSD_HIP(hipMemcpyAsync(histE + (int64_t)slot * total, Ev, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+    for (size_t k = 0; k < order.size(); ++k)
+      if (order[k] == slot) {
+        order.erase(order.begin() + k);
+        break;
+      }
+    order.push_back(slot);
+    const int nh = (int)order.size();
+    for (int j = 0; j < nh; ++j)
+      dot(histE + (int64_t)slot * total, histE + (int64_t)order[j] * total, total, scal + 4 + j, part, s);
+    std::vector<double> d(nh);
+    DCSD_HIP(hipMemcpyAsync(d.data(), scal + 4, nh * sizeof(double), hipMemcpyDeviceToHost, s));
+    DCSD_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < nh; ++j) {
+      gram[slot * m + order[j]] = d[j];
+      gram[order[j] * m + slot] = d[j];
+    }
+    if (it >= cfg.diis_start && nh >= 2) {
+      const int N = nh + 1;
+      std::vector<double> A((size_t)N * N, 0.0), b(N, 0.0);
+      for (int i = 0; i < nh; ++i)
+        for (int j = 0; j < nh; ++j) A[i * N + j] = gram[order[i] * m + order[j]];
+      for (int i = 0; i < nh; ++i) {
+        A[i * N + nh] = -1.0;
+        A[nh * N + i] = -1.0;
+      }
+      b[nh] = -1.0;
+      if (solve_dense(A, b, N)) {
+        // coefficients in slot order for the device combination
+        std::vector<double> c(m, 0.0);
+        for (int i = 0; i < nh; ++i) c[order[i]] = b[i];
+        DCSD_HIP(hipMemcpyAsync(coef, c.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+        DCSD_HIP(hipStreamSynchronize(s));
+        combine(X, histT, total, coef, std::min(count, m), total, s);
+        return;
+      }
+    }
+  }
+  DCSD_HIP(hipMemcpyAsync(X, Tn, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
 int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
   const int m = cfg.diis_dim;
   const bool low = cfg.precision != DCSD_PREC_FP64;
@@ -113,51 +166,7 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
       if (rep) *rep = r;
       return DCSD_OK;
     }
-    const bool en = cfg.precond == DCSD_PRECOND_EN;
-    jacobi(Tn, Ev, T, Rw, f[0], f[1], en ? Jpq : nullptr, en ? Kpq : nullptr, nc, o, v, n, cfg.level_shift, total, s);
-    if (m > 0) {
-      const int slot = count % m;
-      ++count;
-      DCSD_HIP(hipMemcpyAsync(histT + (int64_t)slot * total, Tn, total * sizeof(double), hipMemcpyDeviceToDevice, s));
-      DCSD_HIP(hipMemcpyAsync(histE + (int64_t)slot * total, Ev, total * sizeof(double), hipMemcpyDeviceToDevice, s));
-      for (size_t k = 0; k < order.size(); ++k)
-        if (order[k] == slot) {
-          order.erase(order.begin() + k);
-          break;
-        }
-      order.push_back(slot);
-      const int nh = (int)order.size();
-      for (int j = 0; j < nh; ++j)
-        dot(histE + (int64_t)slot * total, histE + (int64_t)order[j] * total, total, scal + 4 + j, part, s);
-      std::vector<double> d(nh);
-      DCSD_HIP(hipMemcpyAsync(d.data(), scal + 4, nh * sizeof(double), hipMemcpyDeviceToHost, s));
-      DCSD_HIP(hipStreamSynchronize(s));
-      for (int j = 0; j < nh; ++j) {
-        gram[slot * m + order[j]] = d[j];
-        gram[order[j] * m + slot] = d[j];
-      }
-      if (it >= cfg.diis_start && nh >= 2) {
-        const int N = nh + 1;
-        std::vector<double> A((size_t)N * N, 0.0), b(N, 0.0);
-        for (int i = 0; i < nh; ++i)
-          for (int j = 0; j < nh; ++j) A[i * N + j] = gram[order[i] * m + order[j]];
-        for (int i = 0; i < nh; ++i) {
-          A[i * N + nh] = -1.0;
-          A[nh * N + i] = -1.0;
-        }
-        b[nh] = -1.0;
-        if (solve_dense(A, b, N)) {
-          // coefficients in slot order for the device combination
-          std::vector<double> c(m, 0.0);
-          for (int i = 0; i < nh; ++i) c[order[i]] = b[i];
-          DCSD_HIP(hipMemcpyAsync(coef, c.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
-          DCSD_HIP(hipStreamSynchronize(s));
-          combine(T, histT, total, coef, std::min(count, m), total, s);
-          continue;
-        }
-      }
-    }
-    DCSD_HIP(hipMemcpyAsync(T, Tn, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+    jacobi_diis(it, T, Rw, gram, order, count);
   }
   if (rep) *rep = r;
   return DCSD_ERR_NOCONV;

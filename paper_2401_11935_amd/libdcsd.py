@@ -108,6 +108,10 @@ def load(path: str | None = None):
     lib.dcsd_timing_start.restype = ctypes.c_int
     lib.dcsd_timing_stop.argtypes = [vp, ctypes.POINTER(Timing)]
     lib.dcsd_timing_stop.restype = ctypes.c_int
+    lib.dcsd_residual_vjp.argtypes = [vp, dp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp]
+    lib.dcsd_residual_vjp.restype = ctypes.c_int
+    lib.dcsd_backward.argtypes = [vp, dp, ctypes.c_double, ctypes.c_double, dp, dp, dp, ctypes.POINTER(Report)]
+    lib.dcsd_backward.restype = ctypes.c_int
     lib.dcsd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, dp, dp,
                                        vp]
     lib.dcsd_selftest_gemm.restype = ctypes.c_int
@@ -186,6 +190,24 @@ class Context:
         out = rep.as_dict()
         out["status"] = STATUS_NAMES[st]
         out["records"] = records
+        if st not in (DCSD_OK, DCSD_ERR_NOCONV):
+            raise DcsdError(st, self.lib.dcsd_last_error(self.h).decode())
+        return out
+
+    def residual_vjp(self, T_ptr: int, Rbar_ptr: int, Wbar: float, EAbar: float, Tbar_ptr: int = 0,
+                     Bbar_ptr: int = 0, Fbar_ptr: int = 0):
+        """Cotangents of (T, B, F) for cotangents (Rbar, Wbar, EAbar) of (R, W, dE_A); 0 = not wanted."""
+        self._check(self.lib.dcsd_residual_vjp(self.h, T_ptr, Rbar_ptr, Wbar, EAbar, Tbar_ptr or None,
+                                               Bbar_ptr or None, Fbar_ptr or None))
+
+    def backward(self, T_ptr: int, ebar_S: float, ebar_T: float, Bbar_ptr: int, Fbar_ptr: int,
+                 lambda_ptr: int = 0) -> dict:
+        """dE/dB and dE/dF (symmetric) of E = ebar_S E_S + ebar_T E_T at converged amplitudes."""
+        rep = Report()
+        st = self.lib.dcsd_backward(self.h, T_ptr, ebar_S, ebar_T, Bbar_ptr, Fbar_ptr, lambda_ptr or None,
+                                    ctypes.byref(rep))
+        out = rep.as_dict()
+        out["status"] = STATUS_NAMES[st]
         if st not in (DCSD_OK, DCSD_ERR_NOCONV):
             raise DcsdError(st, self.lib.dcsd_last_error(self.h).decode())
         return out
