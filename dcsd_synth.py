@@ -83,9 +83,10 @@ def unpack(vec: np.ndarray, nc: int, nv: int) -> dict:
 
 
 def pack(blocks: dict, nc: int, nv: int) -> np.ndarray:
-    out = np.zeros(amplitude_count(nc, nv))
+    dt = np.result_type(np.float64, *[np.asarray(b) for b in blocks.values()])
+    out = np.zeros(amplitude_count(nc, nv), dt)
     for k, (off, shape) in block_offsets(nc, nv).items():
-        out[off:off + int(np.prod(shape))] = np.asarray(blocks[k], dtype=np.float64).ravel()
+        out[off:off + int(np.prod(shape))] = np.asarray(blocks[k], dtype=dt).ravel()
     return out
 
 

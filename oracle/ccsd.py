@@ -58,7 +58,7 @@ class SlabSource:
         """sum_ef tau_ij^ef <ab|ef>  ( = 1/2 sum_ef tau_ij^ef <ab||ef> )."""
         ham = self.ham
         no, nv = tau.shape[0], tau.shape[2]
-        out = np.zeros((no, no, nv, nv))
+        out = np.zeros((no, no, nv, nv), np.result_type(tau, ham.B))
         vs = ham.vir_spin
         spins = [np.where(vs == s)[0] for s in (0, 1)]
         for a_sp in np.unique(ham.vir_sp):
@@ -95,11 +95,12 @@ def ccsd_residual(ham: Hamiltonian, t1: np.ndarray, t2: np.ndarray, ints: dict |
     tau = t2 + t1t1 - t1t1.swapaxes(2, 3)
 
     # terms with one occupied and three virtual indices, one occupied slab at a time
-    Fae_3v = np.zeros((nv, nv))
-    Wmbej_3v = np.zeros((no, nv, nv, no))
-    R1_3v = np.zeros((no, nv))
-    X_3v = np.zeros((no, no, nv, nv))
-    Y_3v = np.zeros((no, no, nv, nv))
+    dt = np.result_type(t2, src.ham.B)
+    Fae_3v = np.zeros((nv, nv), dt)
+    Wmbej_3v = np.zeros((no, nv, nv, no), dt)
+    R1_3v = np.zeros((no, nv), dt)
+    X_3v = np.zeros((no, no, nv, nv), dt)
+    Y_3v = np.zeros((no, no, nv, nv), dt)
     for m in range(no):
         G = src.ovvv(m)                                   # <ma||ef>
         Fae_3v += es("f,afe->ae", t1[m], G)
@@ -136,5 +137,5 @@ def ccsd_residual(ham: Hamiltonian, t1: np.ndarray, t2: np.ndarray, ints: dict |
 def ccsd_energy(ints: dict, t1: np.ndarray, t2: np.ndarray) -> float:
     """Delta E_A = sum f_ia t_i^a + 1/4 sum <ij||ab> t_ij^ab + 1/2 sum <ij||ab> t_i^a t_j^b."""
     fov, oovv = ints["fov"], ints["oovv"]
-    return float(es("ia,ia->", fov, t1) + 0.25 * es("ijab,ijab->", oovv, t2)
-                 + 0.5 * es("ijab,ia,jb->", oovv, t1, t1))
+    return (es("ia,ia->", fov, t1) + 0.25 * es("ijab,ijab->", oovv, t2)
+            + 0.5 * es("ijab,ia,jb->", oovv, t1, t1))[()]

@@ -212,7 +212,7 @@ def local_coupling(holes, parts, amps: Amplitudes, grid_shape):
     vec = _exp_apply(vec, _excitation_terms(L, amps, "B"), 1.0)
     vec = _exp_apply(vec, _excitation_terms(L, amps, "A"), -1.0)
     val = vec.get(x[0], 0.0)
-    return np.broadcast_to(x[1] * np.asarray(val, dtype=np.float64), grid_shape).copy()
+    return np.broadcast_to(x[1] * np.asarray(val), grid_shape).copy()
 
 
 def coupling(blocks: dict, nc: int, nv: int) -> dict:
@@ -221,8 +221,9 @@ def coupling(blocks: dict, nc: int, nv: int) -> dict:
     The element of the Phi_A -> Phi_B double is set to zero (its residual is
     W itself, and that element is not solved for)."""
     o, v = nc + 1, nv + 1
-    K = {"t1a": np.zeros((o, v)), "t1b": np.zeros((o, v)),
-         "t2aa": np.zeros((o, o, v, v)), "t2bb": np.zeros((o, o, v, v)), "t2ab": np.zeros((o, o, v, v))}
+    dt = np.result_type(*blocks.values())
+    K = {"t1a": np.zeros((o, v), dt), "t1b": np.zeros((o, v), dt),
+         "t2aa": np.zeros((o, o, v, v), dt), "t2bb": np.zeros((o, o, v, v), dt), "t2ab": np.zeros((o, o, v, v), dt)}
 
     def occ_choices(spin, axis):
         act = T_A if spin == ALPHA else U_B

@@ -37,8 +37,9 @@ class Hamiltonian:
     """
 
     def __init__(self, B: np.ndarray, F: np.ndarray, nc: int):
-        self.B = np.asarray(B, dtype=np.float64)
-        self.F = np.asarray(F, dtype=np.float64)
+        # FP64 (complex FP64 only for complex-step derivatives in the tests)
+        self.B = np.asarray(B, dtype=np.result_type(B, np.float64))
+        self.F = np.asarray(F, dtype=np.result_type(F, np.float64))
         self.naux, self.n, _ = self.B.shape
         self.nc = nc
         self.nv = self.n - nc - 2
@@ -64,7 +65,7 @@ class Hamiltonian:
 
     def _g_avg(self) -> np.ndarray:
         B, nc, t, u = self.B, self.nc, self.t, self.u
-        G = np.zeros((self.n, self.n))
+        G = np.zeros((self.n, self.n), B.dtype)
         for k in range(nc):
             J = np.einsum("P,Ppq->pq", B[:, k, k], B)
             K = np.einsum("Ppk,Pkq->pq", B[:, :, k:k + 1], B[:, k:k + 1, :])
@@ -143,7 +144,7 @@ class Hamiltonian:
         oooo = self.asym(O, O, O, O)
         no = len(O[0])
         idx = np.arange(no)
-        return float(np.trace(hk) + 0.5 * oooo[idx[:, None], idx[None, :], idx[:, None], idx[None, :]].sum())
+        return (np.trace(hk) + 0.5 * oooo[idx[:, None], idx[None, :], idx[:, None], idx[None, :]].sum())[()]
 
     def spin_fock_closed_form(self):
         """f^alpha, f^beta = F -/+ 1/2 (K_t - K_u) (spatial, full n x n)."""
@@ -160,10 +161,11 @@ class Hamiltonian:
         t2aa = vec[off:off + s].reshape(o, o, v, v); off += s
         t2bb = vec[off:off + s].reshape(o, o, v, v); off += s
         t2ab = vec[off:off + s].reshape(o, o, v, v)
-        t1 = np.zeros((2 * o, 2 * v))
+        dt = np.result_type(vec, self.B)
+        t1 = np.zeros((2 * o, 2 * v), dt)
         t1[:o, :v] = t1a
         t1[o:, v:] = t1b
-        t2 = np.zeros((2 * o, 2 * o, 2 * v, 2 * v))
+        t2 = np.zeros((2 * o, 2 * o, 2 * v, 2 * v), dt)
         t2[:o, :o, :v, :v] = t2aa
         t2[o:, o:, v:, v:] = t2bb
         t2[:o, o:, :v, v:] = t2ab

@@ -23,10 +23,10 @@ import numpy as np
 
 def diis_coefficients(errors) -> np.ndarray:
     m = len(errors)
-    Bm = np.empty((m + 1, m + 1))
+    Bm = np.empty((m + 1, m + 1), np.result_type(*errors))
     for i in range(m):
         for j in range(i + 1):
-            Bm[i, j] = Bm[j, i] = float(np.dot(errors[i], errors[j]))
+            Bm[i, j] = Bm[j, i] = np.dot(errors[i], errors[j])  # no conjugation (complex-step safe)
     Bm[m, :m] = Bm[:m, m] = -1.0
     Bm[m, m] = 0.0
     rhs = np.zeros(m + 1)

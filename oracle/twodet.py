@@ -63,10 +63,10 @@ class TwoDet:
 
     def residual(self, vec: np.ndarray):
         """(R, W): the packed 2D residual and the effective coupling W."""
-        vec = np.array(vec, dtype=np.float64)
+        vec = np.array(vec, dtype=np.result_type(vec, np.float64))
         vec[self.ab] = 0.0
         Rc = self.connected(vec)
-        W = float(Rc[self.ab])
+        W = Rc[self.ab]
         R = Rc - self.coupling(vec) * W
         R[self.ab] = 0.0
         return R, W
