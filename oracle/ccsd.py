@@ -121,7 +121,7 @@ def ccsd_residual(ham: Hamiltonian, t1: np.ndarray, t2: np.ndarray, ints: dict |
     R1 = (fov + es("ie,ae->ia", t1, Fae) - es("ma,mi->ia", t1, Fmi) + es("imae,me->ia", t2, Fme)
           - es("nf,naif->ia", t1, I["ovov"]) - 0.5 * R1_3v - 0.5 * es("mnae,nmei->ia", t2, I["oovo"]))
 
-    R2 = I["oovv"].copy()
+    R2 = I["oovv"].astype(np.result_type(I["oovv"], t2))
     R2 += p_ab(es("ijae,be->ijab", t2, Fae - 0.5 * es("mb,me->be", t1, Fme)))
     R2 -= p_ij(es("imab,mj->ijab", t2, Fmi + 0.5 * es("je,me->mj", t1, Fme)))
     R2 += 0.5 * es("mnab,mnij->ijab", tau, Wmnij)
