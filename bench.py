@@ -93,6 +93,7 @@ def parse():
     ap.add_argument("--precisions", default="fp32,bf16",
                     help="low precisions compared with FP64 (residual evals at the same amplitudes; '' = skip)")
     ap.add_argument("--evals", type=int, default=3, help="timed residual evaluations per precision")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip timing the residual VJP")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -222,6 +223,37 @@ def precision_comparison(L, torch, args, Bd, Fd, stream, fm):
     return out
 
 
+def adjoint_timing(L, torch, args, Bd, Fd, stream):
+    """One residual VJP (dcsd_residual_vjp) at the first-order amplitudes: the
+    amplitude-only sweep that each lambda iteration runs, and the full sweep
+    through the constants to B and F; each call re-records the tape (one
+    forward residual plus the constants)."""
+    base = dict(nc=args.nc, nv=args.nv, naux=args.naux, method=args.method, ladder_block=args.ladder_block)
+    ctx = L.Context(L.default_config(max_iter=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
+    T = torch.zeros(ctx.size, dtype=torch.float64, device=Bd.device)
+    ctx.solve(T.data_ptr())
+    Rbar = torch.randn(ctx.size, dtype=torch.float64, device=Bd.device, generator=torch.Generator(Bd.device).manual_seed(7))
+    Tb, Bb, Fb = torch.empty_like(T), torch.empty_like(Bd), torch.empty_like(Fd)
+    R = torch.empty_like(T)
+    out = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.residual(T.data_ptr(), R.data_ptr())
+    out["forward_residual_ms"] = 1e3 * (time.perf_counter() - t0)
+    for name, full in (("vjp_amplitudes_ms", False), ("vjp_full_ms", True)):
+        for rep in range(2):  # the first call allocates the cotangent arrays
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.residual_vjp(T.data_ptr(), Rbar.data_ptr(), 0.5, 1.0, Tb.data_ptr(),
+                             Bb.data_ptr() if full else 0, Fb.data_ptr() if full else 0)
+            dt = 1e3 * (time.perf_counter() - t0)
+        out[name] = dt
+    out["note"] = ("record (forward residual + constants, operand snapshots) and one backward sweep, FP64; "
+                   "ladder integral batches recomputed in the sweep")
+    ctx.close()
+    return out
+
+
 def tiny_convergence(L, torch, stream):
     """Mixed-precision solves of the tiny configuration (nc=3, nv=16, naux=60)
     to max|R| <= 1e-10 beside the FP64 solve."""
@@ -337,6 +369,9 @@ def main():
     if args.precisions:
         out["precisions"] = precision_comparison(L, torch, args, Bd, Fd, stream, fm)
         out["mixed_convergence_tiny"] = tiny_convergence(L, torch, stream)
+    if not args.no_adjoint:
+        print("bench: residual VJP", file=sys.stderr, flush=True)
+        out["adjoint"] = adjoint_timing(L, torch, args, Bd, Fd, stream)
     if args.cpu_slabs > 0:
         print("bench: timing the oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(nc, nv, naux, args.seed, args.cpu_slabs)

@@ -426,7 +426,7 @@ void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vecto
 
 // Adjoint of one pattern: with rb the cotangent of -K_x W gathered over the
 // element's (antisymmetric) copies, Tbar[f] += -W rb dK_x/dT_f (atomic: one
-// amplitude enters many elements) and Wbar += -sum_x K_x rb (atomic).
+// amplitude enters many elements) and Wbar += -sum_x K_x rb.
 __device__ inline int64_t factor_off(const Amp& A, const DFac& f, int i, int j, int a, int b, int& arr) {
   if (f.type == 1) {
     const int h = occ_pos(f.kind[0], slot_val(f.slot[0], i, j, a, b), A.nc);
@@ -441,59 +441,74 @@ __device__ inline int64_t factor_off(const Amp& A, const DFac& f, int i, int j, 
   arr = 2 + f.blk;
   return (((int64_t)h1 * A.o + h2) * A.v + p1) * A.v + p2;
 }
+__device__ inline double wave_sum(double v) {
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+  return v;
+}
+// Every lane of a wave runs the same term loop (lanes past the end or outside
+// the i < j, a < b half contribute zero), so that factors whose cotangent
+// address is the same in all 64 lanes - every factor that does not depend on
+// the fastest grid index, e.g. amplitudes with only t/u indices, which all
+// elements of a pattern share - are summed in the wave first and added with
+// one atomic instead of 64.
 __global__ void coupling_pattern_adj(const DTerm* __restrict__ terms, int nterms, PatternLaunch pl, Amp A,
                                      double* Tbar, const double* __restrict__ Rbar, const double* __restrict__ Wp,
                                      double* Wbar) {
   const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id < tot) {
-    int64_t r = id;
-    const int bb = (int)(r % pl.cnt[3]); r /= pl.cnt[3];
-    const int aa = (int)(r % pl.cnt[2]); r /= pl.cnt[2];
-    const int jj = (int)(r % pl.cnt[1]);
-    const int ii = (int)(r / pl.cnt[1]);
-    const bool same = pl.block == 2 || pl.block == 3;
-    const bool skip = (same && pl.kind[0] == CORE && pl.kind[1] == CORE && ii >= jj) ||
-                      (same && pl.kind[2] == VIRT && pl.kind[3] == VIRT && aa >= bb);
-    if (!skip) {
-      const int nc = A.nc, o = A.o, v = A.v;
-      const int64_t ov = (int64_t)o * v, s2 = ov * ov;
-      const int i = occ_pos(pl.kind[0], ii, nc), a = vir_pos(pl.kind[2], aa);
-      double rb;
-      if (pl.block < 2) {
-        rb = Rbar[pl.block * ov + (int64_t)i * v + a];
-      } else {
-        const int j = occ_pos(pl.kind[1], jj, nc), b = vir_pos(pl.kind[3], bb);
-        const double* Rb = Rbar + 2 * ov + (int64_t)(pl.block - 2) * s2;
-        auto at = [&](int p, int q, int c, int d) { return Rb[(((int64_t)p * o + q) * v + c) * v + d]; };
-        rb = at(i, j, a, b);
-        if (same) rb += -at(j, i, a, b) - at(i, j, b, a) + at(j, i, b, a);
-      }
-      const double W = *Wp;
-      const double g = -W * rb;
-      double K = 0.0;
-      double* bars[5] = {Tbar, Tbar + ov, Tbar + 2 * ov, Tbar + 2 * ov + s2, Tbar + 2 * ov + 2 * s2};
-      for (int t = 0; t < nterms; ++t) {
-        const DTerm& T = terms[t];
-        double fv[MAXF];
-        for (int q = 0; q < T.nf; ++q) fv[q] = factor(A, T.f[q], ii, jj, aa, bb);
-        double prod = T.coef;
-        for (int q = 0; q < T.nf; ++q) prod *= fv[q];
-        K += prod;
-        if (g != 0.0) {
-          for (int q = 0; q < T.nf; ++q) {
-            double part = T.coef;
-            for (int q2 = 0; q2 < T.nf; ++q2)
-              if (q2 != q) part *= fv[q2];
-            int arr;
-            const int64_t off = factor_off(A, T.f[q], ii, jj, aa, bb, arr);
-            atomicAdd(bars[arr] + off, g * part);
-          }
-        }
-      }
-      if (K != 0.0 && rb != 0.0) atomicAdd(Wbar, -K * rb);
+  const int64_t id0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool inrange = id0 < tot;
+  int64_t r = inrange ? id0 : tot - 1;
+  const int bb = (int)(r % pl.cnt[3]); r /= pl.cnt[3];
+  const int aa = (int)(r % pl.cnt[2]); r /= pl.cnt[2];
+  const int jj = (int)(r % pl.cnt[1]);
+  const int ii = (int)(r / pl.cnt[1]);
+  const bool same = pl.block == 2 || pl.block == 3;
+  const bool skip = (same && pl.kind[0] == CORE && pl.kind[1] == CORE && ii >= jj) ||
+                    (same && pl.kind[2] == VIRT && pl.kind[3] == VIRT && aa >= bb);
+  const int nc = A.nc, o = A.o, v = A.v;
+  const int64_t ov = (int64_t)o * v, s2 = ov * ov;
+  double rb = 0.0;
+  if (inrange && !skip) {
+    const int i = occ_pos(pl.kind[0], ii, nc), a = vir_pos(pl.kind[2], aa);
+    if (pl.block < 2) {
+      rb = Rbar[pl.block * ov + (int64_t)i * v + a];
+    } else {
+      const int j = occ_pos(pl.kind[1], jj, nc), b = vir_pos(pl.kind[3], bb);
+      const double* Rb = Rbar + 2 * ov + (int64_t)(pl.block - 2) * s2;
+      auto at = [&](int p, int q, int c, int d) { return Rb[(((int64_t)p * o + q) * v + c) * v + d]; };
+      rb = at(i, j, a, b);
+      if (same) rb += -at(j, i, a, b) - at(i, j, b, a) + at(j, i, b, a);
     }
   }
+  const double g = -(*Wp) * rb;  // cotangent of K_x
+  double K = 0.0;
+  double* bars[5] = {Tbar, Tbar + ov, Tbar + 2 * ov, Tbar + 2 * ov + s2, Tbar + 2 * ov + 2 * s2};
+  for (int t = 0; t < nterms; ++t) {
+    const DTerm& T = terms[t];
+    double fv[MAXF];
+    for (int q = 0; q < T.nf; ++q) fv[q] = factor(A, T.f[q], ii, jj, aa, bb);
+    double prod = T.coef;
+    for (int q = 0; q < T.nf; ++q) prod *= fv[q];
+    K += prod;
+    for (int q = 0; q < T.nf; ++q) {
+      double part = T.coef;
+      for (int q2 = 0; q2 < T.nf; ++q2)
+        if (q2 != q) part *= fv[q2];
+      int arr;
+      const int64_t off = factor_off(A, T.f[q], ii, jj, aa, bb, arr);
+      const double val = g * part;
+      const long long key = ((long long)arr << 40) | (long long)off;
+      const long long k0 = __shfl(key, 0);
+      if (__all(key == k0)) {
+        const double sum = wave_sum(val);
+        if (__lane_id() == 0 && sum != 0.0) atomicAdd(bars[arr] + off, sum);
+      } else if (val != 0.0) {
+        atomicAdd(bars[arr] + off, val);
+      }
+    }
+  }
+  const double w = wave_sum(-K * rb);
+  if (__lane_id() == 0 && w != 0.0) atomicAdd(Wbar, w);
 }
 
 void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* Tbar,
