@@ -6,6 +6,7 @@
 // that the 16-lane groups of a 64-bit LDS read fall in disjoint bank halves.
 // Ragged M, N, K edges are zero-filled on load and masked on store.
 #include "kernels.h"
+#include "tiles.h"
 
 namespace dcsd {
 
@@ -55,9 +56,9 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t bid = blockIdx.x;
-  const int64_t m0 = (bid / g.tiles_n) * BM;
-  const int64_t n0 = (bid % g.tiles_n) * BN;
+  int64_t tm, tn;
+  tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t batch = blockIdx.y;
   const double* A = g.A + batch * g.sA;
   const double* B = g.B + batch * g.sB;
@@ -68,27 +69,29 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
     kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
   }
 
+  // Element e = tid + i*NT of a K step sits at a thread part (fixed over the K loop and
+  // kept as a 32-bit byte offset) plus a part that only depends on i: the load address
+  // is a uniform base plus the thread's offset, so no per-element 64-bit address lives
+  // in registers across the loop (the host bounds the offsets below 2^32 bytes).
+  const int ka0 = A_MC ? tid / BM : tid % BK, ma0 = A_MC ? tid % BM : tid / BK;
+  const int kb0 = B_NC ? tid / BN : tid % BK, nb0 = B_NC ? tid % BN : tid / BK;
+  constexpr int AK = A_MC ? NT / BM : 0, AM = A_MC ? 0 : NT / BK;  // per-i steps of (k, m)
+  constexpr int BKS = B_NC ? NT / BN : 0, BNS = B_NC ? 0 : NT / BK;
+  const uint32_t aoff = (uint32_t)(8 * (A_MC ? ma0 + ka0 * g.lda : ma0 * g.lda + ka0));
+  const uint32_t boff = (uint32_t)(8 * (B_NC ? nb0 + kb0 * g.ldb : nb0 * g.ldb + kb0));
   double ra[LA], rb[LB];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < LA; ++i) {
-      const int e = tid + i * NT;
-      int k, m;
-      if (A_MC) { k = e / BM; m = e % BM; } else { k = e % BK; m = e / BK; }
-      const int64_t gm = m0 + m, gk = k0 + k;
-      double v = 0.0;
-      if (gm < g.M && gk < kend) v = A_MC ? A[gm + gk * g.lda] : A[gm * g.lda + gk];
-      ra[i] = v;
+      const int64_t gm = m0 + ma0 + i * AM, gk = k0 + ka0 + i * AK;
+      const double* base = A + (A_MC ? (m0 + i * AM) + (k0 + i * AK) * g.lda : (m0 + i * AM) * g.lda + k0 + i * AK);
+      ra[i] = (gm < g.M && gk < kend) ? *(const double*)((const char*)base + aoff) : 0.0;
     }
 #pragma unroll
     for (int i = 0; i < LB; ++i) {
-      const int e = tid + i * NT;
-      int k, n;
-      if (B_NC) { k = e / BN; n = e % BN; } else { k = e % BK; n = e / BK; }
-      const int64_t gn = n0 + n, gk = k0 + k;
-      double v = 0.0;
-      if (gn < g.N && gk < kend) v = B_NC ? B[gn + gk * g.ldb] : B[gn * g.ldb + gk];
-      rb[i] = v;
+      const int64_t gn = n0 + nb0 + i * BNS, gk = k0 + kb0 + i * BKS;
+      const double* base = B + (B_NC ? (n0 + i * BNS) + (k0 + i * BKS) * g.ldb : (n0 + i * BNS) * g.ldb + k0 + i * BKS);
+      rb[i] = (gn < g.N && gk < kend) ? *(const double*)((const char*)base + boff) : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -152,31 +155,87 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
   // epilogue: for the FP64 16x16x4 MFMA, lane holds D[lane/16 + 4*r][lane%16] of each 16x16 tile
   double* C = g.C + batch * g.sC;
   if (SPLIT) C += (int64_t)blockIdx.z * g.split_stride;
+  const int64_t mb = m0 + wm * WM + lrow, nbase = n0 + wn * WN + lcol;
+  if constexpr (EPI == 1) {
+    // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]: the offset splits into a row part
+    // p*nq*vu^2 + c*vu and a column part q*vu^2 + d, both stepped without divisions
+    const int vu = (int)g.vu;
+    const int64_t vv = g.vu * g.vu;
+    int64_t coff[TN];
+    {
+      int q = (int)(nbase / vu), d = (int)(nbase % vu);
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < TN; ++j) {
+        coff[j] = (int64_t)q * vv + d;
+        d += 16;
+        while (d >= vu) {
+          d -= vu;
+          ++q;
+        }
+      }
+    }
+    int p = (int)(mb / vu), c = (int)(mb % vu);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (mb + i * 16 + 4 * r < g.M) {
+          const int64_t roff = (int64_t)p * g.nq * vv + (int64_t)c * vu;
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (nbase + j * 16 < g.N) C[roff + coff[j]] = acc[i][j][r];
+        }
+        c += 4;
+        while (c >= vu) {
+          c -= vu;
+          ++p;
+        }
+      }
+    }
+    return;
+  }
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = mb + i * 16 + 4 * r;
+          const int64_t gn = nbase + j * 16;
+          if (gm < g.M && gn < g.N) C[C_NC ? gm * g.ldc + gn : gm + gn * g.ldc] = acc[i][j][r];
+        }
+    return;
+  }
+  // alpha/beta epilogue staged through LDS, one 16-row block of the wave tile at a
+  // time: the accumulators go to LDS straight from the matrix-core registers (scaling
+  // them in place would copy all of them to VGPRs, inside the K loop as well), and the
+  // C reads and writes become contiguous along C's leading dimension
+  constexpr int SROW = WN + 1;
+  static_assert(4 * 16 * SROW <= 2 * SA, "epilogue staging does not fit");
+  double* stg = &sA[0][0] + wave * 16 * SROW;
+  const int64_t mw = m0 + wm * WM, nw = n0 + wn * WN;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 16 + lrow + 4 * r;
-        const int64_t gn = n0 + wn * WN + j * 16 + lcol;
-        if (gm < g.M && gn < g.N) {
-          if (EPI == 1) {
-            // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]
-            const int64_t p = gm / g.vu, c = gm % g.vu, q = gn / g.vu, d = gn % g.vu;
-            C[((p * g.nq + q) * g.vu + c) * g.vu + d] = acc[i][j][r];
-            continue;
-          }
-          const int64_t off = C_NC ? gm * g.ldc + gn : gm + gn * g.ldc;
-          if (SPLIT) {
-            C[off] = acc[i][j][r];
-          } else {
-            double v = g.alpha * acc[i][j][r];
-            if (g.beta != 0.0) v += g.beta * C[off];
-            C[off] = v;
-          }
-        }
+      for (int r = 0; r < 4; ++r) stg[(lrow + 4 * r) * SROW + j * 16 + lcol] = acc[i][j][r];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16 * WN / 64; ++t) {
+      const int e = lane + 64 * t;
+      const int rr = C_NC ? e / WN : e % 16, cc = C_NC ? e % WN : e / 16;
+      const int64_t gm = mw + i * 16 + rr, gn = nw + cc;
+      if (gm < g.M && gn < g.N) {
+        const int64_t off = C_NC ? gm * g.ldc + gn : gm + gn * g.ldc;
+        double v = g.alpha * stg[rr * SROW + cc];
+        if (g.beta != 0.0) v += g.beta * C[off];
+        C[off] = v;
       }
+    }
+    __syncthreads();
+  }
 }
 
 // C = alpha * sum_z W[z] + beta * C, W[z] laid out like C (same ldc/c_nc/batch strides).
@@ -230,6 +289,9 @@ void dispatch(const GemmArgs& g, KArgs& k, hipStream_t s) {
 void gemm_f64(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   if (g.batch > 65535 || g.ksplit > 65535 || g.ksplit < 1) throw ArgError("gemm_f64: grid too large");
+  // the kernels keep each thread's operand offset within a K step as 32-bit bytes
+  if (g.lda >= ((int64_t)1 << 25) || g.ldb >= ((int64_t)1 << 25))
+    throw ArgError("gemm_f64: leading dimension too large");
   KArgs k{};
   k.M = g.M; k.N = g.N; k.K = g.K;
   k.A = g.A; k.lda = g.lda; k.B = g.B; k.ldb = g.ldb;
@@ -268,6 +330,7 @@ void gemm_f64(const GemmArgs& g, hipStream_t s) {
 // with Bl laid out [P][row][c] (row stride vu, P stride ld).
 void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int64_t p0, int64_t np, int64_t q0,
                     int64_t nq, double* V2, hipStream_t s) {
+  if (ld >= ((int64_t)1 << 25)) throw ArgError("gemm_f64_pairs: leading dimension too large");
   KArgs k{};
   k.M = np * vu; k.N = nq * vu; k.K = naux;
   k.A = Bl + p0 * vu; k.lda = ld;

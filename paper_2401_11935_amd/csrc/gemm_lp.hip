@@ -15,6 +15,7 @@
 
 #include "../../include/libdcsd.h"
 #include "kernels.h"
+#include "tiles.h"
 
 namespace dcsd {
 
@@ -48,15 +49,11 @@ template <>
 struct Traits<float> {
   static constexpr int VL = 4;     // elements per 16-byte load
   static constexpr int KSTEP = 4;  // K per MFMA
-  static constexpr int BK = 16;
-  static constexpr int ROW = 20;   // LDS row stride (elements): 80 bytes
 };
 template <>
 struct Traits<__bf16> {
   static constexpr int VL = 8;
   static constexpr int KSTEP = 32;
-  static constexpr int BK = 64;
-  static constexpr int ROW = 72;   // 144 bytes
 };
 
 // Rounding of an FP32 value to the storage precision, nearest even, written
@@ -87,24 +84,35 @@ __device__ inline uint4 load_chunk(const T* p, int64_t kk, int64_t kend) {
   return x.u;
 }
 
-template <class T, int EPI, bool SPLIT>
+// K depth of one LDS stage: 16 FP32 / 64 BF16 elements with 128-row tiles,
+// 32 BF16 with 256-row tiles (keeps the staging registers at 32 next to the
+// 256 accumulators of a 128 x 128 wave tile).  Rows padded by 16 bytes.
+template <class T, int BT>
+struct Stage {
+  static constexpr int BK = sizeof(T) == 4 ? 16 : (BT == 256 ? 32 : 64);
+  static constexpr int ROW = BK + 16 / (int)sizeof(T);
+};
+
+// BT x BT tile per workgroup of four waves, each a (BT/2) x (BT/2) sub-tile.
+template <class T, int EPI, bool SPLIT, int BT = 128>
 __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
   constexpr int VL = Traits<T>::VL;
-  constexpr int BK = Traits<T>::BK;
+  constexpr int BK = Stage<T, BT>::BK;
   constexpr int KSTEP = Traits<T>::KSTEP;
-  constexpr int ROW = Traits<T>::ROW;
+  constexpr int ROW = Stage<T, BT>::ROW;
   constexpr int CPR = BK / VL;               // 16-byte chunks per row
-  constexpr int CH = TILE * CPR / NT;        // chunks per thread per operand
-  constexpr int WM = TILE / 2, WN = TILE / 2;
+  constexpr int CH = BT * CPR / NT;          // chunks per thread per operand
+  constexpr int WM = BT / 2, WN = BT / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  __shared__ __attribute__((aligned(16))) T sA[2][TILE * ROW];
-  __shared__ __attribute__((aligned(16))) T sB[2][TILE * ROW];
+  __shared__ __attribute__((aligned(16))) T sA[2][BT * ROW];
+  __shared__ __attribute__((aligned(16))) T sB[2][BT * ROW];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = ((int64_t)blockIdx.x / g.tiles_n) * TILE;
-  const int64_t n0 = ((int64_t)blockIdx.x % g.tiles_n) * TILE;
+  int64_t tm, tn;
+  tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
+  const int64_t m0 = tm * BT, n0 = tn * BT;
   int64_t kbeg = 0, kend = g.K;
   if (SPLIT) {
     kbeg = (int64_t)blockIdx.z * g.kchunk;
@@ -113,16 +121,24 @@ __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
   const T* A = (const T*)g.A;
   const T* B = (const T*)g.B;
 
+  // element offsets of this thread's 16-byte chunks, fixed over the K loop (-1: row
+  // outside; the host guarantees M*lda and N*ldb below 2^31)
+  int oa[CH], ob[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    const int e = tid + c * NT;
+    const int r = e / CPR, kc = (e % CPR) * VL;
+    oa[c] = m0 + r < g.M ? (int)((m0 + r) * g.lda) + kc : -1;
+    ob[c] = n0 + r < g.N ? (int)((n0 + r) * g.ldb) + kc : -1;
+  }
   uint4 ra[CH], rb[CH];
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int e = tid + c * NT;
-      const int r = e / CPR, kc = (e % CPR) * VL;
+      const int kc = ((tid + c * NT) % CPR) * VL;
       const int64_t kk = k0 + kc;
-      const int64_t gm = m0 + r, gn = n0 + r;
-      ra[c] = (gm < g.M && kk < kend) ? load_chunk<T>(A + gm * g.lda + kk, kk, kend) : uint4{0u, 0u, 0u, 0u};
-      rb[c] = (gn < g.N && kk < kend) ? load_chunk<T>(B + gn * g.ldb + kk, kk, kend) : uint4{0u, 0u, 0u, 0u};
+      ra[c] = (oa[c] >= 0 && kk < kend) ? load_chunk<T>(A + oa[c] + k0, kk, kend) : uint4{0u, 0u, 0u, 0u};
+      rb[c] = (ob[c] >= 0 && kk < kend) ? load_chunk<T>(B + ob[c] + k0, kk, kend) : uint4{0u, 0u, 0u, 0u};
     }
   };
   auto store = [&](int buf) {
@@ -188,21 +204,62 @@ __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
   }
 
   // FP32 16 x 16 accumulators: element r of a lane is D[4*(lane/16) + r][lane%16]
+  const int64_t mb = m0 + wm * WM + 4 * lrow, nbase = n0 + wn * WN + lcol;
+  if constexpr (EPI == EPI_PAIRS) {
+    // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]: the offset splits into a row part
+    // p*nq*kp + c*vu and a column part q*kp + d, both stepped without divisions
+    const int vu = (int)g.vu;
+    int64_t coff[TN];
+    {
+      int q = (int)(nbase / vu), d = (int)(nbase % vu);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        coff[j] = (int64_t)q * g.kp + d;
+        d += 16;
+        while (d >= vu) {
+          d -= vu;
+          ++q;
+        }
+      }
+    }
+    int p = (int)(mb / vu), c = (int)(mb % vu);
+    T* V = (T*)g.C;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      int pr = p, cr = c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = mb + i * 16 + r;
+        if (gm < g.M) {
+          const int64_t roff = (int64_t)pr * g.nq * g.kp + (int64_t)cr * vu;
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (nbase + j * 16 < g.N) V[roff + coff[j]] = lp_round<T>(acc[i][j][r]);
+        }
+        if (++cr == vu) {
+          cr = 0;
+          ++pr;
+        }
+      }
+      c += 16;
+      while (c >= vu) {
+        c -= vu;
+        ++p;
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gm = m0 + wm * WM + i * 16 + 4 * lrow + r;
-        const int64_t gn = n0 + wn * WN + j * 16 + lcol;
+        const int64_t gm = mb + i * 16 + r;
+        const int64_t gn = nbase + j * 16;
         if (gm >= g.M || gn >= g.N) continue;
         const float val = acc[i][j][r];
-        if (EPI == EPI_PAIRS) {
-          // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]
-          const int64_t p = gm / g.vu, c = gm % g.vu, q = gn / g.vu, d = gn % g.vu;
-          ((T*)g.C)[(p * g.nq + q) * g.kp + c * g.vu + d] = lp_round<T>(val);
-        } else if (EPI == EPI_SPLIT) {
+        if (EPI == EPI_SPLIT) {
           float* W = (float*)g.C + (SPLIT ? (int64_t)blockIdx.z * g.split_stride : 0);
           W[gm * g.N + gn] = val;
         } else {
@@ -294,7 +351,7 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
     return;
   }
   int64_t chunk = (q.K + q.ks - 1) / q.ks;
-  chunk = (chunk + Traits<T>::BK - 1) / Traits<T>::BK * Traits<T>::BK;
+  chunk = (chunk + Stage<T, TILE>::BK - 1) / Stage<T, TILE>::BK * Stage<T, TILE>::BK;
   const int ks = (int)((q.K + chunk - 1) / chunk);
   a.C = q.work;
   a.kchunk = chunk;
@@ -306,7 +363,7 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
   DCSD_CHECK_LAUNCH();
 }
 
-template <class T>
+template <class T, int BT>
 void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_t p0, int64_t np, int64_t q0,
                   int64_t nq, int64_t kp, void* V2, hipStream_t s) {
   LArgs a{};
@@ -315,14 +372,16 @@ void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_
   a.B = (const T*)BlT + q0 * vu * ldk; a.ldb = ldk;
   a.C = V2; a.vu = vu; a.nq = nq; a.kp = kp;
   a.kchunk = naux;
-  a.tiles_n = (a.N + TILE - 1) / TILE;
-  const int64_t tiles = ((a.M + TILE - 1) / TILE) * a.tiles_n;
-  hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+  a.tiles_n = (a.N + BT - 1) / BT;
+  const int64_t tiles = ((a.M + BT - 1) / BT) * a.tiles_n;
+  hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false, BT>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();
 }
 
 void check_lp(const LpGemm& q) {
   if (q.M <= 0 || q.N <= 0 || q.K <= 0) throw ArgError("low-precision GEMM: empty shape");
+  if (q.M * q.lda >= ((int64_t)1 << 31) || q.N * q.ldb >= ((int64_t)1 << 31))
+    throw ArgError("low-precision GEMM: operand too large for 32-bit offsets");
   if (q.lda % 8 || q.ldb % 8 || q.lda < q.K || q.ldb < q.K) throw ArgError("low-precision GEMM: bad leading dimension");
   if (((uintptr_t)q.A | (uintptr_t)q.B) & 15) throw ArgError("low-precision GEMM: operands not 16-byte aligned");
   if (q.ks > 1 && !q.work) throw ArgError("low-precision GEMM: split-K needs a workspace");
@@ -351,10 +410,12 @@ void lp_gemm(const LpGemm& q, hipStream_t s) {
 void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_t p0, int64_t np,
               int64_t q0, int64_t nq, int64_t kp, void* V2, hipStream_t s) {
   if (ldk % 8 || kp % 8) throw ArgError("low-precision ladder: bad leading dimension");
+  if ((p0 + np) * vu * ldk >= ((int64_t)1 << 31) || (q0 + nq) * vu * ldk >= ((int64_t)1 << 31))
+    throw ArgError("low-precision ladder: factor too large for 32-bit offsets");
   if (precision == DCSD_PREC_BF16)
-    launch_pairs<__bf16>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
+    launch_pairs<__bf16, 128>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
   else
-    launch_pairs<float>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
+    launch_pairs<float, 128>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
 }
 
 }  // namespace dcsd
