@@ -244,6 +244,21 @@ void dcsd_destroy(dcsd_ctx* ctx);
 dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t K, const double* A_dev,
                                const double* B_dev, double* C_dev, void* hip_stream);
 
+/* Diagnostic (not part of the method): C = alpha * A * B + beta * C through
+ * the library's FP64 GEMM with explicit operand layouts, as the method's
+ * contractions call it.  A is M x K, stored m-contiguous when a_mc != 0
+ * (element (m, k) at A_dev[m + k*lda]) or k-contiguous otherwise
+ * (A_dev[m*lda + k]); B is K x N, stored n-contiguous when b_nc != 0
+ * (B_dev[n + k*ldb]) or k-contiguous otherwise (B_dev[n*ldb + k]); C is M x N
+ * row-major with leading dimension ldc and is read when beta != 0.  ksplit > 1
+ * splits K into that many chunks summed by a second kernel (the library
+ * allocates and frees the partial sums).  Returns DCSD_ERR_ARG on
+ * non-positive sizes, ksplit < 1 or leading dimensions smaller than the
+ * stored extents. */
+dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const double* A_dev, int64_t lda,
+                                      int32_t a_mc, const double* B_dev, int64_t ldb, int32_t b_nc, double* C_dev,
+                                      int64_t ldc, double alpha, double beta, int32_t ksplit, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

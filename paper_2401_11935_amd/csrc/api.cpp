@@ -285,4 +285,37 @@ dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t 
   return st_out;
 }
 
+dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const double* A_dev, int64_t lda,
+                                      int32_t a_mc, const double* B_dev, int64_t ldb, int32_t b_nc, double* C_dev,
+                                      int64_t ldc, double alpha, double beta, int32_t ksplit, void* hip_stream) {
+  if (M <= 0 || N <= 0 || K <= 0 || !A_dev || !B_dev || !C_dev || ksplit < 1) return DCSD_ERR_ARG;
+  if (lda < (a_mc ? M : K) || ldb < (b_nc ? N : K) || ldc < N) return DCSD_ERR_ARG;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  double* w = nullptr;
+  dcsd_status st_out = DCSD_OK;
+  try {
+    dcsd::GemmArgs g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A_dev; g.lda = lda; g.a_mc = a_mc != 0;
+    g.B = B_dev; g.ldb = ldb; g.b_nc = b_nc != 0;
+    g.C = C_dev; g.ldc = ldc; g.c_nc = true;
+    g.alpha = alpha; g.beta = beta;
+    g.ksplit = ksplit;
+    if (ksplit > 1) {
+      if (hipMalloc((void**)&w, (size_t)ksplit * M * ldc * sizeof(double)) != hipSuccess)
+        throw dcsd::HipError("allocation failed");
+      g.work = w;
+    }
+    dcsd::gemm_f64(g, st);
+    if (hipStreamSynchronize(st) != hipSuccess) st_out = DCSD_ERR_HIP;
+  } catch (const dcsd::ArgError&) {
+    st_out = DCSD_ERR_ARG;
+  } catch (...) {
+    st_out = DCSD_ERR_HIP;
+  }
+  (void)hipStreamSynchronize(st);
+  if (w) (void)hipFree(w);
+  return st_out;
+}
+
 }  // extern "C"

@@ -238,6 +238,169 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// K-major operands (A stored [k][m], B stored [k][n]).  Each K step's operand rows
+// go from global memory straight into LDS (global_load_lds_dwordx4: 16 bytes per
+// lane, one 128-wide row per wave instruction), through two LDS stages with
+// BK = 8, on 8 waves holding 4 x 2 wave tiles of 32 x 64.  A step first reads
+// all of its fragments, then issues the next step's rows into the other stage,
+// then runs its MFMAs, so the row loads overlap the matrix work without any
+// register staging.  Lanes whose rows lie past M (N) or K read a zero row.
+// Needs even M, N, lda, ldb and batch strides and 16-byte aligned A, B.
+constexpr int DL_BK = 8, DL_WGM = 4, DL_WGN = 2, DL_NW = DL_WGM * DL_WGN, DL_NT = 64 * DL_NW;
+__device__ __attribute__((aligned(16))) double dl_zero_row[128];
+
+template <int EPI, bool SPLIT, bool C_NC>
+__global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
+  constexpr int BM = 128, BN = 128, ROW = BM + 16;
+  constexpr int WM = BM / DL_WGM, WN = BN / DL_WGN, TM = WM / 16, TN = WN / 16, KS = DL_BK / 4;
+  constexpr int HPW = DL_BK / DL_NW;  // rows of A (and of B) per wave per step
+  static_assert(HPW >= 1 && DL_BK % DL_NW == 0, "row split");
+  __shared__ __attribute__((aligned(16))) double sA[2][DL_BK * ROW];
+  __shared__ __attribute__((aligned(16))) double sB[2][DL_BK * ROW];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / DL_WGN, wn = wave % DL_WGN;
+  int64_t tm, tn;
+  tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t batch = blockIdx.y;
+  int64_t kbeg = 0, kend = g.K;
+  if (SPLIT) {
+    kbeg = (int64_t)blockIdx.z * g.kchunk;
+    kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  }
+  const bool am = m0 + 2 * lane < g.M, bn = n0 + 2 * lane < g.N;
+  const double* zrow = dl_zero_row + 2 * lane;
+  const double* arow = g.A + batch * g.sA + m0 + 2 * lane;
+  const double* brow = g.B + batch * g.sB + n0 + 2 * lane;
+  auto issue = [&](int slot, int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < HPW; ++q) {
+      const int k = wave + q * DL_NW;
+      const bool kin = k0 + k < kend;
+      const double* sa = (am && kin) ? arow + (k0 + k) * g.lda : zrow;
+      const double* sb = (bn && kin) ? brow + (k0 + k) * g.ldb : zrow;
+      __builtin_amdgcn_global_load_lds((const void*)sa, (void __attribute__((address_space(3)))*)&sA[slot][k * ROW],
+                                       16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)sb, (void __attribute__((address_space(3)))*)&sB[slot][k * ROW],
+                                       16, 0, 0);
+    }
+  };
+
+  dbl4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const int lrow = lane >> 4, lcol = lane & 15;
+  const int64_t nk = (kend - kbeg + DL_BK - 1) / DL_BK;
+  issue(0, kbeg);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    // this wave's rows of step kt have landed; the barrier publishes everyone's, and
+    // every wave has finished reading the other stage (step kt-1)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    const int slot = (int)(kt & 1);
+    const double* a_s = sA[slot];
+    const double* b_s = sB[slot];
+    double af[KS][TM], bf[KS][TN];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[ks][i] = a_s[(ks * 4 + lrow) * ROW + wm * WM + i * 16 + lcol];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bf[ks][j] = b_s[(ks * 4 + lrow) * ROW + wn * WN + j * 16 + lcol];
+    }
+    issue(slot ^ 1, kbeg + (kt + 1) * DL_BK);  // rows past kend are zero rows
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks][i], bf[ks][j], acc[i][j], 0, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the last (zero) stage has landed before the wave retires
+
+  double* C = g.C + batch * g.sC;
+  if (SPLIT) C += (int64_t)blockIdx.z * g.split_stride;
+  const int64_t mb = m0 + wm * WM + lrow, nbase = n0 + wn * WN + lcol;
+  if constexpr (EPI == 1) {
+    // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d], offsets stepped as in gemm_kernel
+    const int vu = (int)g.vu;
+    const int64_t vv = g.vu * g.vu;
+    int64_t coff[TN];
+    {
+      int q = (int)(nbase / vu), d = (int)(nbase % vu);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        coff[j] = (int64_t)q * vv + d;
+        d += 16;
+        while (d >= vu) {
+          d -= vu;
+          ++q;
+        }
+      }
+    }
+    int p = (int)(mb / vu), c = (int)(mb % vu);
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (mb + i * 16 + 4 * r < g.M) {
+          const int64_t roff = (int64_t)p * g.nq * vv + (int64_t)c * vu;
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (nbase + j * 16 < g.N) C[roff + coff[j]] = acc[i][j][r];
+        }
+        c += 4;
+        while (c >= vu) {
+          c -= vu;
+          ++p;
+        }
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = mb + i * 16 + 4 * r, gn = nbase + j * 16;
+        if (gm < g.M && gn < g.N) {
+          const int64_t off = C_NC ? gm * g.ldc + gn : gm + gn * g.ldc;
+          if (SPLIT) {
+            C[off] = acc[i][j][r];
+          } else {
+            double v = g.alpha * acc[i][j][r];
+            if (g.beta != 0.0) v += g.beta * C[off];
+            C[off] = v;
+          }
+        }
+      }
+}
+
+// the direct-to-LDS kernel's layout and alignment conditions
+bool dl_ok(const GemmArgs& g) {
+  const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  return g.a_mc && g.b_nc && g.M % 2 == 0 && g.N % 2 == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 &&
+         al16(g.A) && al16(g.B) && (g.batch == 1 || (g.sA % 2 == 0 && g.sB % 2 == 0));
+}
+
+template <bool C_NC>
+void launch_dl(const GemmArgs& g, KArgs& k, hipStream_t s) {
+  const int64_t tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+  k.tiles_n = tn;
+  dim3 grid((unsigned)(tm * tn), (unsigned)g.batch, (unsigned)g.ksplit);
+  if (g.ksplit > 1)
+    hipLaunchKernelGGL((gemm_dl_kernel<0, true, C_NC>), grid, dim3(DL_NT), 0, s, k);
+  else
+    hipLaunchKernelGGL((gemm_dl_kernel<0, false, C_NC>), grid, dim3(DL_NT), 0, s, k);
+}
+
 // C = alpha * sum_z W[z] + beta * C, W[z] laid out like C (same ldc/c_nc/batch strides).
 __global__ void split_reduce(const double* W, double* C, int64_t M, int64_t N, int64_t ldc, bool c_nc,
                              int64_t batch, int64_t sC, int nsplit, int64_t split_stride, double alpha,
@@ -311,7 +474,10 @@ void gemm_f64(const GemmArgs& g, hipStream_t s) {
     k.split_stride = 0;
   }
   const int64_t tiles128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
-  if (g.M >= 128 && g.N >= 128 && tiles128 >= 128)
+  if (g.M >= 128 && g.N >= 128 && tiles128 >= 128 && dl_ok(g)) {
+    if (g.c_nc) launch_dl<true>(g, k, s);
+    else launch_dl<false>(g, k, s);
+  } else if (g.M >= 128 && g.N >= 128 && tiles128 >= 128)
     dispatch<128, 128>(g, k, s);
   else
     dispatch<64, 64>(g, k, s);
@@ -339,7 +505,11 @@ void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int6
   k.kchunk = naux; k.vu = vu; k.nq = nq;
   const int64_t tm = (k.M + 127) / 128, tn = (k.N + 127) / 128;
   k.tiles_n = tn;
-  hipLaunchKernelGGL((gemm_kernel<128, 128, true, true, true, false, 1>), dim3((unsigned)(tm * tn)), dim3(NT), 0, s, k);
+  const bool al = (((uintptr_t)k.A | (uintptr_t)k.B) & 15) == 0;
+  if (k.M % 2 == 0 && k.N % 2 == 0 && ld % 2 == 0 && al)
+    hipLaunchKernelGGL((gemm_dl_kernel<1, false, true>), dim3((unsigned)(tm * tn)), dim3(DL_NT), 0, s, k);
+  else
+    hipLaunchKernelGGL((gemm_kernel<128, 128, true, true, true, false, 1>), dim3((unsigned)(tm * tn)), dim3(NT), 0, s, k);
   DCSD_CHECK_LAUNCH();
 }
 

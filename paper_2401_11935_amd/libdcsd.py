@@ -115,6 +115,10 @@ def load(path: str | None = None):
     lib.dcsd_selftest_gemm.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, dp, dp,
                                        vp]
     lib.dcsd_selftest_gemm.restype = ctypes.c_int
+    lib.dcsd_selftest_gemm_layout.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, dp, ctypes.c_int64,
+                                              ctypes.c_int32, dp, ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]
+    lib.dcsd_selftest_gemm_layout.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -247,3 +251,12 @@ def selftest_gemm(M: int, N: int, K: int, A_ptr: int, B_ptr: int, C_ptr: int, st
     st = (lib or load()).dcsd_selftest_gemm(precision, M, N, K, A_ptr, B_ptr, C_ptr, stream or None)
     if st != DCSD_OK:
         raise DcsdError(st, "selftest_gemm")
+
+
+def selftest_gemm_layout(M: int, N: int, K: int, A_ptr: int, lda: int, a_mc: bool, B_ptr: int, ldb: int,
+                         b_nc: bool, C_ptr: int, ldc: int, alpha: float = 1.0, beta: float = 0.0, ksplit: int = 1,
+                         stream: int = 0, lib=None):
+    st = (lib or load()).dcsd_selftest_gemm_layout(M, N, K, A_ptr, lda, int(a_mc), B_ptr, ldb, int(b_nc), C_ptr, ldc,
+                                                   alpha, beta, ksplit, stream or None)
+    if st != DCSD_OK:
+        raise DcsdError(st, "selftest_gemm_layout")

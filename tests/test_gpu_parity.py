@@ -52,6 +52,46 @@ def test_gemm_matches_numpy(M, N, K):
     assert err <= tol, f"max |C - A B| = {err:.3e} > {tol:.3e}"
 
 
+# (M, N, K, a_mc, b_nc, ksplit, alpha, beta, pad, shift): outputs of at least 128 tiles with
+# K-major operands take the direct-to-LDS kernel when M, N, the leading dimensions and the
+# batch strides are even and both bases are 16-byte aligned; the other rows check its
+# fallbacks (odd M, an 8-byte shifted base, small outputs) and the other operand layouts
+LAYOUTS = [(1536, 1536, 37, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1408, 100, 1, 1, 3, 0.5, 1.0, 0, 0),
+           (1530, 1542, 8, 1, 1, 1, -1.0, 1.0, 0, 0), (1536, 1536, 24, 1, 1, 1, 1.0, 0.0, 6, 0),
+           (1535, 1536, 20, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1536, 20, 1, 1, 1, 1.0, 0.0, 0, 1),
+           (100, 60, 7, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1536, 33, 0, 1, 1, 1.0, 0.5, 0, 0),
+           (1536, 1536, 33, 0, 0, 2, 1.0, 0.0, 0, 0), (1536, 1280, 33, 1, 0, 1, 2.0, 0.0, 2, 0)]
+
+
+@pytest.mark.parametrize("M,N,K,a_mc,b_nc,ks,alpha,beta,pad,shift", LAYOUTS)
+def test_gemm_layouts_match_numpy(M, N, K, a_mc, b_nc, ks, alpha, beta, pad, shift):
+    from paper_2401_11935_amd import libdcsd as L
+    from gpu_util import stream, to_dev
+    say("gemm layout", M, N, K, a_mc, b_nc, ks, alpha, beta, pad, shift)
+    rng = np.random.default_rng(M + 7 * N + 11 * K + a_mc + 2 * b_nc + 3 * ks)
+    Am, Bm, C0 = rng.normal(size=(M, K)), rng.normal(size=(K, N)), rng.normal(size=(M, N))
+    lda, ldb = (M if a_mc else K) + pad, (N if b_nc else K) + pad
+    As = np.zeros((K, lda) if a_mc else (M, lda))
+    if a_mc:
+        As[:, :M] = Am.T  # element (m, k) at m + k*lda
+    else:
+        As[:, :K] = Am  # element (m, k) at m*lda + k
+    Bs = np.zeros((K, ldb) if b_nc else (N, ldb))
+    if b_nc:
+        Bs[:, :N] = Bm  # element (k, n) at n + k*ldb
+    else:
+        Bs[:, :K] = Bm.T  # element (k, n) at n*ldb + k
+    Ad = to_dev(np.concatenate([np.zeros(shift), As.ravel()]))
+    Bd = to_dev(np.concatenate([np.zeros(shift), Bs.ravel()]))
+    Cd = to_dev(C0)
+    L.selftest_gemm_layout(M, N, K, Ad.data_ptr() + 8 * shift, lda, bool(a_mc), Bd.data_ptr() + 8 * shift, ldb,
+                           bool(b_nc), Cd.data_ptr(), N, alpha, beta, ks, stream())
+    ref = alpha * (Am @ Bm) + beta * C0
+    err = float(np.abs(Cd.cpu().numpy() - ref).max())
+    tol = 1e-13 * max(1.0, float(np.abs(ref).max())) * np.sqrt(K)
+    assert err <= tol, f"max |C - ref| = {err:.3e} > {tol:.3e}"
+
+
 SMALL = [(2, 5, 13, "dcsd", 0), (2, 5, 13, "ccsd", 0), (0, 4, 7, "dcsd", 0), (0, 6, 9, "ccsd", 3),
          (3, 7, 11, "dcsd", 4), (3, 7, 11, "ccsd", 5), (1, 9, 17, "dcsd", 2), (4, 3, 5, "ccsd", 1),
          (5, 40, 37, "dcsd", 16), (6, 33, 70, "ccsd", 0)]
