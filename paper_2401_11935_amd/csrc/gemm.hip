@@ -239,53 +239,81 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// K-major operands (A stored [k][m], B stored [k][n]).  Each K step's operand rows
-// go from global memory straight into LDS (global_load_lds_dwordx4: 16 bytes per
-// lane, one 128-wide row per wave instruction), through two LDS stages with
-// BK = 8, on 8 waves holding 4 x 2 wave tiles of 32 x 64.  A step first reads
-// all of its fragments, then issues the next step's rows into the other stage,
-// then runs its MFMAs, so the row loads overlap the matrix work without any
-// register staging.  Lanes whose rows lie past M (N) or K read a zero row.
-// Needs even M, N, lda, ldb and batch strides and 16-byte aligned A, B.
+// Direct-to-LDS GEMM.  Each K step's operand tiles go from global memory
+// straight into LDS (global_load_lds_dwordx4: 16 bytes per lane, 1 KiB per wave
+// instruction) through two LDS stages with BK = 8, on 8 waves holding 4 x 2 wave
+// tiles of 32 x 64.  A step first reads all of its fragments, then issues the
+// next step's tiles into the other stage, then runs its MFMAs, so the loads
+// overlap the matrix work without register staging (four waves per SIMD).
+//
+// Operand layouts (KM = true: the operand's M (N) index is contiguous, stored
+// [k][m]; KM = false: its K index is contiguous, stored [m][k]):
+//  * KM tile: 8 rows (k) of 128 doubles, padded to DL_ROW; wave w loads row w.
+//  * K-contiguous tile: 128 rows (m) of 8 doubles; wave w loads rows 16w..16w+15,
+//    4 lanes per row, and each lane fetches the 16-byte chunk that lands in its
+//    slot under the swizzle slot = chunk ^ ((row >> 2) & 3), which spreads the
+//    16 rows of an MFMA fragment read over distinct LDS banks.
+// Lanes whose elements lie past M (N) or past the K range read a zero row.
+// Needs even extents along each operand's contiguous index, even leading
+// dimensions and batch strides, and 16-byte aligned A, B.
 constexpr int DL_BK = 8, DL_WGM = 4, DL_WGN = 2, DL_NW = DL_WGM * DL_WGN, DL_NT = 64 * DL_NW;
+constexpr int DL_ROW = 128 + 16;
 __device__ __attribute__((aligned(16))) double dl_zero_row[128];
 
-template <int EPI, bool SPLIT, bool C_NC>
+template <bool KM>
+struct DlTile {
+  static constexpr int SIZE = KM ? DL_BK * DL_ROW : 128 * DL_BK;  // doubles per stage
+  // LDS index of element (r, k) of the tile (r: row along M or N within the tile)
+  static __device__ int at(int r, int k) {
+    return KM ? k * DL_ROW + r : r * DL_BK + 2 * ((k >> 1) ^ ((r >> 2) & 3)) + (k & 1);
+  }
+  // this lane's global source for the wave's share of the step starting at k0
+  static __device__ const double* src(const double* P, int64_t ld, int64_t o0, int64_t extent, int64_t k0,
+                                      int64_t kend, int wave, int lane, const double* zrow) {
+    if (KM) {
+      const int64_t k = k0 + wave;
+      return (o0 + 2 * lane < extent && k < kend) ? P + k * ld + o0 + 2 * lane : zrow;
+    }
+    const int r = wave * 16 + (lane >> 2);
+    const int chunk = (lane & 3) ^ ((r >> 2) & 3);
+    const int64_t k = k0 + 2 * chunk;
+    return (o0 + r < extent && k < kend) ? P + (o0 + r) * ld + k : zrow;
+  }
+  static __device__ int dst(int wave) { return KM ? wave * DL_ROW : wave * 128; }
+};
+
+template <bool A_KM, bool B_KM, int EPI, bool SPLIT, bool C_NC>
 __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
-  constexpr int BM = 128, BN = 128, ROW = BM + 16;
+  constexpr int BM = 128, BN = 128;
   constexpr int WM = BM / DL_WGM, WN = BN / DL_WGN, TM = WM / 16, TN = WN / 16, KS = DL_BK / 4;
-  constexpr int HPW = DL_BK / DL_NW;  // rows of A (and of B) per wave per step
-  static_assert(HPW >= 1 && DL_BK % DL_NW == 0, "row split");
-  __shared__ __attribute__((aligned(16))) double sA[2][DL_BK * ROW];
-  __shared__ __attribute__((aligned(16))) double sB[2][DL_BK * ROW];
+  static_assert(DL_NW == DL_BK && DL_NW * 16 == BM, "one wave instruction per operand per step");
+  using TA = DlTile<A_KM>;
+  using TB = DlTile<B_KM>;
+  __shared__ __attribute__((aligned(16))) double sA[2][TA::SIZE];
+  __shared__ __attribute__((aligned(16))) double sB[2][TB::SIZE];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / DL_WGN, wn = wave % DL_WGN;
   int64_t tm, tn;
+  const int64_t z = blockIdx.z;
   tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t batch = blockIdx.y;
   int64_t kbeg = 0, kend = g.K;
   if (SPLIT) {
-    kbeg = (int64_t)blockIdx.z * g.kchunk;
+    kbeg = z * g.kchunk;
     kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
   }
-  const bool am = m0 + 2 * lane < g.M, bn = n0 + 2 * lane < g.N;
   const double* zrow = dl_zero_row + 2 * lane;
-  const double* arow = g.A + batch * g.sA + m0 + 2 * lane;
-  const double* brow = g.B + batch * g.sB + n0 + 2 * lane;
+  const double* A = g.A + batch * g.sA;
+  const double* B = g.B + batch * g.sB;
   auto issue = [&](int slot, int64_t k0) {
-#pragma unroll
-    for (int q = 0; q < HPW; ++q) {
-      const int k = wave + q * DL_NW;
-      const bool kin = k0 + k < kend;
-      const double* sa = (am && kin) ? arow + (k0 + k) * g.lda : zrow;
-      const double* sb = (bn && kin) ? brow + (k0 + k) * g.ldb : zrow;
-      __builtin_amdgcn_global_load_lds((const void*)sa, (void __attribute__((address_space(3)))*)&sA[slot][k * ROW],
-                                       16, 0, 0);
-      __builtin_amdgcn_global_load_lds((const void*)sb, (void __attribute__((address_space(3)))*)&sB[slot][k * ROW],
-                                       16, 0, 0);
-    }
+    const double* sa = TA::src(A, g.lda, m0, g.M, k0, kend, wave, lane, zrow);
+    const double* sb = TB::src(B, g.ldb, n0, g.N, k0, kend, wave, lane, zrow);
+    __builtin_amdgcn_global_load_lds((const void*)sa, (void __attribute__((address_space(3)))*)&sA[slot][TA::dst(wave)],
+                                     16, 0, 0);
+    __builtin_amdgcn_global_load_lds((const void*)sb, (void __attribute__((address_space(3)))*)&sB[slot][TB::dst(wave)],
+                                     16, 0, 0);
   };
 
   dbl4 acc[TM][TN];
@@ -297,7 +325,7 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
   const int64_t nk = (kend - kbeg + DL_BK - 1) / DL_BK;
   issue(0, kbeg);
   for (int64_t kt = 0; kt < nk; ++kt) {
-    // this wave's rows of step kt have landed; the barrier publishes everyone's, and
+    // this wave's loads of step kt have landed; the barrier publishes everyone's, and
     // every wave has finished reading the other stage (step kt-1)
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -308,11 +336,11 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-      for (int i = 0; i < TM; ++i) af[ks][i] = a_s[(ks * 4 + lrow) * ROW + wm * WM + i * 16 + lcol];
+      for (int i = 0; i < TM; ++i) af[ks][i] = a_s[TA::at(wm * WM + i * 16 + lcol, ks * 4 + lrow)];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) bf[ks][j] = b_s[(ks * 4 + lrow) * ROW + wn * WN + j * 16 + lcol];
+      for (int j = 0; j < TN; ++j) bf[ks][j] = b_s[TB::at(wn * WN + j * 16 + lcol, ks * 4 + lrow)];
     }
-    issue(slot ^ 1, kbeg + (kt + 1) * DL_BK);  // rows past kend are zero rows
+    issue(slot ^ 1, kbeg + (kt + 1) * DL_BK);  // past kend: zero rows
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -324,7 +352,7 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
   __builtin_amdgcn_s_waitcnt(0);  // the last (zero) stage has landed before the wave retires
 
   double* C = g.C + batch * g.sC;
-  if (SPLIT) C += (int64_t)blockIdx.z * g.split_stride;
+  if (SPLIT) C += z * g.split_stride;
   const int64_t mb = m0 + wm * WM + lrow, nbase = n0 + wn * WN + lcol;
   if constexpr (EPI == 1) {
     // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d], offsets stepped as in gemm_kernel
@@ -386,19 +414,38 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
 // the direct-to-LDS kernel's layout and alignment conditions
 bool dl_ok(const GemmArgs& g) {
   const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  return g.a_mc && g.b_nc && g.M % 2 == 0 && g.N % 2 == 0 && g.lda % 2 == 0 && g.ldb % 2 == 0 &&
-         al16(g.A) && al16(g.B) && (g.batch == 1 || (g.sA % 2 == 0 && g.sB % 2 == 0));
+  // split-K with both operands K-contiguous (the ladder contraction: few rows, operands
+  // streamed from HBM) runs faster on the register-staged kernel's deeper K steps
+  if (!g.a_mc && !g.b_nc && g.ksplit > 1) return false;
+  const bool a = g.a_mc ? g.M % 2 == 0 : g.K % 2 == 0;
+  const bool b = g.b_nc ? g.N % 2 == 0 : g.K % 2 == 0;
+  return a && b && g.lda % 2 == 0 && g.ldb % 2 == 0 && al16(g.A) && al16(g.B) &&
+         (g.batch == 1 || (g.sA % 2 == 0 && g.sB % 2 == 0));
 }
 
-template <bool C_NC>
-void launch_dl(const GemmArgs& g, KArgs& k, hipStream_t s) {
+template <bool A_KM, bool B_KM, bool C_NC>
+void launch_dl3(const GemmArgs& g, KArgs& k, hipStream_t s) {
   const int64_t tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
   k.tiles_n = tn;
   dim3 grid((unsigned)(tm * tn), (unsigned)g.batch, (unsigned)g.ksplit);
   if (g.ksplit > 1)
-    hipLaunchKernelGGL((gemm_dl_kernel<0, true, C_NC>), grid, dim3(DL_NT), 0, s, k);
+    hipLaunchKernelGGL((gemm_dl_kernel<A_KM, B_KM, 0, true, C_NC>), grid, dim3(DL_NT), 0, s, k);
   else
-    hipLaunchKernelGGL((gemm_dl_kernel<0, false, C_NC>), grid, dim3(DL_NT), 0, s, k);
+    hipLaunchKernelGGL((gemm_dl_kernel<A_KM, B_KM, 0, false, C_NC>), grid, dim3(DL_NT), 0, s, k);
+}
+
+void launch_dl(const GemmArgs& g, KArgs& k, hipStream_t s) {
+  const int code = (g.a_mc ? 4 : 0) | (g.b_nc ? 2 : 0) | (g.c_nc ? 1 : 0);
+  switch (code) {
+    case 0: launch_dl3<false, false, false>(g, k, s); break;
+    case 1: launch_dl3<false, false, true>(g, k, s); break;
+    case 2: launch_dl3<false, true, false>(g, k, s); break;
+    case 3: launch_dl3<false, true, true>(g, k, s); break;
+    case 4: launch_dl3<true, false, false>(g, k, s); break;
+    case 5: launch_dl3<true, false, true>(g, k, s); break;
+    case 6: launch_dl3<true, true, false>(g, k, s); break;
+    default: launch_dl3<true, true, true>(g, k, s); break;
+  }
 }
 
 // C = alpha * sum_z W[z] + beta * C, W[z] laid out like C (same ldc/c_nc/batch strides).
@@ -475,8 +522,7 @@ void gemm_f64(const GemmArgs& g, hipStream_t s) {
   }
   const int64_t tiles128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
   if (g.M >= 128 && g.N >= 128 && tiles128 >= 128 && dl_ok(g)) {
-    if (g.c_nc) launch_dl<true>(g, k, s);
-    else launch_dl<false>(g, k, s);
+    launch_dl(g, k, s);
   } else if (g.M >= 128 && g.N >= 128 && tiles128 >= 128)
     dispatch<128, 128>(g, k, s);
   else
@@ -507,7 +553,7 @@ void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int6
   k.tiles_n = tn;
   const bool al = (((uintptr_t)k.A | (uintptr_t)k.B) & 15) == 0;
   if (k.M % 2 == 0 && k.N % 2 == 0 && ld % 2 == 0 && al)
-    hipLaunchKernelGGL((gemm_dl_kernel<1, false, true>), dim3((unsigned)(tm * tn)), dim3(DL_NT), 0, s, k);
+    hipLaunchKernelGGL((gemm_dl_kernel<true, true, 1, false, true>), dim3((unsigned)(tm * tn)), dim3(DL_NT), 0, s, k);
   else
     hipLaunchKernelGGL((gemm_kernel<128, 128, true, true, true, false, 1>), dim3((unsigned)(tm * tn)), dim3(NT), 0, s, k);
   DCSD_CHECK_LAUNCH();

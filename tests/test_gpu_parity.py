@@ -54,13 +54,18 @@ def test_gemm_matches_numpy(M, N, K):
 
 # (M, N, K, a_mc, b_nc, ksplit, alpha, beta, pad, shift): outputs of at least 128 tiles with
 # K-major operands take the direct-to-LDS kernel when M, N, the leading dimensions and the
-# batch strides are even and both bases are 16-byte aligned; the other rows check its
-# fallbacks (odd M, an 8-byte shifted base, small outputs) and the other operand layouts
+# batch strides are even and both bases are 16-byte aligned (K-major operands need an even
+# extent along M (N), K-contiguous ones an even K); the other rows check its fallbacks (odd
+# M or K, an 8-byte shifted base, small outputs)
 LAYOUTS = [(1536, 1536, 37, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1408, 100, 1, 1, 3, 0.5, 1.0, 0, 0),
            (1530, 1542, 8, 1, 1, 1, -1.0, 1.0, 0, 0), (1536, 1536, 24, 1, 1, 1, 1.0, 0.0, 6, 0),
            (1535, 1536, 20, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1536, 20, 1, 1, 1, 1.0, 0.0, 0, 1),
            (100, 60, 7, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1536, 33, 0, 1, 1, 1.0, 0.5, 0, 0),
-           (1536, 1536, 33, 0, 0, 2, 1.0, 0.0, 0, 0), (1536, 1280, 33, 1, 0, 1, 2.0, 0.0, 2, 0)]
+           (1536, 1536, 33, 0, 0, 2, 1.0, 0.0, 0, 0), (1536, 1280, 33, 1, 0, 1, 2.0, 0.0, 2, 0),
+           (1536, 1536, 40, 0, 1, 1, 1.0, 0.5, 0, 0), (1536, 1536, 64, 0, 0, 3, 1.0, 0.0, 0, 0),
+           (1536, 1280, 34, 1, 0, 1, 2.0, 0.0, 2, 0), (1501, 1527, 50, 0, 0, 1, -0.5, 1.0, 4, 0),
+           (1500, 1530, 26, 0, 1, 2, 1.0, 1.0, 0, 0), (1500, 1530, 120, 1, 1, 8, 0.5, 1.0, 0, 0),
+           (338, 1024, 1000, 0, 0, 16, 1.0, 0.0, 0, 0)]
 
 
 @pytest.mark.parametrize("M,N,K,a_mc,b_nc,ks,alpha,beta,pad,shift", LAYOUTS)
