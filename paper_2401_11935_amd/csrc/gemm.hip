@@ -241,10 +241,15 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
 // ---------------------------------------------------------------------------
 // Direct-to-LDS GEMM.  Each K step's operand tiles go from global memory
 // straight into LDS (global_load_lds_dwordx4: 16 bytes per lane, 1 KiB per wave
-// instruction) through two LDS stages with BK = 8, on 8 waves holding 4 x 2 wave
-// tiles of 32 x 64.  A step first reads all of its fragments, then issues the
-// next step's tiles into the other stage, then runs its MFMAs, so the loads
-// overlap the matrix work without register staging (four waves per SIMD).
+// instruction) through a ring of S LDS stages with BK = 8, on 8 waves holding
+// 4 x 2 wave tiles of 32 x 64 (four waves per SIMD).  A step waits until its own
+// stage has landed (S - 2 younger steps stay in flight), reads all of its
+// fragments, issues the step S - 1 ahead into the stage read one step earlier,
+// then runs its MFMAs, so the loads overlap S - 1 steps of matrix work without
+// register staging.  The fragment reads are written as LDS reads that wait for
+// their own results inside the same asm block, and the step barrier is a bare
+// s_barrier: the compiler's own waits before LDS reads and at workgroup fences
+// would drain every load in flight, including the younger stages.
 //
 // Operand layouts (KM = true: the operand's M (N) index is contiguous, stored
 // [k][m]; KM = false: its K index is contiguous, stored [m][k]):
@@ -282,15 +287,25 @@ struct DlTile {
   static __device__ int dst(int wave) { return KM ? wave * DL_ROW : wave * 128; }
 };
 
+__device__ inline uint32_t lds_byte_address(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// s_waitcnt immediate: at most `vm` vector-memory operations outstanding, no other wait
+constexpr int waitcnt_vm(int vm) { return (vm & 0xF) | ((vm >> 4) << 14) | (7 << 4) | (0xF << 8); }
+
 template <bool A_KM, bool B_KM, int EPI, bool SPLIT, bool C_NC>
 __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
   constexpr int BM = 128, BN = 128;
   constexpr int WM = BM / DL_WGM, WN = BN / DL_WGN, TM = WM / 16, TN = WN / 16, KS = DL_BK / 4;
   static_assert(DL_NW == DL_BK && DL_NW * 16 == BM, "one wave instruction per operand per step");
+  static_assert(TM == 2 && TN == 4 && KS == 2, "the fragment reads below are written for 2 x 4 fragments");
+  // K-major tiles stream from L2 (two stages suffice); K-contiguous ones see longer latency
+  constexpr int S = (A_KM && B_KM) ? 2 : 4;
   using TA = DlTile<A_KM>;
   using TB = DlTile<B_KM>;
-  __shared__ __attribute__((aligned(16))) double sA[2][TA::SIZE];
-  __shared__ __attribute__((aligned(16))) double sB[2][TB::SIZE];
+  __shared__ __attribute__((aligned(16))) double sA[S][TA::SIZE];
+  __shared__ __attribute__((aligned(16))) double sB[S][TB::SIZE];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / DL_WGN, wn = wave % DL_WGN;
@@ -322,25 +337,44 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
   const int lrow = lane >> 4, lcol = lane & 15;
+  // byte offsets of this lane's fragments within a stage, per k sub-step; the next
+  // 16 rows of a tile sit a fixed distance further in both layouts
+  uint32_t ao[KS], bo[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    ao[ks] = 8u * (uint32_t)TA::at(wm * WM + lcol, ks * 4 + lrow);
+    bo[ks] = 8u * (uint32_t)TB::at(wn * WN + lcol, ks * 4 + lrow);
+  }
+  constexpr uint32_t AI = 8u * (A_KM ? 16 : 16 * DL_BK), BJ = 8u * (B_KM ? 16 : 16 * DL_BK);
   const int64_t nk = (kend - kbeg + DL_BK - 1) / DL_BK;
-  issue(0, kbeg);
+#pragma unroll
+  for (int t = 0; t < S - 1; ++t) issue(t, kbeg + t * DL_BK);
   for (int64_t kt = 0; kt < nk; ++kt) {
-    // this wave's loads of step kt have landed; the barrier publishes everyone's, and
-    // every wave has finished reading the other stage (step kt-1)
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    const int slot = (int)(kt & 1);
-    const double* a_s = sA[slot];
-    const double* b_s = sB[slot];
+    // this wave's loads of step kt have landed (the S - 2 younger steps may not have);
+    // after the barrier everyone's have, and every wave has finished reading the stage
+    // that the issue below refills (it was read at step kt - 1)
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * (S - 2)));
+    __builtin_amdgcn_s_barrier();
+    const int slot = (int)(kt & (S - 1));
+    const uint32_t sa = lds_byte_address(sA[slot]), sb = lds_byte_address(sB[slot]);
     double af[KS][TM], bf[KS][TN];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-      for (int i = 0; i < TM; ++i) af[ks][i] = a_s[TA::at(wm * WM + i * 16 + lcol, ks * 4 + lrow)];
-#pragma unroll
-      for (int j = 0; j < TN; ++j) bf[ks][j] = b_s[TB::at(wn * WN + j * 16 + lcol, ks * 4 + lrow)];
+      const uint32_t pa = sa + ao[ks], pb = sb + bo[ks];
+      asm volatile(
+          "ds_read_b64 %0, %6\n"
+          "ds_read_b64 %1, %6 offset:%8\n"
+          "ds_read_b64 %2, %7\n"
+          "ds_read_b64 %3, %7 offset:%9\n"
+          "ds_read_b64 %4, %7 offset:%10\n"
+          "ds_read_b64 %5, %7 offset:%11\n"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(af[ks][0]), "=&v"(af[ks][1]), "=&v"(bf[ks][0]), "=&v"(bf[ks][1]), "=&v"(bf[ks][2]),
+            "=&v"(bf[ks][3])
+          : "v"(pa), "v"(pb), "n"(AI), "n"(BJ), "n"(2 * BJ), "n"(3 * BJ)
+          : "memory");
     }
-    issue(slot ^ 1, kbeg + (kt + 1) * DL_BK);  // past kend: zero rows
+    issue((int)((kt + S - 1) & (S - 1)), kbeg + (kt + S - 1) * DL_BK);  // past kend: zero rows
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
@@ -414,9 +448,6 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
 // the direct-to-LDS kernel's layout and alignment conditions
 bool dl_ok(const GemmArgs& g) {
   const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  // split-K with both operands K-contiguous (the ladder contraction: few rows, operands
-  // streamed from HBM) runs faster on the register-staged kernel's deeper K steps
-  if (!g.a_mc && !g.b_nc && g.ksplit > 1) return false;
   const bool a = g.a_mc ? g.M % 2 == 0 : g.K % 2 == 0;
   const bool b = g.b_nc ? g.N % 2 == 0 : g.K % 2 == 0;
   return a && b && g.lda % 2 == 0 && g.ldb % 2 == 0 && al16(g.A) && al16(g.B) &&
