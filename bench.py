@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_ladder_assembly_fp64_nc12_nv400_naux1200.json")
-ASSEMBLY_KERNEL = "gemm_kernel<128, 128, true, true, true, false, 1>"
+ASSEMBLY_KERNEL = "gemm_dl_kernel<true, true, 1, false, true>"
 ASSEMBLY_SOURCE = os.path.join(ROOT, "paper_2401_11935_amd", "csrc", "gemm.hip")
 
 
