@@ -26,257 +26,14 @@
 #include <stdexcept>
 #include <vector>
 
+#include "coupling_terms.h"
 #include "kernels.h"
 
 namespace dcsd {
 
 namespace {
 
-enum Kind : int { CORE = 0, KT = 1, KU = 2, VIRT = 3 };
-
-// A spin-orbital of a pattern: spin, kind and (for core/virtual) which index
-// of x (0..3 = i, j, a, b) supplies its position.
-struct Lo {
-  int spin, kind, slot;
-  bool operator==(const Lo& o) const { return spin == o.spin && kind == o.kind && slot == o.slot; }
-};
-
-bool occA(const Lo& d) { return d.kind == CORE || (d.kind == KT && d.spin == 0) || (d.kind == KU && d.spin == 1); }
-
-// ---- device tables -----------------------------------------------------------
-// Factor: a T_A amplitude.  type 1: t1[spin][occ(o0)][vir(o1)];
-// type 2: t2[blk][occ(o0)][occ(o1)][vir(o2)][vir(o3)], blk 0 aa, 1 bb, 2 ab.
-// Orbital reference: kind (CORE/VIRT use the x index `slot`, KT/KU are fixed).
-struct DFac {
-  signed char type, blk;
-  signed char kind[4];
-  signed char slot[4];
-};
-constexpr int MAXF = 6;
-struct DTerm {
-  double coef;
-  int nf;
-  DFac f[MAXF];
-};
-
-struct PatternLaunch {
-  int block;       // 0 t1a, 1 t1b, 2 t2aa, 3 t2bb, 4 t2ab
-  int kind[4];     // kinds of i, j, a, b (j, b unused for singles)
-  int cnt[4];      // index range sizes
-  int term_off, nterms;
-};
-
-// ---- host-side symbolic expansion -------------------------------------------
-struct HTerm {
-  double coef;
-  std::vector<DFac> f;
-};
-
-int apply_ops_host(unsigned& mask, const std::vector<std::pair<int, int>>& ops) {
-  int sign = 1;
-  for (int q = (int)ops.size() - 1; q >= 0; --q) {
-    const unsigned bit = 1u << ops[q].second;
-    if (__builtin_popcount(mask & (bit - 1u)) & 1) sign = -sign;
-    if (ops[q].first) {
-      if (mask & bit) return 0;
-      mask |= bit;
-    } else {
-      if (!(mask & bit)) return 0;
-      mask ^= bit;
-    }
-  }
-  return sign;
-}
-
-// T_A single amplitude (h -> p) as a device factor; false if it vanishes.
-bool fac1(const Lo& h, const Lo& p, DFac& f) {
-  if (h.spin != p.spin || !occA(h) || occA(p)) return false;
-  f = DFac{};
-  f.type = 1;
-  f.blk = (signed char)h.spin;
-  f.kind[0] = (signed char)h.kind; f.slot[0] = (signed char)h.slot;
-  f.kind[1] = (signed char)p.kind; f.slot[1] = (signed char)p.slot;
-  return true;
-}
-
-// T_A double amplitude (h1 h2 -> p1 p2) in the stored block order; returns
-// the sign (0 if it vanishes).
-int fac2(Lo h1, Lo h2, Lo p1, Lo p2, DFac& f) {
-  if (!occA(h1) || !occA(h2) || occA(p1) || occA(p2)) return 0;
-  if (h1 == h2 || p1 == p2) return 0;
-  int sign = 1, blk;
-  if (h1.spin == h2.spin) {
-    if (p1.spin != h1.spin || p2.spin != h1.spin) return 0;
-    blk = h1.spin;
-  } else {
-    if (p1.spin == p2.spin) return 0;
-    if (h1.spin == 1) { std::swap(h1, h2); sign = -sign; }
-    if (p1.spin == 1) { std::swap(p1, p2); sign = -sign; }
-    blk = 2;
-  }
-  f = DFac{};
-  f.type = 2;
-  f.blk = (signed char)blk;
-  const Lo o[4] = {h1, h2, p1, p2};
-  for (int k = 0; k < 4; ++k) {
-    f.kind[k] = (signed char)o[k].kind;
-    f.slot[k] = (signed char)o[k].slot;
-  }
-  return sign;
-}
-
-Lo flip(Lo d) {
-  d.spin ^= 1;
-  return d;
-}
-
-const int kMatch[5][10][4] = {
-    {},
-    {{-1}},
-    {{-1, -1}, {1, 0}},
-    {{-1, -1, -1}, {-1, 2, 1}, {1, 0, -1}, {2, -1, 0}},
-    {{-1, -1, -1, -1}, {-1, -1, 3, 2}, {-1, 2, 1, -1}, {-1, 3, -1, 1}, {1, 0, -1, -1},
-     {1, 0, 3, 2}, {2, -1, 0, -1}, {2, 3, 0, 1}, {3, -1, -1, 0}, {3, 2, 1, 0}}};
-const int kNMatch[5] = {1, 1, 2, 4, 10};
-
-// Cluster expansion of the coefficient of a+_{P0}..a+_{P(r-1)} a_{H(r-1)}..a_{H0}|B>
-// in e^{T_B}|B>, as a list of (coefficient, factors) with T_B = flipped T_A.
-std::vector<HTerm> expand_cluster(const std::vector<Lo>& L, const std::vector<int>& H, const std::vector<int>& P) {
-  const int r = (int)H.size();
-  std::vector<HTerm> out;
-  if (r == 0) {
-    out.push_back({1.0, {}});
-    return out;
-  }
-  std::vector<int> perm(r);
-  for (int k = 0; k < r; ++k) perm[k] = k;
-  do {
-    int sgn = 1;
-    for (int a = 0; a < r; ++a)
-      for (int b = a + 1; b < r; ++b)
-        if (perm[a] > perm[b]) sgn = -sgn;
-    for (int m = 0; m < kNMatch[r]; ++m) {
-      const int* mt = kMatch[r][m];
-      HTerm t{(double)sgn, {}};
-      bool ok = true;
-      for (int k = 0; k < r && ok; ++k) {
-        const int partner = mt[k];
-        DFac f;
-        if (partner < 0) {
-          ok = fac1(flip(L[H[k]]), flip(L[P[perm[k]]]), f);
-          if (ok) t.f.push_back(f);
-        } else if (partner > k) {
-          const int s = fac2(flip(L[H[k]]), flip(L[H[partner]]), flip(L[P[perm[k]]]), flip(L[P[perm[partner]]]), f);
-          ok = s != 0;
-          if (ok) {
-            t.coef *= 0.5 * s;
-            t.f.push_back(f);
-          }
-        }
-      }
-      if (ok) out.push_back(t);
-    }
-  } while (std::next_permutation(perm.begin(), perm.end()));
-  return out;
-}
-
-// All terms of K_x for one pattern (x = holes -> parts).
-std::vector<HTerm> expand_pattern(const std::vector<Lo>& holes, const std::vector<Lo>& parts) {
-  std::vector<Lo> L = {{0, KT, -1}, {1, KU, -1}, {0, KU, -1}, {1, KT, -1}};  // t a, u b, u a, t b
-  auto add = [&](const Lo& d) {
-    for (size_t k = 0; k < L.size(); ++k)
-      if (L[k] == d) return (int)k;
-    L.push_back(d);
-    return (int)L.size() - 1;
-  };
-  const int rank = (int)holes.size();
-  int hi[2], pi[2];
-  for (int k = 0; k < rank; ++k) hi[k] = add(holes[k]);
-  for (int k = 0; k < rank; ++k) pi[k] = add(parts[k]);
-  unsigned maskA = 0;
-  for (size_t k = 0; k < L.size(); ++k)
-    if (occA(L[k])) maskA |= 1u << k;
-  unsigned maskB = maskA;
-  const int sB = apply_ops_host(maskB, {{1, 2}, {1, 3}, {0, 1}, {0, 0}});  // a+_{ua} a+_{tb} a_{ub} a_{ta}
-
-  // sub-excitations y of x with the e^{-T_A} matrix elements <A^x|e^{-T_A}|A^y>
-  struct Y {
-    std::vector<std::pair<int, int>> ops;
-    std::vector<HTerm> e;
-  };
-  std::vector<Y> ys;
-  auto mono = [](double c, std::initializer_list<std::pair<bool, DFac>> fs) {
-    HTerm t{c, {}};
-    for (auto& p : fs) {
-      if (!p.first) return HTerm{0.0, {}};
-      t.f.push_back(p.second);
-    }
-    return t;
-  };
-  DFac f0, f1;
-  if (rank == 1) {
-    ys.push_back({{}, {}});
-    {
-      const bool ok = fac1(holes[0], parts[0], f0);
-      ys.back().e.push_back(mono(-1.0, {{ok, f0}}));
-    }
-    ys.push_back({{{1, pi[0]}, {0, hi[0]}}, {HTerm{1.0, {}}}});
-  } else {
-    Y y0{{}, {}};
-    {
-      DFac f2;
-      const int s = fac2(holes[0], holes[1], parts[0], parts[1], f2);
-      if (s) y0.e.push_back(HTerm{-1.0 * s, {f2}});
-      bool a = fac1(holes[0], parts[0], f0), b = fac1(holes[1], parts[1], f1);
-      y0.e.push_back(mono(1.0, {{a, f0}, {b, f1}}));
-      a = fac1(holes[0], parts[1], f0);
-      b = fac1(holes[1], parts[0], f1);
-      y0.e.push_back(mono(-1.0, {{a, f0}, {b, f1}}));
-    }
-    ys.push_back(y0);
-    // single y = (h -> p): -t(j->b) for (i->a), +t(i->b) for (j->a), +t(j->a) for (i->b), -t(i->a) for (j->b)
-    const int yh[4] = {0, 1, 0, 1}, yp[4] = {0, 0, 1, 1};
-    const double ys_sign[4] = {-1.0, 1.0, 1.0, -1.0};
-    for (int q = 0; q < 4; ++q) {
-      const int oh = 1 - yh[q], opp = 1 - yp[q];
-      const bool ok = fac1(holes[oh], parts[opp], f0);
-      ys.push_back({{{1, pi[yp[q]]}, {0, hi[yh[q]]}}, {mono(ys_sign[q], {{ok, f0}})}});
-    }
-    ys.push_back({{{1, pi[0]}, {1, pi[1]}, {0, hi[1]}, {0, hi[0]}}, {HTerm{1.0, {}}}});
-  }
-
-  std::vector<HTerm> terms;
-  for (const Y& y : ys) {
-    bool any = false;
-    for (const HTerm& e : y.e) any = any || e.coef != 0.0;
-    if (!any) continue;
-    unsigned my = maskA;
-    const int sy = apply_ops_host(my, y.ops);
-    if (sy == 0) continue;
-    const unsigned hb = maskB & ~my, pb = my & ~maskB;
-    if (__builtin_popcount(hb) != __builtin_popcount(pb) || __builtin_popcount(hb) > 4) continue;
-    std::vector<int> H, P;
-    for (size_t k = 0; k < L.size(); ++k) {
-      if (hb & (1u << k)) H.push_back((int)k);
-      if (pb & (1u << k)) P.push_back((int)k);
-    }
-    std::vector<std::pair<int, int>> canon;
-    for (int p : P) canon.push_back({1, p});
-    for (int k = (int)H.size() - 1; k >= 0; --k) canon.push_back({0, H[k]});
-    unsigned mc = maskB;
-    const int sc = apply_ops_host(mc, canon);
-    if (sc == 0 || mc != my) continue;
-    const double pre = (double)(sy * sB * sc);
-    for (const HTerm& c : expand_cluster(L, H, P))
-      for (const HTerm& e : y.e) {
-        if (e.coef == 0.0) continue;
-        HTerm t{pre * c.coef * e.coef, e.f};
-        t.f.insert(t.f.end(), c.f.begin(), c.f.end());
-        terms.push_back(t);
-      }
-  }
-  return terms;
-}
+using namespace cpl;
 
 // ---- device evaluation --------------------------------------------------------
 struct Amp {
@@ -304,39 +61,83 @@ __device__ inline double factor(const Amp& A, const DFac& f, int i, int j, int a
   return A.t2[f.blk][(((int64_t)h1 * A.o + h2) * A.v + p1) * A.v + p2];
 }
 
-// One pattern: thread -> (i, j, a, b) over the pattern's index ranges (core and
-// virtual indices 0-based).  Equal-spin doubles with two core (virtual) indices
-// are handled for i < j (a < b) and written to the four antisymmetric copies.
-__global__ void coupling_pattern(const DTerm* __restrict__ terms, int nterms, PatternLaunch pl, Amp A,
-                                 double* __restrict__ R, const double* __restrict__ Wp) {
-  const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
+// Compile-time tables (generated at build time from the same expansion):
+// Fixed<P> holds pattern P's distinct factors and its terms over them.
+#include "coupling_tables.inc"
+
+// p -> (lo, hi), lo < hi < n, enumerating the pairs row by row (hi fastest)
+__device__ inline void tri_pair(int64_t p, int n, int& lo, int& hi) {
+  const auto start = [n](int64_t r) { return r * (2 * (int64_t)n - r - 1) / 2; };
+  const double b = 2.0 * n - 1.0;
+  int64_t r = (int64_t)((b - sqrt(fmax(b * b - 8.0 * (double)p, 0.0))) * 0.5);
+  r = r < 0 ? 0 : (r > n - 2 ? n - 2 : r);
+  while (r > 0 && start(r) > p) --r;
+  while (r < n - 2 && start(r + 1) <= p) ++r;
+  lo = (int)r;
+  hi = (int)(r + 1 + (p - start(r)));
+}
+
+// Element count of a pattern launch: equal-spin doubles with two core (two
+// virtual) indices take i < j (a < b) only and write the antisymmetric copies.
+template <class F>
+__host__ __device__ inline void pair_counts(const PatternLaunch& pl, int64_t& nij, int64_t& nab) {
+  constexpr bool same = F::block == 2 || F::block == 3;
+  constexpr bool tri_ij = same && F::kind[0] == CORE && F::kind[1] == CORE;
+  constexpr bool tri_ab = same && F::kind[2] == VIRT && F::kind[3] == VIRT;
+  nij = tri_ij ? (int64_t)pl.cnt[0] * (pl.cnt[0] - 1) / 2 : (int64_t)pl.cnt[0] * pl.cnt[1];
+  nab = tri_ab ? (int64_t)pl.cnt[2] * (pl.cnt[2] - 1) / 2 : (int64_t)pl.cnt[2] * pl.cnt[3];
+}
+
+// One pattern, one thread per element (i, j, a, b) (core and virtual indices
+// 0-based): every distinct factor is loaded once, then the terms are summed
+// with indices known at compile time.
+template <int P>
+__global__ __launch_bounds__(256) void coupling_fixed(PatternLaunch pl, Amp A, double* __restrict__ R,
+                                                      const double* __restrict__ Wp) {
+  using F = Fixed<P>;
+  constexpr bool same = F::block == 2 || F::block == 3;
+  constexpr bool tri_ij = same && F::kind[0] == CORE && F::kind[1] == CORE;
+  constexpr bool tri_ab = same && F::kind[2] == VIRT && F::kind[3] == VIRT;
+  int64_t nij, nab;
+  pair_counts<F>(pl, nij, nab);
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= tot) return;
-  int64_t r = id;
-  const int bb = (int)(r % pl.cnt[3]); r /= pl.cnt[3];
-  const int aa = (int)(r % pl.cnt[2]); r /= pl.cnt[2];
-  const int jj = (int)(r % pl.cnt[1]);
-  const int ii = (int)(r / pl.cnt[1]);
-  const bool same = pl.block == 2 || pl.block == 3;
-  if (same && pl.kind[0] == CORE && pl.kind[1] == CORE && ii >= jj) return;
-  if (same && pl.kind[2] == VIRT && pl.kind[3] == VIRT && aa >= bb) return;
+  if (id >= nij * nab) return;
+  const int64_t pij = id / nab, pab = id % nab;
+  int ii, jj, aa, bb;
+  if (tri_ij) {
+    tri_pair(pij, pl.cnt[0], ii, jj);
+  } else {
+    ii = (int)(pij / pl.cnt[1]);
+    jj = (int)(pij % pl.cnt[1]);
+  }
+  if (tri_ab) {
+    tri_pair(pab, pl.cnt[2], aa, bb);
+  } else {
+    aa = (int)(pab / pl.cnt[3]);
+    bb = (int)(pab % pl.cnt[3]);
+  }
+  double fv[F::ND];
+#pragma unroll
+  for (int f = 0; f < F::ND; ++f) fv[f] = factor(A, F::fac[f], ii, jj, aa, bb);
   double K = 0.0;
-  for (int t = 0; t < nterms; ++t) {
-    const DTerm& T = terms[t];
-    double v = T.coef;
-    for (int q = 0; q < T.nf; ++q) v *= factor(A, T.f[q], ii, jj, aa, bb);
+#pragma unroll
+  for (int t = 0; t < F::NT; ++t) {
+    double v = F::term[t].coef;
+#pragma unroll
+    for (int q = 0; q < MAXF; ++q)
+      if (q < F::term[t].nf) v *= fv[F::term[t].idx[q]];
     K += v;
   }
   const double KW = K * (*Wp);
   const int nc = A.nc, o = A.o, v = A.v;
   const int64_t ov = (int64_t)o * v, s2 = ov * ov;
-  const int i = occ_pos(pl.kind[0], ii, nc), a = vir_pos(pl.kind[2], aa);
-  if (pl.block < 2) {
-    R[pl.block * ov + (int64_t)i * v + a] -= KW;
+  const int i = occ_pos(F::kind[0], ii, nc), a = vir_pos(F::kind[2], aa);
+  if (F::block < 2) {
+    R[F::block * ov + (int64_t)i * v + a] -= KW;
     return;
   }
-  const int j = occ_pos(pl.kind[1], jj, nc), b = vir_pos(pl.kind[3], bb);
-  double* Rb = R + 2 * ov + (int64_t)(pl.block - 2) * s2;
+  const int j = occ_pos(F::kind[1], jj, nc), b = vir_pos(F::kind[3], bb);
+  double* Rb = R + 2 * ov + (int64_t)(F::block - 2) * s2;
   auto at = [&](int p, int q, int c, int d) -> double& { return Rb[(((int64_t)p * o + q) * v + c) * v + d]; };
   at(i, j, a, b) -= KW;
   if (same) {
@@ -346,80 +147,58 @@ __global__ void coupling_pattern(const DTerm* __restrict__ terms, int nterms, Pa
   }
 }
 
+template <int P>
+void launch_fixed(const PatternLaunch& pl, const Amp& A, double* R, const double* Wp, hipStream_t s) {
+  int64_t nij, nab;
+  pair_counts<Fixed<P>>(pl, nij, nab);
+  const int64_t tot = nij * nab;
+  if (tot <= 0 || Fixed<P>::NT == 0) return;
+  hipLaunchKernelGGL(coupling_fixed<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, pl, A, R, Wp);
+}
+
+// Does pattern P's compile-time table equal the fixed form of these terms?
+template <int P>
+bool fixed_matches(const PatternLaunch& pl, const DTerm* terms) {
+  using F = Fixed<P>;
+  if (pl.block != F::block) return false;
+  for (int k = 0; k < 4; ++k)
+    if (pl.kind[k] != F::kind[k]) return false;
+  std::vector<DFac> fac;
+  std::vector<FTerm> term;
+  fixed_form(terms + pl.term_off, pl.nterms, fac, term);
+  if ((int)fac.size() != F::ND || (int)term.size() != F::NT) return false;
+  for (int k = 0; k < F::ND; ++k)
+    if (!same_factor(fac[k], F::fac[k])) return false;
+  for (int t = 0; t < F::NT; ++t)
+    if (term[t].coef != F::term[t].coef || term[t].nf != F::term[t].nf ||
+        !std::equal(term[t].idx, term[t].idx + term[t].nf, F::term[t].idx))
+      return false;
+  return true;
+}
+
+using FixedLaunch = void (*)(const PatternLaunch&, const Amp&, double*, const double*, hipStream_t);
+using FixedMatch = bool (*)(const PatternLaunch&, const DTerm*);
+#define DCSD_FIXED_LAUNCH(P) &launch_fixed<P>,
+#define DCSD_FIXED_MATCH(P) &fixed_matches<P>,
+const FixedLaunch kFixedLaunch[] = {DCSD_FIXED_PATTERNS(DCSD_FIXED_LAUNCH)};
+const FixedMatch kFixedMatch[] = {DCSD_FIXED_PATTERNS(DCSD_FIXED_MATCH)};
+#undef DCSD_FIXED_LAUNCH
+#undef DCSD_FIXED_MATCH
+
 }  // namespace
 
-namespace {
-void add_patterns(std::vector<PatternLaunch>& pls, std::vector<DTerm>& all, int nc, int nv) {
-  const int v = nv + 1;
-  (void)v;
-  auto choices_occ = [&](int spin, int slot) {
-    std::vector<std::pair<Lo, int>> c;
-    if (nc > 0) c.push_back({{spin, CORE, slot}, nc});
-    c.push_back({{spin, spin == 0 ? KT : KU, -1}, 1});
-    return c;
-  };
-  auto choices_vir = [&](int spin, int slot) {
-    std::vector<std::pair<Lo, int>> c;
-    c.push_back({{spin, VIRT, slot}, nv});
-    c.push_back({{spin, spin == 0 ? KU : KT, -1}, 1});
-    return c;
-  };
-  auto emit = [&](int block, const std::vector<Lo>& h, const std::vector<Lo>& p, const int cnt[4]) {
-    PatternLaunch pl{};
-    pl.block = block;
-    pl.kind[0] = h[0].kind;
-    pl.kind[2] = p[0].kind;
-    pl.kind[1] = h.size() > 1 ? h[1].kind : CORE;
-    pl.kind[3] = p.size() > 1 ? p[1].kind : CORE;
-    for (int k = 0; k < 4; ++k) pl.cnt[k] = cnt[k];
-    pl.term_off = (int)all.size();
-    for (const HTerm& t : expand_pattern(h, p)) {
-      if (t.coef == 0.0) continue;
-      DTerm d{};
-      d.coef = t.coef;
-      d.nf = (int)t.f.size();
-      if (d.nf > MAXF) throw std::runtime_error("coupling: too many factors");
-      for (int q = 0; q < d.nf; ++q) d.f[q] = t.f[q];
-      all.push_back(d);
-    }
-    pl.nterms = (int)all.size() - pl.term_off;
-    pls.push_back(pl);
-  };
-  // singles
-  for (int spin = 0; spin < 2; ++spin)
-    for (auto& oc : choices_occ(spin, 0))
-      for (auto& vc : choices_vir(spin, 2)) {
-        const int cnt[4] = {oc.second, 1, vc.second, 1};
-        emit(spin, {oc.first}, {vc.first}, cnt);
-      }
-  // doubles; equal spins: i < j and a < b (t is the last alpha-occupied, u the first alpha-virtual, etc.)
-  for (int blk = 2; blk < 5; ++blk) {
-    const int s1 = blk == 3 ? 1 : 0, s2 = blk == 2 ? 0 : 1;
-    for (auto& oi : choices_occ(s1, 0))
-      for (auto& oj : choices_occ(s2, 1))
-        for (auto& va : choices_vir(s1, 2))
-          for (auto& vb : choices_vir(s2, 3)) {
-            if (blk < 4) {
-              // equal spins: keep ordered pairs only (core < t, u-type virtual < virt)
-              if (oi.first.kind != CORE && oj.first.kind != CORE) continue;  // t, t
-              if (oi.first.kind != CORE && oj.first.kind == CORE) continue;  // (t, core): covered by (core, t)
-              if (va.first.kind != VIRT && vb.first.kind != VIRT) continue;  // u, u
-              if (va.first.kind == VIRT && vb.first.kind != VIRT) continue;  // (virt, u): covered by (u, virt)
-            } else if (oi.first.kind != CORE && oj.first.kind != CORE && va.first.kind != VIRT &&
-                       vb.first.kind != VIRT) {
-              continue;  // the Phi_A -> Phi_B double (handled separately)
-            }
-            const int cnt[4] = {oi.second, oj.second, va.second, vb.second};
-            emit(blk, {oi.first, oj.first}, {va.first, vb.first}, cnt);
-          }
-  }
-}
-}  // namespace
 
 void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vector<char>& term_blob) {
   std::vector<PatternLaunch> pls;
   std::vector<DTerm> all;
   add_patterns(pls, all, nc, nv);
+  // each pattern's compile-time table must be the fixed form of the terms expanded here
+  for (PatternLaunch& pl : pls) {
+    pl.fixed = -1;
+    for (int p = 0; p < kFixedPatterns && pl.fixed < 0; ++p)
+      if (kFixedMatch[p](pl, all.data())) pl.fixed = p;
+    if (pl.fixed < 0) throw std::runtime_error("coupling: no compile-time table matches a pattern");
+  }
   launch_blob.assign((const char*)pls.data(), (const char*)(pls.data() + pls.size()));
   term_blob.assign((const char*)all.data(), (const char*)(all.data() + all.size()));
 }
@@ -546,16 +325,13 @@ void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, c
   A.t2[0] = T + 2 * ov;
   A.t2[1] = T + 2 * ov + s2;
   A.t2[2] = T + 2 * ov + 2 * s2;
+  (void)d_terms;  // the forward pass uses the compile-time tables
   const PatternLaunch* pls = (const PatternLaunch*)launch_blob.data();
   const size_t np = launch_blob.size() / sizeof(PatternLaunch);
-  const DTerm* terms = (const DTerm*)d_terms;
   for (size_t k = 0; k < np; ++k) {
     const PatternLaunch& pl = pls[k];
-    const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
-    if (tot == 0 || pl.nterms == 0) continue;
-    const int threads = 256;
-    hipLaunchKernelGGL(coupling_pattern, dim3((unsigned)((tot + threads - 1) / threads)), dim3(threads), 0, s,
-                       terms + pl.term_off, pl.nterms, pl, A, R, W_dev);
+    if (pl.fixed < 0 || pl.fixed >= kFixedPatterns) throw std::runtime_error("coupling: pattern without a table");
+    kFixedLaunch[pl.fixed](pl, A, R, W_dev, s);
     DCSD_CHECK_LAUNCH();
   }
 }
