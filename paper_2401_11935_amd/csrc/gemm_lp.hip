@@ -26,6 +26,7 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int NT = 256;
 constexpr int TILE = 128;
+__device__ __attribute__((aligned(16))) unsigned char lp_zero_row[64 * 16];  // zero source for rows past M, N, K
 
 enum { EPI_SPLIT = 0, EPI_PAIRS = 1, EPI_F64 = 2 };
 
@@ -94,6 +95,54 @@ struct Stage {
 };
 
 // BT x BT tile per workgroup of four waves, each a (BT/2) x (BT/2) sub-tile.
+// Pair-blocked epilogue: m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d] in the
+// storage precision.  The offset splits into a row part p*nq*kp + c*vu and a
+// column part q*kp + d, both stepped without divisions.  FP32 16 x 16
+// accumulators: element r of a lane is D[4*(lane/16) + r][lane%16]; mb and
+// nbase are this lane's first row and column.
+template <class T, int TM, int TN>
+__device__ inline void store_pairs(const LArgs& g, const f4 (&acc)[TM][TN], int64_t mb, int64_t nbase) {
+  const int vu = (int)g.vu;
+  int64_t coff[TN];
+  {
+    int q = (int)(nbase / vu), d = (int)(nbase % vu);
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      coff[j] = (int64_t)q * g.kp + d;
+      d += 16;
+      while (d >= vu) {
+        d -= vu;
+        ++q;
+      }
+    }
+  }
+  int p = (int)(mb / vu), c = (int)(mb % vu);
+  T* V = (T*)g.C;
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    int pr = p, cr = c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gm = mb + i * 16 + r;
+      if (gm < g.M) {
+        const int64_t roff = (int64_t)pr * g.nq * g.kp + (int64_t)cr * vu;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if (nbase + j * 16 < g.N) V[roff + coff[j]] = lp_round<T>(acc[i][j][r]);
+      }
+      if (++cr == vu) {
+        cr = 0;
+        ++pr;
+      }
+    }
+    c += 16;
+    while (c >= vu) {
+      c -= vu;
+      ++p;
+    }
+  }
+}
+
 template <class T, int EPI, bool SPLIT, int BT = 128>
 __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
   constexpr int VL = Traits<T>::VL;
@@ -206,47 +255,7 @@ __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
   // FP32 16 x 16 accumulators: element r of a lane is D[4*(lane/16) + r][lane%16]
   const int64_t mb = m0 + wm * WM + 4 * lrow, nbase = n0 + wn * WN + lcol;
   if constexpr (EPI == EPI_PAIRS) {
-    // m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d]: the offset splits into a row part
-    // p*nq*kp + c*vu and a column part q*kp + d, both stepped without divisions
-    const int vu = (int)g.vu;
-    int64_t coff[TN];
-    {
-      int q = (int)(nbase / vu), d = (int)(nbase % vu);
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        coff[j] = (int64_t)q * g.kp + d;
-        d += 16;
-        while (d >= vu) {
-          d -= vu;
-          ++q;
-        }
-      }
-    }
-    int p = (int)(mb / vu), c = (int)(mb % vu);
-    T* V = (T*)g.C;
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      int pr = p, cr = c;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gm = mb + i * 16 + r;
-        if (gm < g.M) {
-          const int64_t roff = (int64_t)pr * g.nq * g.kp + (int64_t)cr * vu;
-#pragma unroll
-          for (int j = 0; j < TN; ++j)
-            if (nbase + j * 16 < g.N) V[roff + coff[j]] = lp_round<T>(acc[i][j][r]);
-        }
-        if (++cr == vu) {
-          cr = 0;
-          ++pr;
-        }
-      }
-      c += 16;
-      while (c >= vu) {
-        c -= vu;
-        ++p;
-      }
-    }
+    store_pairs<T, TM, TN>(g, acc, mb, nbase);
     return;
   }
 #pragma unroll
@@ -270,6 +279,141 @@ __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
           C[off] = out;
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// Direct-to-LDS pair assembly (the ladder integral batches in FP32 or BF16).
+// Both operands are K-contiguous rows; one LDS stage holds 128 bytes of K
+// (32 FP32 or 64 BF16 elements) for the 128 rows of each operand tile, loaded
+// straight from global memory (global_load_lds_dwordx4, 8 rows of 128 bytes
+// per wave instruction).  Each lane fetches the 16-byte chunk that lands in
+// its slot under slot = chunk ^ ((row >> 1) & 7), so that the 16 rows of a
+// fragment read fall on distinct LDS banks.  A ring of S stages: a step waits
+// for its own stage (S - 2 younger ones stay in flight), crosses a bare
+// barrier, reads all its fragments with LDS reads that wait for their own
+// results inside the asm block, issues the step S - 1 ahead, and runs its
+// MFMAs.  Every fragment read brings 16 bytes of K per lane: BF16 feeds one
+// 16x16x32 MFMA with it; FP32 feeds four 16x16x4 MFMAs, lane group g holding
+// k = 16 b + 4 g + s in step s of block b (A and B use the same assignment).
+// Requires K to be a multiple of the elements per 16 bytes, 16-byte aligned
+// operands and leading dimensions that are multiples of 8 elements.
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+// stages and 16-byte chunks per row and stage: BF16 two stages of 128-byte rows, FP32 three
+// of 64-byte rows (measured at the 12864 x 12864 x 1200 ladder batches)
+template <class T>
+struct DlShape {
+  static constexpr int S = sizeof(T) == 2 ? 2 : 3, CPR = sizeof(T) == 2 ? 8 : 4;
+};
+
+__device__ inline uint32_t lds_byte_address(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+constexpr int waitcnt_vm(int vm) { return (vm & 0xF) | ((vm >> 4) << 14) | (7 << 4) | (0xF << 8); }
+
+template <class T, int S, int CPR>
+__global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
+  constexpr int VL = Traits<T>::VL;          // elements per 16-byte chunk
+  constexpr int RB = 16 * CPR;               // bytes of K per row and stage
+  constexpr int BK = CPR * VL;               // elements of K per stage
+  constexpr int H = CPR / 4;                 // fragment sub-steps per stage (4 chunks each)
+  constexpr int RPI = 64 / CPR;              // rows per wave instruction
+  constexpr int IPW = 128 / RPI / 4;         // instructions per operand per wave and stage
+  constexpr int WM = 64, WN = 64, TM = 4, TN = 4;
+  constexpr int STAGE = 128 * RB;            // bytes per operand per stage
+  static_assert(CPR == 4 || CPR == 8, "4 or 8 chunks per row");
+  __shared__ __attribute__((aligned(16))) unsigned char sA[S][STAGE];
+  __shared__ __attribute__((aligned(16))) unsigned char sB[S][STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t tm, tn;
+  tile_of(blockIdx.x, (g.M + 127) / 128, g.tiles_n, tm, tn);
+  const int64_t m0 = tm * 128, n0 = tn * 128;
+  const T* A = (const T*)g.A;
+  const T* B = (const T*)g.B;
+  const T* zrow = (const T*)lp_zero_row;
+  // swizzle of a row: 8 chunks use (row >> 1) & 7, 4 chunks (row >> 2) & 3
+  auto swz = [](int r) { return CPR == 8 ? (r >> 1) & 7 : (r >> 2) & 3; };
+  // wave instruction q covers rows RPI*q .. RPI*q + RPI-1; lane l takes row RPI*q + l/CPR
+  // and the chunk that lands in slot l % CPR
+  auto issue = [&](int slot, int64_t k0) {
+#pragma unroll
+    for (int qi = 0; qi < IPW; ++qi) {
+      const int q = wave * IPW + qi;
+      const int r = q * RPI + lane / CPR;
+      const int chunk = (lane % CPR) ^ swz(r);
+      const int64_t k = k0 + chunk * VL;
+      const T* sa = (m0 + r < g.M && k < g.K) ? A + (m0 + r) * g.lda + k : zrow;
+      const T* sb = (n0 + r < g.N && k < g.K) ? B + (n0 + r) * g.ldb + k : zrow;
+      const int dst = q * RPI * RB;
+      __builtin_amdgcn_global_load_lds((const void*)sa, (void __attribute__((address_space(3)))*)&sA[slot][dst], 16, 0,
+                                       0);
+      __builtin_amdgcn_global_load_lds((const void*)sb, (void __attribute__((address_space(3)))*)&sB[slot][dst], 16, 0,
+                                       0);
+    }
+  };
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  const int lrow = lane >> 4, lcol = lane & 15;
+  // byte offset of this lane's fragment for sub-step h (chunk 4h + lane/16) of row block 0;
+  // the swizzle of rows base + lcol depends on lcol only (the bases are multiples of 16), and
+  // the next 16 rows lie 16 * RB bytes on
+  uint32_t ao[H], bo[H];
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    ao[h] = (uint32_t)((wm * WM + lcol) * RB + (((4 * h + lrow) ^ swz(lcol)) * 16));
+    bo[h] = (uint32_t)((wn * WN + lcol) * RB + (((4 * h + lrow) ^ swz(lcol)) * 16));
+  }
+  const int64_t nk = (g.K + BK - 1) / BK;
+#pragma unroll
+  for (int t = 0; t < S - 1; ++t) issue(t, (int64_t)t * BK);
+  int slot = 0, fill = S - 1;  // stage read this step, stage refilled this step
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * IPW * (S - 2)));
+    __builtin_amdgcn_s_barrier();
+    const uint32_t sa = lds_byte_address(sA[slot]), sb = lds_byte_address(sB[slot]);
+    u4v af[H][TM], bf[H][TN];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+      const uint32_t pa = sa + ao[h], pb = sb + bo[h];
+      asm volatile(
+          "ds_read_b128 %0, %8\n"
+          "ds_read_b128 %1, %8 offset:%10\n"
+          "ds_read_b128 %2, %8 offset:%11\n"
+          "ds_read_b128 %3, %8 offset:%12\n"
+          "ds_read_b128 %4, %9\n"
+          "ds_read_b128 %5, %9 offset:%10\n"
+          "ds_read_b128 %6, %9 offset:%11\n"
+          "ds_read_b128 %7, %9 offset:%12\n"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(af[h][0]), "=&v"(af[h][1]), "=&v"(af[h][2]), "=&v"(af[h][3]), "=&v"(bf[h][0]), "=&v"(bf[h][1]),
+            "=&v"(bf[h][2]), "=&v"(bf[h][3])
+          : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB)
+          : "memory");
+    }
+    issue(fill, (kt + S - 1) * BK);  // past K: zero rows
+    slot = slot + 1 == S ? 0 : slot + 1;
+    fill = fill + 1 == S ? 0 : fill + 1;
+#pragma unroll
+    for (int h = 0; h < H; ++h)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          if constexpr (VL == 8) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af[h][i]),
+                                                                __builtin_bit_cast(bf8, bf[h][j]), acc[i][j], 0, 0, 0);
+          } else {
+            const f4 a = __builtin_bit_cast(f4, af[h][i]), b = __builtin_bit_cast(f4, bf[h][j]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc[i][j], 0, 0, 0);
+          }
+        }
+  }
+  __builtin_amdgcn_s_waitcnt(0);  // the last (zero) stages have landed before the wave retires
+  store_pairs<T, TM, TN>(g, acc, m0 + wm * WM + 4 * lrow, n0 + wn * WN + lcol);
 }
 
 // C(m,n) = alpha * sum_z W[z][m*N + n] + beta * C(m,n), summed in FP64 in z order.
@@ -374,7 +518,10 @@ void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_
   a.kchunk = naux;
   a.tiles_n = (a.N + BT - 1) / BT;
   const int64_t tiles = ((a.M + BT - 1) / BT) * a.tiles_n;
-  hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false, BT>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+  if (BT == 128 && naux % Traits<T>::VL == 0)
+    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false, BT>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();
 }
 

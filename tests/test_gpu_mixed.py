@@ -85,7 +85,10 @@ def test_lowp_gemm_within_fp32_summation_bound(precision, M, N, K):
         assert np.abs(C - A @ B).max() > 1e-12
 
 
-MIXED_SHAPES = [(2, 5, 13, "dcsd", 0), (3, 7, 11, "ccsd", 5), (5, 40, 37, "dcsd", 16), (6, 33, 70, "ccsd", 0)]
+# naux a multiple of 8 takes the direct-to-LDS pair assembly (K in whole 16-byte chunks);
+# the others take the register-staged kernel
+MIXED_SHAPES = [(2, 5, 13, "dcsd", 0), (3, 7, 11, "ccsd", 5), (5, 40, 37, "dcsd", 16), (6, 33, 70, "ccsd", 0),
+                (4, 30, 48, "dcsd", 8), (5, 41, 64, "ccsd", 0)]
 BARS = {"fp32": 2e-6, "bf16": 1e-2}
 
 
