@@ -96,19 +96,24 @@ struct Stage {
 
 // BT x BT tile per workgroup of four waves, each a (BT/2) x (BT/2) sub-tile.
 // Pair-blocked epilogue: m = (p, c), n = (q, d) -> V2[(p*nq + q)][c][d] in the
-// storage precision.  The offset splits into a row part p*nq*kp + c*vu and a
-// column part q*kp + d, both stepped without divisions.  FP32 16 x 16
-// accumulators: element r of a lane is D[4*(lane/16) + r][lane%16]; mb and
-// nbase are this lane's first row and column.
+// storage precision (FP32 -> BF16 by the hardware conversion, nearest even).
+// FP32 16 x 16 accumulators: element r of a lane is D[4*(lane/16) + r][lane%16];
+// mb and nbase are this lane's first row and column.  The byte offset splits
+// into a row part (p*nq*kp + c*vu) and a column part (q*kp + d), both stepped
+// without divisions in 32 bits (the host bounds the block below 4 GiB), so that
+// every store is the uniform base plus one 32-bit offset.
 template <class T, int TM, int TN>
 __device__ inline void store_pairs(const LArgs& g, const f4 (&acc)[TM][TN], int64_t mb, int64_t nbase) {
+  constexpr uint32_t es = sizeof(T);
   const int vu = (int)g.vu;
-  int64_t coff[TN];
+  uint32_t coff[TN];
+  bool cok[TN];
   {
     int q = (int)(nbase / vu), d = (int)(nbase % vu);
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-      coff[j] = (int64_t)q * g.kp + d;
+      coff[j] = ((uint32_t)q * (uint32_t)g.kp + (uint32_t)d) * es;
+      cok[j] = nbase + 16 * j < g.N;
       d += 16;
       while (d >= vu) {
         d -= vu;
@@ -116,29 +121,25 @@ __device__ inline void store_pairs(const LArgs& g, const f4 (&acc)[TM][TN], int6
       }
     }
   }
+  const uint32_t pstep = (uint32_t)(g.nq * g.kp) * es, cstep = (uint32_t)vu * es;
   int p = (int)(mb / vu), c = (int)(mb % vu);
-  T* V = (T*)g.C;
+  char* V = (char*)g.C;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
-    int pr = p, cr = c;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t gm = mb + i * 16 + r;
-      if (gm < g.M) {
-        const int64_t roff = (int64_t)pr * g.nq * g.kp + (int64_t)cr * vu;
+      // row mb + 16 i + r: (p, c) advanced by one row from the previous r, by 13 across i
+      if (mb + 16 * i + r < g.M) {
+        const uint32_t ro = (uint32_t)p * pstep + (uint32_t)c * cstep;
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          if (nbase + j * 16 < g.N) V[roff + coff[j]] = lp_round<T>(acc[i][j][r]);
+          if (cok[j]) *(T*)(V + (ro + coff[j])) = (T)acc[i][j][r];
       }
-      if (++cr == vu) {
-        cr = 0;
-        ++pr;
+      c += r == 3 ? 13 : 1;
+      while (c >= vu) {
+        c -= vu;
+        ++p;
       }
-    }
-    c += 16;
-    while (c >= vu) {
-      c -= vu;
-      ++p;
     }
   }
 }
@@ -559,6 +560,8 @@ void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t
   if (ldk % 8 || kp % 8) throw ArgError("low-precision ladder: bad leading dimension");
   if ((p0 + np) * vu * ldk >= ((int64_t)1 << 31) || (q0 + nq) * vu * ldk >= ((int64_t)1 << 31))
     throw ArgError("low-precision ladder: factor too large for 32-bit offsets");
+  if (np * nq * kp * (int64_t)lp_size(precision) >= ((int64_t)1 << 32))
+    throw ArgError("low-precision ladder: integral block too large for 32-bit offsets");
   if (precision == DCSD_PREC_BF16)
     launch_pairs<__bf16, 128>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
   else
