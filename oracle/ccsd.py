@@ -72,6 +72,27 @@ class SlabSource:
         return out
 
 
+def ladder_element(B: np.ndarray, nc: int, t2_block: np.ndarray, block: int, i: int, j: int, a: int, b: int) -> float:
+    """One element of the particle-particle ladder sum_ef t_ij^ef <ab|ef> of the
+    doubles residual (Theory section, doubles equations; tau = t2 when the
+    singles vanish), written out for a single (i, j, a, b) of a packed doubles
+    block (0 alpha-alpha, 1 beta-beta, 2 alpha-beta, indices in the per-spin
+    orders alpha-vir = [u, virt], beta-vir = [t, virt]).  With e of a's spin and
+    f of b's spin, <ab|ef> = (ae|bf) and (pq|rs) = sum_P B[P,p,q] B[P,r,s].
+    For checking sampled elements at sizes where the full residual is too costly.
+
+    Pinned by: every element against the slab-batched ladder of the full
+    residual on small systems (tests/test_oracle_ladder_element.py).
+    """
+    n = B.shape[1]
+    virt = np.arange(nc + 2, n)
+    vir = (np.concatenate([[nc + 1], virt]), np.concatenate([[nc], virt]))  # alpha, beta
+    sa, sb = ((0, 0), (1, 1), (0, 1))[block]
+    E, Fv = vir[sa], vir[sb]
+    I = B[:, E[a], E].T @ B[:, Fv[b], Fv]  # [e, f] = (a e | b f)
+    return float(np.sum(I * t2_block[i, j]))
+
+
 def integrals(ham: Hamiltonian) -> dict:
     O, V = ham.O, ham.V
     return {

@@ -253,6 +253,49 @@ def test_medium_residual_matches_oracle_samples():
         assert abs(float(np.dot(R, R)) - g["res_norm2"]) <= 1e-9 * g["res_norm2"]
 
 
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("cfg", [synth.MIXED, synth.LARGEST], ids=lambda c: c.name)
+def test_full_size_ladder_samples(cfg):
+    """The particle-particle ladder alone (term mask), singles zero, at the metric
+    (12, 400, 1200) and the largest (20, 600, 1800) sizes with the bench's
+    launch configuration: 16 seeded elements per doubles block against the
+    oracle's single-element ladder (bar 1e-9); the largest size also with BF16
+    ladder GEMMs (bar 1e-2 of the sampled magnitude)."""
+    from oracle.ccsd import ladder_element
+    from gpu_util import GpuProblem
+    say("full-size ladder samples", cfg.name, "inputs")
+    B, F = synth.make_config_inputs(cfg)
+    say("full-size ladder samples", cfg.name, "amplitudes")
+    T = synth.random_amplitudes(cfg.nc, cfg.nv, cfg.seed + 11, 0.05)
+    blocks = synth.unpack(T, cfg.nc, cfg.nv)
+    blocks["t1a"][:] = 0.0
+    blocks["t1b"][:] = 0.0
+    o, v = cfg.nc + 1, cfg.nv + 1
+    rng = np.random.default_rng(cfg.seed + 13)
+    samples = []
+    for blk, name in enumerate(("t2aa", "t2bb", "t2ab")):
+        while sum(1 for s_ in samples if s_[1] == name) < 16:
+            i, j, a, b = (int(x) for x in rng.integers(0, (o, o, v, v)))
+            if (blk < 2 and (i == j or a == b)) or (blk == 2 and (i, j, a, b) == (cfg.nc, cfg.nc, 0, 0)):
+                continue
+            samples.append((blk, name, i, j, a, b))
+    say("full-size ladder samples", cfg.name, "oracle elements")
+    ref = np.array([ladder_element(B, cfg.nc, blocks[name], blk, i, j, a, b) for blk, name, i, j, a, b in samples])
+    precisions = ["fp64", "bf16"] if cfg.name == "largest" else ["fp64"]
+    for prec in precisions:
+        say("full-size ladder samples", cfg.name, prec, "residual")
+        p = GpuProblem(B, F, cfg.nc, "dcsd", precision=prec, term_mask=1 << 3)
+        R, _ = p.residual(T)
+        p.close()
+        Rb = synth.unpack(R, cfg.nc, cfg.nv)
+        got = np.array([Rb[name][i, j, a, b] for _, name, i, j, a, b in samples])
+        err = float(np.abs(got - ref).max())
+        scale = max(1.0, float(np.abs(ref).max()))
+        bar = 1e-9 if prec == "fp64" else 1e-2 * scale
+        say(f"  {prec}: sampled max|dR| = {err:.3e} (bar {bar:.1e}), max|R| sampled {np.abs(ref).max():.3e}")
+        assert err <= bar
+
+
 def test_internal_amplitude_ignored_on_input():
     from gpu_util import GpuProblem
     nc, nv, naux = 2, 5, 13
