@@ -224,71 +224,115 @@ __device__ inline double wave_sum(double v) {
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
   return v;
 }
-// Every lane of a wave runs the same term loop (lanes past the end or outside
-// the i < j, a < b half contribute zero), so that factors whose cotangent
-// address is the same in all 64 lanes - every factor that does not depend on
-// the fastest grid index, e.g. amplitudes with only t/u indices, which all
-// elements of a pattern share - are summed in the wave first and added with
-// one atomic instead of 64.
-__global__ void coupling_pattern_adj(const DTerm* __restrict__ terms, int nterms, PatternLaunch pl, Amp A,
-                                     double* Tbar, const double* __restrict__ Rbar, const double* __restrict__ Wp,
-                                     double* Wbar) {
-  const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
+// Adjoint of one pattern with its compile-time table.  Every lane of a wave runs
+// the same code (lanes past the end contribute zero), so that a factor whose
+// cotangent address is the same in all 64 lanes - every factor that does not
+// depend on the indices that vary within the wave, e.g. amplitudes with only
+// t/u indices, which all elements of a pattern share - is summed in the wave
+// first and added with one atomic instead of 64.  Each distinct factor gets one
+// cotangent per element: dK/dfactor summed over the terms that contain it.
+template <int P>
+__global__ __launch_bounds__(256) void coupling_fixed_adj(PatternLaunch pl, Amp A, double* Tbar,
+                                                          const double* __restrict__ Rbar,
+                                                          const double* __restrict__ Wp, double* Wbar) {
+  using F = Fixed<P>;
+  constexpr bool same = F::block == 2 || F::block == 3;
+  constexpr bool tri_ij = same && F::kind[0] == CORE && F::kind[1] == CORE;
+  constexpr bool tri_ab = same && F::kind[2] == VIRT && F::kind[3] == VIRT;
+  int64_t nij, nab;
+  pair_counts<F>(pl, nij, nab);
+  const int64_t tot = nij * nab;
   const int64_t id0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const bool inrange = id0 < tot;
-  int64_t r = inrange ? id0 : tot - 1;
-  const int bb = (int)(r % pl.cnt[3]); r /= pl.cnt[3];
-  const int aa = (int)(r % pl.cnt[2]); r /= pl.cnt[2];
-  const int jj = (int)(r % pl.cnt[1]);
-  const int ii = (int)(r / pl.cnt[1]);
-  const bool same = pl.block == 2 || pl.block == 3;
-  const bool skip = (same && pl.kind[0] == CORE && pl.kind[1] == CORE && ii >= jj) ||
-                    (same && pl.kind[2] == VIRT && pl.kind[3] == VIRT && aa >= bb);
+  const int64_t id = inrange ? id0 : tot - 1;
+  const int64_t pij = id / nab, pab = id % nab;
+  int ii, jj, aa, bb;
+  if (tri_ij) {
+    tri_pair(pij, pl.cnt[0], ii, jj);
+  } else {
+    ii = (int)(pij / pl.cnt[1]);
+    jj = (int)(pij % pl.cnt[1]);
+  }
+  if (tri_ab) {
+    tri_pair(pab, pl.cnt[2], aa, bb);
+  } else {
+    aa = (int)(pab / pl.cnt[3]);
+    bb = (int)(pab % pl.cnt[3]);
+  }
   const int nc = A.nc, o = A.o, v = A.v;
   const int64_t ov = (int64_t)o * v, s2 = ov * ov;
   double rb = 0.0;
-  if (inrange && !skip) {
-    const int i = occ_pos(pl.kind[0], ii, nc), a = vir_pos(pl.kind[2], aa);
-    if (pl.block < 2) {
-      rb = Rbar[pl.block * ov + (int64_t)i * v + a];
+  if (inrange) {
+    const int i = occ_pos(F::kind[0], ii, nc), a = vir_pos(F::kind[2], aa);
+    if (F::block < 2) {
+      rb = Rbar[F::block * ov + (int64_t)i * v + a];
     } else {
-      const int j = occ_pos(pl.kind[1], jj, nc), b = vir_pos(pl.kind[3], bb);
-      const double* Rb = Rbar + 2 * ov + (int64_t)(pl.block - 2) * s2;
+      const int j = occ_pos(F::kind[1], jj, nc), b = vir_pos(F::kind[3], bb);
+      const double* Rb = Rbar + 2 * ov + (int64_t)(F::block - 2) * s2;
       auto at = [&](int p, int q, int c, int d) { return Rb[(((int64_t)p * o + q) * v + c) * v + d]; };
       rb = at(i, j, a, b);
       if (same) rb += -at(j, i, a, b) - at(i, j, b, a) + at(j, i, b, a);
     }
   }
   const double g = -(*Wp) * rb;  // cotangent of K_x
+  double fv[F::ND], dfv[F::ND];
+#pragma unroll
+  for (int f = 0; f < F::ND; ++f) {
+    fv[f] = factor(A, F::fac[f], ii, jj, aa, bb);
+    dfv[f] = 0.0;
+  }
   double K = 0.0;
-  double* bars[5] = {Tbar, Tbar + ov, Tbar + 2 * ov, Tbar + 2 * ov + s2, Tbar + 2 * ov + 2 * s2};
-  for (int t = 0; t < nterms; ++t) {
-    const DTerm& T = terms[t];
-    double fv[MAXF];
-    for (int q = 0; q < T.nf; ++q) fv[q] = factor(A, T.f[q], ii, jj, aa, bb);
-    double prod = T.coef;
-    for (int q = 0; q < T.nf; ++q) prod *= fv[q];
+#pragma unroll
+  for (int t = 0; t < F::NT; ++t) {
+    double prod = F::term[t].coef;
+#pragma unroll
+    for (int q = 0; q < MAXF; ++q)
+      if (q < F::term[t].nf) prod *= fv[F::term[t].idx[q]];
     K += prod;
-    for (int q = 0; q < T.nf; ++q) {
-      double part = T.coef;
-      for (int q2 = 0; q2 < T.nf; ++q2)
-        if (q2 != q) part *= fv[q2];
-      int arr;
-      const int64_t off = factor_off(A, T.f[q], ii, jj, aa, bb, arr);
-      const double val = g * part;
-      const long long key = ((long long)arr << 40) | (long long)off;
-      const long long k0 = __shfl(key, 0);
-      if (__all(key == k0)) {
-        const double sum = wave_sum(val);
-        if (__lane_id() == 0 && sum != 0.0) atomicAdd(bars[arr] + off, sum);
-      } else if (val != 0.0) {
-        atomicAdd(bars[arr] + off, val);
-      }
+#pragma unroll
+    for (int q = 0; q < MAXF; ++q) {
+      if (q >= F::term[t].nf) continue;
+      double part = F::term[t].coef;
+#pragma unroll
+      for (int q2 = 0; q2 < MAXF; ++q2)
+        if (q2 < F::term[t].nf && q2 != q) part *= fv[F::term[t].idx[q2]];
+      dfv[F::term[t].idx[q]] += part;
+    }
+  }
+  double* bars[5] = {Tbar, Tbar + ov, Tbar + 2 * ov, Tbar + 2 * ov + s2, Tbar + 2 * ov + 2 * s2};
+#pragma unroll
+  for (int f = 0; f < F::ND; ++f) {
+    int arr;
+    const int64_t off = factor_off(A, F::fac[f], ii, jj, aa, bb, arr);
+    const double val = g * dfv[f];
+    const long long key = ((long long)arr << 40) | (long long)off;
+    const long long k0 = __shfl(key, 0);
+    if (__all(key == k0)) {
+      const double sum = wave_sum(val);
+      if (__lane_id() == 0 && sum != 0.0) atomicAdd(bars[arr] + off, sum);
+    } else if (val != 0.0) {
+      atomicAdd(bars[arr] + off, val);
     }
   }
   const double w = wave_sum(-K * rb);
   if (__lane_id() == 0 && w != 0.0) atomicAdd(Wbar, w);
 }
+
+template <int P>
+void launch_fixed_adj(const PatternLaunch& pl, const Amp& A, double* Tbar, const double* Rbar, const double* Wp,
+                      double* Wbar, hipStream_t s) {
+  int64_t nij, nab;
+  pair_counts<Fixed<P>>(pl, nij, nab);
+  const int64_t tot = nij * nab;
+  if (tot <= 0 || Fixed<P>::NT == 0) return;
+  hipLaunchKernelGGL(coupling_fixed_adj<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, pl, A, Tbar, Rbar,
+                     Wp, Wbar);
+}
+using FixedAdjLaunch = void (*)(const PatternLaunch&, const Amp&, double*, const double*, const double*, double*,
+                                hipStream_t);
+#define DCSD_FIXED_ADJ(P) &launch_fixed_adj<P>,
+const FixedAdjLaunch kFixedAdjLaunch[] = {DCSD_FIXED_PATTERNS(DCSD_FIXED_ADJ)};
+#undef DCSD_FIXED_ADJ
 
 void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* Tbar,
                         const double* Rbar, const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s) {
@@ -301,15 +345,13 @@ void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_term
   A.t2[0] = T + 2 * ov;
   A.t2[1] = T + 2 * ov + s2;
   A.t2[2] = T + 2 * ov + 2 * s2;
+  (void)d_terms;  // the compile-time tables hold the terms
   const PatternLaunch* pls = (const PatternLaunch*)launch_blob.data();
   const size_t np = launch_blob.size() / sizeof(PatternLaunch);
-  const DTerm* terms = (const DTerm*)d_terms;
   for (size_t k = 0; k < np; ++k) {
     const PatternLaunch& pl = pls[k];
-    const int64_t tot = (int64_t)pl.cnt[0] * pl.cnt[1] * pl.cnt[2] * pl.cnt[3];
-    if (tot == 0 || pl.nterms == 0) continue;
-    hipLaunchKernelGGL(coupling_pattern_adj, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                       terms + pl.term_off, pl.nterms, pl, A, Tbar, Rbar, W_dev, Wbar);
+    if (pl.fixed < 0 || pl.fixed >= kFixedPatterns) throw std::runtime_error("coupling: pattern without a table");
+    kFixedAdjLaunch[pl.fixed](pl, A, Tbar, Rbar, W_dev, Wbar, s);
     DCSD_CHECK_LAUNCH();
   }
 }
