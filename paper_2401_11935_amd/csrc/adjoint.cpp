@@ -399,8 +399,7 @@ void Ctx::adjoint_op(const TapeOp& op, bool params) {
       break;
     }
     case OP_COUPLING:
-      coupling_apply_adj(coup_launch, coup_terms, op.val[0], bar(op.src), bar(op.dst), op.val[1], bar(op.src2), nc,
-                         nv, s);
+      coupling_apply_adj(coup_launch, op.val[0], bar(op.src), bar(op.dst), op.val[1], bar(op.src2), nc, nv, s);
       break;
     case OP_ENERGY:
       energy_adj(bar(op.src), params ? bar(Isc) : nullptr, params ? bar(f[0]) : nullptr,

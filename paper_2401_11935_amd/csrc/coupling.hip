@@ -188,7 +188,7 @@ const FixedMatch kFixedMatch[] = {DCSD_FIXED_PATTERNS(DCSD_FIXED_MATCH)};
 }  // namespace
 
 
-void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vector<char>& term_blob) {
+void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob) {
   std::vector<PatternLaunch> pls;
   std::vector<DTerm> all;
   add_patterns(pls, all, nc, nv);
@@ -200,7 +200,6 @@ void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vecto
     if (pl.fixed < 0) throw std::runtime_error("coupling: no compile-time table matches a pattern");
   }
   launch_blob.assign((const char*)pls.data(), (const char*)(pls.data() + pls.size()));
-  term_blob.assign((const char*)all.data(), (const char*)(all.data() + all.size()));
 }
 
 // Adjoint of one pattern: with rb the cotangent of -K_x W gathered over the
@@ -334,8 +333,8 @@ using FixedAdjLaunch = void (*)(const PatternLaunch&, const Amp&, double*, const
 const FixedAdjLaunch kFixedAdjLaunch[] = {DCSD_FIXED_PATTERNS(DCSD_FIXED_ADJ)};
 #undef DCSD_FIXED_ADJ
 
-void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* Tbar,
-                        const double* Rbar, const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s) {
+void coupling_apply_adj(const std::vector<char>& launch_blob, const double* T, double* Tbar, const double* Rbar,
+                        const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s) {
   Amp A;
   const int o = nc + 1, v = nv + 1;
   const int64_t ov = (int64_t)o * v, s2 = ov * ov;
@@ -345,7 +344,6 @@ void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_term
   A.t2[0] = T + 2 * ov;
   A.t2[1] = T + 2 * ov + s2;
   A.t2[2] = T + 2 * ov + 2 * s2;
-  (void)d_terms;  // the compile-time tables hold the terms
   const PatternLaunch* pls = (const PatternLaunch*)launch_blob.data();
   const size_t np = launch_blob.size() / sizeof(PatternLaunch);
   for (size_t k = 0; k < np; ++k) {
@@ -356,8 +354,8 @@ void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_term
   }
 }
 
-void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* R,
-                    const double* W_dev, int nc, int nv, hipStream_t s) {
+void coupling_apply(const std::vector<char>& launch_blob, const double* T, double* R, const double* W_dev, int nc,
+                    int nv, hipStream_t s) {
   Amp A;
   const int o = nc + 1, v = nv + 1;
   const int64_t ov = (int64_t)o * v, s2 = ov * ov;
@@ -367,7 +365,6 @@ void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, c
   A.t2[0] = T + 2 * ov;
   A.t2[1] = T + 2 * ov + s2;
   A.t2[2] = T + 2 * ov + 2 * s2;
-  (void)d_terms;  // the forward pass uses the compile-time tables
   const PatternLaunch* pls = (const PatternLaunch*)launch_blob.data();
   const size_t np = launch_blob.size() / sizeof(PatternLaunch);
   for (size_t k = 0; k < np; ++k) {

@@ -48,7 +48,6 @@ struct Ctx {
   double* QY1[2] = {nullptr, nullptr}, *QY2[2] = {nullptr, nullptr};
   double* Ikl[3] = {nullptr, nullptr, nullptr};  // aa, bb, ab: [(k,l),(c,d)]
   std::vector<char> coup_launch;       // coupling pattern launches (host)
-  double* coup_terms = nullptr;        // coupling term tables (device)
   int* pair_i = nullptr;
   int* pair_j = nullptr;
   double e_ref = 0.0;

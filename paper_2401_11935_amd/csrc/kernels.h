@@ -26,11 +26,11 @@ void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, cons
                        int64_t npair, int n, int nc, int o, int v, hipStream_t s);
 
 // Coupling between the two determinants: R -= K(T) * W (the caller sets R at the A->B double to 0).
-// coupling_prepare expands the per-pattern term tables on the host (once);
-// the term blob is copied to device memory and passed to coupling_apply.
-void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob, std::vector<char>& term_blob);
-void coupling_apply(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* R,
-                    const double* W_dev, int nc, int nv, hipStream_t s);
+// coupling_prepare lists the patterns of the problem's sizes and checks each against its
+// compile-time term table (once); coupling_apply launches them.
+void coupling_prepare(int nc, int nv, std::vector<char>& launch_blob);
+void coupling_apply(const std::vector<char>& launch_blob, const double* T, double* R, const double* W_dev, int nc,
+                    int nv, hipStream_t s);
 
 // ---- adjoints (accumulate into the cotangents of the inputs) -------------------------
 void swap_tu_adj(double* src_bar, const double* dst_bar, int64_t batch, int n, int nc, hipStream_t s);
@@ -49,8 +49,8 @@ void ladder_mtransform_adj(double* Rpbar, double* t1bar, const double* R2aa_bar,
                            const double* R2ab_bar, const double* Rp, const double* t1a, const double* t1b,
                            const int* pair_i, const int* pair_j, int64_t rows, int64_t o2, int64_t npair, int n,
                            int nc, int o, int v, double* VB, double* S, double* Sbar, hipStream_t s);
-void coupling_apply_adj(const std::vector<char>& launch_blob, const void* d_terms, const double* T, double* Tbar,
-                        const double* Rbar, const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s);
+void coupling_apply_adj(const std::vector<char>& launch_blob, const double* T, double* Tbar, const double* Rbar,
+                        const double* W_dev, double* Wbar, int nc, int nv, hipStream_t s);
 // dst = src with the equal-spin doubles blocks antisymmetrised (dst != src)
 void antisym_copy(double* dst, const double* src, int o, int v, hipStream_t s);
 // out[P][p][q] = (in[P][p][q] + in[P][q][p]) / 2 for batch n x n matrices (out != in)

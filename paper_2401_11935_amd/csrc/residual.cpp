@@ -370,16 +370,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     }
   }
 
-  // ---- coupling term tables (host expansion, one upload) ------------------------
-  {
-    std::vector<char> blob;
-    coupling_prepare(nc, nv, coup_launch, blob);
-    coup_terms = alloc(((int64_t)blob.size() + 7) / 8);
-    if (!blob.empty()) {
-      DCSD_HIP(hipMemcpyAsync(coup_terms, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
-      DCSD_HIP(hipStreamSynchronize(s));
-    }
-  }
+  // ---- coupling patterns (checked against their compile-time tables) -----------
+  coupling_prepare(nc, nv, coup_launch);
   // external inputs take part in the adjoint's buffer registry (not owned)
   reg(const_cast<double*>(B), NA * n2, false);
   reg(const_cast<double*>(F), n2, false);
@@ -774,7 +766,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
       op.val[1] = tape_value(scal, 1);
       tape_op(op);
     }
-    coupling_apply(coup_launch, coup_terms, Tw, R, scal, nc, nv, s);
+    coupling_apply(coup_launch, Tw, R, scal, nc, nv, s);
   }
   // the Phi_A -> Phi_B double: its residual is W itself and is not solved for
   rfill(R + ab_pos, 0.0, 1, s);
