@@ -108,7 +108,8 @@ def flop_model(nc, nv, naux, lb):
     o2, npair = o * o, o * (o - 1) // 2
     for i, a in enumerate(nb):
         for j, b in enumerate(nb[i:]):
-            asm += 2.0 * a * vu * b * vu * naux
+            pairs = a * (a + 1) / 2 if j == 0 else a * b  # distinct pairs of a diagonal batch
+            asm += 2.0 * pairs * vu * vu * naux
             rows = o2 + 2 * npair + (0 if j == 0 else o2)
             con += 2.0 * rows * a * b * vu * vu
     ov = o * v

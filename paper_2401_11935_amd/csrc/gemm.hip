@@ -31,6 +31,7 @@ struct KArgs {
   int64_t tiles_n;
   int64_t split_stride;  // element stride between split partial outputs
   int64_t vu, nq;        // pair-blocked output (EPI = 1)
+  int64_t skip_lower;    // EPI = 1, diagonal batch: skip tiles whose pairs all have p > q
 };
 
 template <int BM, int BN, bool A_MC, bool B_NC, bool C_NC, bool SPLIT, int EPI = 0>
@@ -57,7 +58,12 @@ __global__ __launch_bounds__(NT) void gemm_kernel(KArgs g) {
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
-  tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+  if (EPI == 1 && g.skip_lower) {
+    if (!diag_tile(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, g.N, g.vu, BM, BN, tm, tn))
+      return;  // whole workgroup, before any barrier
+  } else {
+    tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+  }
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t batch = blockIdx.y;
   const double* A = g.A + batch * g.sA;
@@ -311,7 +317,12 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
   const int wm = wave / DL_WGN, wn = wave % DL_WGN;
   int64_t tm, tn;
   const int64_t z = blockIdx.z;
-  tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+  if (EPI == 1 && g.skip_lower) {
+    if (!diag_tile(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, g.N, g.vu, BM, BN, tm, tn))
+      return;  // whole workgroup, before any barrier
+  } else {
+    tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+  }
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t batch = blockIdx.y;
   int64_t kbeg = 0, kend = g.K;
@@ -580,14 +591,24 @@ void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int6
   k.B = Bl + q0 * vu; k.ldb = ld;
   k.C = V2; k.ldc = 0; k.alpha = 1.0; k.beta = 0.0;
   k.kchunk = naux; k.vu = vu; k.nq = nq;
+  // a diagonal batch is symmetric under (p, c) <-> (q, d): the tiles entirely in p > q are
+  // skipped and those pairs copied from their mirrors below
   const int64_t tm = (k.M + 127) / 128, tn = (k.N + 127) / 128;
   k.tiles_n = tn;
+  k.skip_lower = p0 == q0 && np == nq && np * (np - 1) / 2 <= 65535 && diag_skips(np, vu, 128, 128);
+  const int64_t grid = k.skip_lower ? diag_grid(tm, tn) : tm * tn;
   const bool al = (((uintptr_t)k.A | (uintptr_t)k.B) & 15) == 0;
   if (k.M % 2 == 0 && k.N % 2 == 0 && ld % 2 == 0 && al)
-    hipLaunchKernelGGL((gemm_dl_kernel<true, true, 1, false, true>), dim3((unsigned)(tm * tn)), dim3(DL_NT), 0, s, k);
+    hipLaunchKernelGGL((gemm_dl_kernel<true, true, 1, false, true>), dim3((unsigned)grid), dim3(DL_NT), 0, s, k);
   else
-    hipLaunchKernelGGL((gemm_kernel<128, 128, true, true, true, false, 1>), dim3((unsigned)(tm * tn)), dim3(NT), 0, s, k);
+    hipLaunchKernelGGL((gemm_kernel<128, 128, true, true, true, false, 1>), dim3((unsigned)grid), dim3(NT), 0, s, k);
   DCSD_CHECK_LAUNCH();
+  if (k.skip_lower) {
+    const int tiles = (int)((vu + 31) / 32);
+    hipLaunchKernelGGL(pair_mirror_kernel<double>, dim3((unsigned)(tiles * tiles), (unsigned)(np * (np - 1) / 2)), dim3(256), 0, s,
+                       V2, vu, vu * vu, np, tiles);
+    DCSD_CHECK_LAUNCH();
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -42,6 +42,7 @@ struct LArgs {
   double alpha, beta;
   int64_t kchunk, tiles_n, split_stride;
   int64_t vu, nq, kp;  // pair-blocked output
+  int64_t skip_lower;  // pair-blocked diagonal batch: skip tiles whose pairs all have p > q
 };
 
 template <class T>
@@ -161,7 +162,12 @@ __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
-  tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
+  if (EPI == EPI_PAIRS && g.skip_lower) {
+    if (!diag_tile(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, g.N, g.vu, BT, BT, tm, tn))
+      return;  // whole workgroup, before any barrier
+  } else {
+    tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
+  }
   const int64_t m0 = tm * BT, n0 = tn * BT;
   int64_t kbeg = 0, kend = g.K;
   if (SPLIT) {
@@ -327,7 +333,12 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
-  tile_of(blockIdx.x, (g.M + 127) / 128, g.tiles_n, tm, tn);
+  if (g.skip_lower) {
+    if (!diag_tile(blockIdx.x, (g.M + 127) / 128, g.tiles_n, g.N, g.vu, 128, 128, tm, tn))
+      return;  // whole workgroup, before any barrier
+  } else {
+    tile_of(blockIdx.x, (g.M + 127) / 128, g.tiles_n, tm, tn);
+  }
   const int64_t m0 = tm * 128, n0 = tn * 128;
   const T* A = (const T*)g.A;
   const T* B = (const T*)g.B;
@@ -518,12 +529,22 @@ void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_
   a.C = V2; a.vu = vu; a.nq = nq; a.kp = kp;
   a.kchunk = naux;
   a.tiles_n = (a.N + BT - 1) / BT;
-  const int64_t tiles = ((a.M + BT - 1) / BT) * a.tiles_n;
+  const int64_t tiles_m = (a.M + BT - 1) / BT;
+  // a diagonal batch is symmetric under (p, c) <-> (q, d): the tiles entirely in p > q are
+  // skipped and those pairs copied from their mirrors below
+  a.skip_lower = p0 == q0 && np == nq && np * (np - 1) / 2 <= 65535 && diag_skips(np, vu, BT, BT);
+  const int64_t tiles = a.skip_lower ? diag_grid(tiles_m, a.tiles_n) : tiles_m * a.tiles_n;
   if (BT == 128 && naux % Traits<T>::VL == 0)
     hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false, BT>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();
+  if (a.skip_lower) {
+    const int t = (int)((vu + 31) / 32);
+    hipLaunchKernelGGL(pair_mirror_kernel<T>, dim3((unsigned)(t * t), (unsigned)(np * (np - 1) / 2)), dim3(256), 0, s,
+                       (T*)V2, vu, kp, np, t);
+    DCSD_CHECK_LAUNCH();
+  }
 }
 
 void check_lp(const LpGemm& q) {

@@ -709,7 +709,9 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
           lp_pairs(prec_now, BlT, ldk, NA, vu, p0, np, q0, nq, kp, V2L, s);
         else
           gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
-        if (rec) tend(ev0, 2.0 * (double)np * vu * (double)nq * vu * (double)NA, 0);
+        // algorithmic flops: a diagonal batch needs its np (np + 1) / 2 distinct pairs
+        const double pairs = diag ? 0.5 * np * (np + 1.0) : (double)np * nq;
+        if (rec) tend(ev0, 2.0 * pairs * vu * (double)vu * (double)NA, 0);
         const int64_t M = diag ? rows_main : rows_all;
         const int64_t N = (int64_t)np * nq;
         const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
