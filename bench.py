@@ -28,35 +28,45 @@ HBM_PEAK_GBS = 8000.0
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic_ladder_assembly_fp64_nc12_nv400_naux1200.json")
 ASSEMBLY_KERNEL = "gemm_dl_kernel<true, true, 1, false, true>"
-ASSEMBLY_SOURCE = os.path.join(ROOT, "paper_2401_11935_amd", "csrc", "gemm.hip")
+ASSEMBLY_SOURCES = [os.path.join(ROOT, "paper_2401_11935_amd", "csrc", f) for f in ("gemm.hip", "tiles.h")]
+MIRROR_KERNEL = "pair_mirror_kernel<double>"
 
 
-def source_hash(path):
+def source_hash(paths):
+    """SHA-256 over the concatenated sources of the assembly kernel."""
     import hashlib
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
 
 
 def traffic_from_pmc(fetch_csv, write_csv, calib_mib, out_path):
     """Per-launch HBM traffic of the FP64 ladder assembly from rocprofv3
     FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each scaled by the factor that
     makes the calibration copy (the first copy kernel of calib_mib MiB) read
-    and write exactly its size."""
+    and write exactly its size.  The mirror copies that complete the diagonal
+    batches are part of the assembly (its live timing includes them), so their
+    bytes are spread over the assembly launches too."""
     import csv
 
     def per_kernel(path):
         rows = list(csv.DictReader(open(path)))
         copy = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
         asm = [float(r["Counter_Value"]) for r in rows if ASSEMBLY_KERNEL in r["Kernel_Name"]]
-        return copy[0], asm
-    cf, af = per_kernel(fetch_csv)
-    cw, aw = per_kernel(write_csv)
+        mirror = [float(r["Counter_Value"]) for r in rows if MIRROR_KERNEL in r["Kernel_Name"]]
+        return copy[0], asm, mirror
+    cf, af, mf = per_kernel(fetch_csv)
+    cw, aw, mw = per_kernel(write_csv)
     kib = calib_mib * 1024.0
     fs, ws = kib / cf, kib / cw
-    fetch = sum(af) / len(af) * fs * 1024.0
-    write = sum(aw) / len(aw) * ws * 1024.0
-    rec = {"kernel": ASSEMBLY_KERNEL, "source": os.path.relpath(ASSEMBLY_SOURCE, ROOT),
-           "source_sha256": source_hash(ASSEMBLY_SOURCE), "launches": len(af),
+    fetch = (sum(af) + sum(mf)) / len(af) * fs * 1024.0
+    write = (sum(aw) + sum(mw)) / len(aw) * ws * 1024.0
+    rec = {"kernel": ASSEMBLY_KERNEL, "sources": [os.path.relpath(p, ROOT) for p in ASSEMBLY_SOURCES],
+           "source_sha256": source_hash(ASSEMBLY_SOURCES), "launches": len(af), "mirror_launches": len(mf),
            "calibration_copy_mib": calib_mib, "fetch_scale": fs, "write_scale": ws,
+           "mirror_fetch_bytes_per_launch": sum(mf) / len(af) * fs * 1024.0,
+           "mirror_write_bytes_per_launch": sum(mw) / len(aw) * ws * 1024.0,
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write, "bytes_per_launch": fetch + write}
     json.dump(rec, open(out_path, "w"), indent=1)
     return rec
@@ -66,7 +76,7 @@ def load_traffic(path):
     if not path or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    if rec.get("source_sha256") != source_hash(ASSEMBLY_SOURCE):
+    if rec.get("source_sha256") != source_hash(ASSEMBLY_SOURCES):
         return None  # the kernel changed since the counters were taken
     return rec["bytes_per_launch"]
 
