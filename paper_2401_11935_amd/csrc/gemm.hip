@@ -368,9 +368,11 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
     __builtin_amdgcn_s_barrier();
     const int slot = (int)(kt & (S - 1));
     const uint32_t sa = lds_byte_address(sA[slot]), sb = lds_byte_address(sB[slot]);
-    double af[KS][TM], bf[KS][TN];
+    // each k sub-step's fragments are read just before its MFMAs, so that a wave's
+    // second read overlaps the MFMAs it has already issued
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
+      double af[TM], bf[TN];
       const uint32_t pa = sa + ao[ks], pb = sb + bo[ks];
       asm volatile(
           "ds_read_b64 %0, %6\n"
@@ -380,19 +382,16 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
           "ds_read_b64 %4, %7 offset:%10\n"
           "ds_read_b64 %5, %7 offset:%11\n"
           "s_waitcnt lgkmcnt(0)"
-          : "=&v"(af[ks][0]), "=&v"(af[ks][1]), "=&v"(bf[ks][0]), "=&v"(bf[ks][1]), "=&v"(bf[ks][2]),
-            "=&v"(bf[ks][3])
+          : "=&v"(af[0]), "=&v"(af[1]), "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3])
           : "v"(pa), "v"(pb), "n"(AI), "n"(BJ), "n"(2 * BJ), "n"(3 * BJ)
           : "memory");
-    }
-    issue((int)((kt + S - 1) & (S - 1)), kbeg + (kt + S - 1) * DL_BK);  // past kend: zero rows
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
+      if (ks == 0) issue((int)((kt + S - 1) & (S - 1)), kbeg + (kt + S - 1) * DL_BK);  // past kend: zero rows
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[ks][i], bf[ks][j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+    }
   }
   __builtin_amdgcn_s_waitcnt(0);  // the last (zero) stage has landed before the wave retires
 
