@@ -12,6 +12,7 @@
 // pair-blocked ladder integrals V2[(p,q)][c][d] in the input precision, or a
 // direct FP64 update C = alpha*AB + beta*C.
 #include <hip/hip_bf16.h>
+#include <algorithm>
 
 #include "../../include/libdcsd.h"
 #include "kernels.h"
@@ -302,8 +303,12 @@ __global__ __launch_bounds__(NT) void gemm_lp_kernel(LArgs g) {
 // MFMAs.  Every fragment read brings 16 bytes of K per lane: BF16 feeds one
 // 16x16x32 MFMA with it; FP32 feeds four 16x16x4 MFMAs, lane group g holding
 // k = 16 b + 4 g + s in step s of block b (A and B use the same assignment).
-// Requires K to be a multiple of the elements per 16 bytes, 16-byte aligned
-// operands and leading dimensions that are multiples of 8 elements.
+// EPI_PAIRS writes the pair-blocked integrals; EPI_SPLIT writes FP32 partial
+// products of the K chunk blockIdx.z (chunks a multiple of BK long) for a
+// fixed-order reduction.  Requires 16-byte aligned operands and leading
+// dimensions that are multiples of 8 elements.  A 16-byte chunk that starts
+// below the end of its K range is loaded whole: K must be a multiple of the
+// elements per 16 bytes, or each row must hold zeros up to that multiple.
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 // stages and 16-byte chunks per row and stage: BF16 two stages of 128-byte rows, FP32 three
 // of 64-byte rows (measured at the 12864 x 12864 x 1200 ladder batches)
@@ -317,7 +322,7 @@ __device__ inline uint32_t lds_byte_address(const void* p) {
 }
 constexpr int waitcnt_vm(int vm) { return (vm & 0xF) | ((vm >> 4) << 14) | (7 << 4) | (0xF << 8); }
 
-template <class T, int S, int CPR>
+template <class T, int S, int CPR, int EPI>
 __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
   constexpr int VL = Traits<T>::VL;          // elements per 16-byte chunk
   constexpr int RB = 16 * CPR;               // bytes of K per row and stage
@@ -333,13 +338,18 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
-  if (g.skip_lower) {
+  if (EPI == EPI_PAIRS && g.skip_lower) {
     if (!diag_tile(blockIdx.x, (g.M + 127) / 128, g.tiles_n, g.N, g.vu, 128, 128, tm, tn))
       return;  // whole workgroup, before any barrier
   } else {
     tile_of(blockIdx.x, (g.M + 127) / 128, g.tiles_n, tm, tn);
   }
   const int64_t m0 = tm * 128, n0 = tn * 128;
+  int64_t kbeg = 0, kend = g.K;
+  if (EPI == EPI_SPLIT) {
+    kbeg = (int64_t)blockIdx.z * g.kchunk;
+    kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  }
   const T* A = (const T*)g.A;
   const T* B = (const T*)g.B;
   const T* zrow = (const T*)lp_zero_row;
@@ -354,8 +364,8 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
       const int r = q * RPI + lane / CPR;
       const int chunk = (lane % CPR) ^ swz(r);
       const int64_t k = k0 + chunk * VL;
-      const T* sa = (m0 + r < g.M && k < g.K) ? A + (m0 + r) * g.lda + k : zrow;
-      const T* sb = (n0 + r < g.N && k < g.K) ? B + (n0 + r) * g.ldb + k : zrow;
+      const T* sa = (m0 + r < g.M && k < kend) ? A + (m0 + r) * g.lda + k : zrow;
+      const T* sb = (n0 + r < g.N && k < kend) ? B + (n0 + r) * g.ldb + k : zrow;
       const int dst = q * RPI * RB;
       __builtin_amdgcn_global_load_lds((const void*)sa, (void __attribute__((address_space(3)))*)&sA[slot][dst], 16, 0,
                                        0);
@@ -378,9 +388,9 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
     ao[h] = (uint32_t)((wm * WM + lcol) * RB + (((4 * h + lrow) ^ swz(lcol)) * 16));
     bo[h] = (uint32_t)((wn * WN + lcol) * RB + (((4 * h + lrow) ^ swz(lcol)) * 16));
   }
-  const int64_t nk = (g.K + BK - 1) / BK;
+  const int64_t nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
 #pragma unroll
-  for (int t = 0; t < S - 1; ++t) issue(t, (int64_t)t * BK);
+  for (int t = 0; t < S - 1; ++t) issue(t, kbeg + (int64_t)t * BK);
   int slot = 0, fill = S - 1;  // stage read this step, stage refilled this step
   for (int64_t kt = 0; kt < nk; ++kt) {
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * IPW * (S - 2)));
@@ -405,7 +415,7 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
           : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB)
           : "memory");
     }
-    issue(fill, (kt + S - 1) * BK);  // past K: zero rows
+    issue(fill, kbeg + (kt + S - 1) * BK);  // past the K range: zero rows
     slot = slot + 1 == S ? 0 : slot + 1;
     fill = fill + 1 == S ? 0 : fill + 1;
 #pragma unroll
@@ -425,7 +435,22 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
         }
   }
   __builtin_amdgcn_s_waitcnt(0);  // the last (zero) stages have landed before the wave retires
-  store_pairs<T, TM, TN>(g, acc, m0 + wm * WM + 4 * lrow, n0 + wn * WN + lcol);
+  const int64_t mb = m0 + wm * WM + 4 * lrow, nbase = n0 + wn * WN + lcol;
+  if constexpr (EPI == EPI_PAIRS) {
+    store_pairs<T, TM, TN>(g, acc, mb, nbase);
+  } else {
+    float* W = (float*)g.C + (int64_t)blockIdx.z * g.split_stride;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = mb + i * 16 + r;
+        if (gm >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          if (nbase + j * 16 < g.N) W[gm * g.N + nbase + j * 16] = acc[i][j][r];
+      }
+  }
 }
 
 // C(m,n) = alpha * sum_z W[z][m*N + n] + beta * C(m,n), summed in FP64 in z order.
@@ -506,13 +531,21 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
     DCSD_CHECK_LAUNCH();
     return;
   }
+  // direct-to-LDS when whole 16-byte chunks may be loaded up to the end of K
+  constexpr int DBK = DlShape<T>::CPR * Traits<T>::VL;
+  const bool dl = q.k_padded || q.K % Traits<T>::VL == 0;
+  const int64_t step = dl ? std::max<int64_t>(DBK, Stage<T, TILE>::BK) : Stage<T, TILE>::BK;
   int64_t chunk = (q.K + q.ks - 1) / q.ks;
-  chunk = (chunk + Stage<T, TILE>::BK - 1) / Stage<T, TILE>::BK * Stage<T, TILE>::BK;
+  chunk = (chunk + step - 1) / step * step;
   const int ks = (int)((q.K + chunk - 1) / chunk);
   a.C = q.work;
   a.kchunk = chunk;
   a.split_stride = q.M * q.N;
-  hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_SPLIT, true>), dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
+  if (dl)
+    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT>),
+                       dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
+  else
+    hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_SPLIT, true>), dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();
   hipLaunchKernelGGL(lp_split_reduce, dim3(nb(q.M * q.N)), dim3(256), 0, s, (const float*)q.work, q.C, q.M, q.N, ks,
                      q.ldc, q.c_nc ? 1 : 0, q.alpha, q.beta);
@@ -535,7 +568,8 @@ void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_
   a.skip_lower = p0 == q0 && np == nq && np * (np - 1) / 2 <= 65535 && diag_skips(np, vu, BT, BT);
   const int64_t tiles = a.skip_lower ? diag_grid(tiles_m, a.tiles_n) : tiles_m * a.tiles_n;
   if (BT == 128 && naux % Traits<T>::VL == 0)
-    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_PAIRS>), dim3((unsigned)tiles), dim3(NT),
+                       0, s, a);
   else
     hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false, BT>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();

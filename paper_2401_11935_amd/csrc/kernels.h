@@ -94,6 +94,7 @@ struct LpGemm {
   double alpha = 1.0, beta = 0.0;
   int ks = 1;
   float* work = nullptr;
+  bool k_padded = false;  // every row of A and B holds zeros from K up to a multiple of 8 elements
 };
 void lp_gemm(const LpGemm& g, hipStream_t s);
 // Pair-blocked ladder integrals V2[(p,q)][c][d] (row stride kp) = sum_P BlT[(p,c)][P] BlT[(q,d)][P]

@@ -324,6 +324,10 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     BlT = lp_alloc((int64_t)n * vu * ldk);
     TstackL = lp_alloc(rows_all * kp);
     V2L = lp_alloc((int64_t)lb * lb * kp);
+    // the ladder contraction loads whole 16-byte chunks up to the end of K = vu^2: the row
+    // padding of both operands is zeroed once here and nothing writes it afterwards
+    fill((double*)TstackL, 0.0, (rows_all * kp * es + 7) / 8, s);
+    fill((double*)V2L, 0.0, ((int64_t)lb * lb * kp * es + 7) / 8, s);
     lp_cap = tov * lp_ld(tov);
     lpA = lp_alloc(lp_cap);
     lpB = lp_alloc(lp_cap);
@@ -725,6 +729,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
           q.A = TstackL; q.lda = kp; q.B = V2L; q.ldb = kp;
           q.C = Rb; q.ldc = N;
           q.ks = ks; q.work = lwork;
+          q.k_padded = true;
           lp_gemm(q, s);
         } else {
           G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
