@@ -438,6 +438,24 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
   const int64_t mb = m0 + wm * WM + 4 * lrow, nbase = n0 + wn * WN + lcol;
   if constexpr (EPI == EPI_PAIRS) {
     store_pairs<T, TM, TN>(g, acc, mb, nbase);
+  } else if constexpr (EPI == EPI_F64) {
+    double* C = (double*)g.C;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gm = mb + i * 16 + r;
+        if (gm >= g.M) continue;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int64_t gn = nbase + j * 16;
+          if (gn >= g.N) continue;
+          const int64_t off = g.c_nc ? gm * g.ldc + gn : gm + gn * g.ldc;
+          double out = g.alpha * (double)acc[i][j][r];
+          if (g.beta != 0.0) out += g.beta * C[off];
+          C[off] = out;
+        }
+      }
   } else {
     float* W = (float*)g.C + (int64_t)blockIdx.z * g.split_stride;
 #pragma unroll
@@ -492,10 +510,12 @@ __global__ __launch_bounds__(256) void lp_convert_kernel(T* dst, int64_t ldd, co
     tile[rr][cc] = x;
   }
   __syncthreads();
+  // the row padding up to the next multiple of 64 columns (within ldd) is written as zeros, so
+  // that GEMMs may load whole 16-byte chunks past the end of K
   for (int e = tid; e < 64 * 64; e += 256) {
     const int rr = e / 64, cc = e % 64;
     const int64_t r = r0 + rr, c = c0 + cc;
-    if (r < rows && c < cols) dst[r * ldd + c] = lp_round<T>((float)tile[rr][cc]);
+    if (r < rows && c < ldd) dst[r * ldd + c] = c < cols ? lp_round<T>((float)tile[rr][cc]) : (T)0.0f;
   }
 }
 
@@ -524,16 +544,20 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
   a.alpha = q.alpha; a.beta = q.beta;
   a.tiles_n = (q.N + TILE - 1) / TILE;
   const int64_t tiles = ((q.M + TILE - 1) / TILE) * a.tiles_n;
-  if (q.ks <= 1) {
-    a.C = q.C; a.ldc = q.ldc; a.c_nc = q.c_nc ? 1 : 0;
-    a.kchunk = q.K;
-    hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_F64, false>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
-    DCSD_CHECK_LAUNCH();
-    return;
-  }
   // direct-to-LDS when whole 16-byte chunks may be loaded up to the end of K
   constexpr int DBK = DlShape<T>::CPR * Traits<T>::VL;
   const bool dl = q.k_padded || q.K % Traits<T>::VL == 0;
+  if (q.ks <= 1) {
+    a.C = q.C; a.ldc = q.ldc; a.c_nc = q.c_nc ? 1 : 0;
+    a.kchunk = q.K;
+    if (dl)
+      hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_F64>), dim3((unsigned)tiles), dim3(NT),
+                         0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_F64, false>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
+    DCSD_CHECK_LAUNCH();
+    return;
+  }
   const int64_t step = dl ? std::max<int64_t>(DBK, Stage<T, TILE>::BK) : Stage<T, TILE>::BK;
   int64_t chunk = (q.K + q.ks - 1) / q.ks;
   chunk = (chunk + step - 1) / step * step;

@@ -86,6 +86,7 @@ void G::lp_product(Ctx& c, const double* A, const double* Asub, const double* B,
   }
   q.ks = (int)ks;
   q.work = c.lwork;
+  q.k_padded = true;  // lp_convert zeroes the row padding of both operands
   lp_gemm(q, c.s);
 }
 
