@@ -40,14 +40,17 @@ struct G {
   G& batch(int64_t b, int64_t sA, int64_t sB, int64_t sC) { a.batch = b; a.sA = sA; a.sB = sB; a.sC = sC; return *this; }
   G& split(int k, double* w) { a.ksplit = k; a.work = w; return *this; }
   // Few output tiles and a long K: split K across workgroups into the context's
-  // workspace (fixed-order reduction, deterministic).
+  // workspace (fixed-order reduction, deterministic), aiming at about 1024
+  // workgroups of the tile size that will run (128 when both M and N reach it;
+  // the 64-wide kernel is capped at 256 splits, beyond which it ran slower).
   void run(Ctx& c) {
     const double* g_ws = c.gws;
     const int64_t g_ws_cap = c.gws_cap;
     if (a.ksplit == 1 && g_ws && a.K >= 2048) {
-      const int64_t tiles = ((a.M + 63) / 64) * ((a.N + 63) / 64) * a.batch;
+      const int64_t T = a.M >= 128 && a.N >= 128 ? 128 : 64;
+      const int64_t tiles = ((a.M + T - 1) / T) * ((a.N + T - 1) / T) * a.batch;
       if (tiles < 256) {
-        int64_t ks = std::min<int64_t>(256, std::max<int64_t>(1, 1024 / tiles));
+        int64_t ks = std::min<int64_t>(T == 128 ? 1024 : 256, std::max<int64_t>(1, 1024 / tiles));
         ks = std::min<int64_t>(ks, a.K / 512);
         const int64_t span = (a.batch - 1) * a.sC + (a.c_nc ? (a.M - 1) * a.ldc + a.N : (a.N - 1) * a.ldc + a.M);
         while (ks > 1 && ks * span > g_ws_cap) ks /= 2;
