@@ -11,6 +11,7 @@ import dcsd_synth as synth
 from oracle.brute import DeterminantSpace
 from oracle.ccsd import ccsd_residual
 from oracle.coupling import coupling
+from oracle.fixedref import FixedRef
 from oracle.hamiltonian import Hamiltonian
 from oracle.twodet import TwoDet
 
@@ -61,6 +62,25 @@ def test_W_and_reference_energy(nc, nv):
     a = ds.vector(ds.mask_A())
     assert abs(ham.e_ref() - ds.read_A(ds.apply_H(a))) < 1e-12
     # <A| e^-T H e^T |A> = E_ref + Delta E_A
+    assert abs(ds.read_A(y) - ham.e_ref() - model.energy_A(vec)) < 1e-12
+
+
+@pytest.mark.parametrize("nc,nv", CASES)
+@pytest.mark.parametrize("state", ["singlet", "triplet"])
+def test_fixed_reference_residual_and_energy_equal_projection(nc, nv, state):
+    """Fixed reference: the projection of e^-T H e^T |A> with the A->B double
+    held at +-1 (the element itself then set to zero), and <A| e^-T H e^T |A>."""
+    B, F, ham, vec = _setup(nc, nv)
+    model = FixedRef(B, F, nc, "ccsd", state)
+    t1, t2 = ham.to_so(model.fixed(vec))
+    ds = DeterminantSpace(ham)
+    y = ds.connected(t1, t2)
+    r1b, r2b = ds.projections(y)
+    ref = ham.from_so(r1b, r2b)
+    ref[model.ab] = 0.0
+    R, W = model.residual(vec)
+    assert W == 0.0
+    assert np.abs(R - ref).max() < 1e-12
     assert abs(ds.read_A(y) - ham.e_ref() - model.energy_A(vec)) < 1e-12
 
 
