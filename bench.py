@@ -104,6 +104,7 @@ def parse():
                     help="low precisions compared with FP64 (residual evals at the same amplitudes; '' = skip)")
     ap.add_argument("--evals", type=int, default=3, help="timed residual evaluations per precision")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the residual VJP")
+    ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -231,6 +232,23 @@ def precision_comparison(L, torch, args, Bd, Fd, stream, fm):
             "ring_tflops": ring["flops"] / (ring["ms"] * 1e-3) / 1e12 if ring["ms"] > 0 else 0.0,
             "kernels": tim,
         }
+    return out
+
+
+def fixed_reference_timing(L, torch, args, Bd, Fd, stream, fm):
+    """FP64 residual evaluations of the fixed-reference methods (singlet) at the
+    metric size: the same kernels as 2D without the coupling terms."""
+    base = dict(nc=args.nc, nv=args.nv, naux=args.naux, ladder_block=args.ladder_block, precond=args.precond,
+                level_shift=args.level_shift)
+    n_amp = L.amplitude_count(args.nc, args.nv)
+    T = torch.zeros(n_amp, dtype=torch.float64, device=Bd.device)
+    out = {"amplitudes": "T = 0 apart from the fixed A->B double (the work does not depend on the values)",
+           "evals_timed": args.evals}
+    for name in ("fr-dcsd-singlet", "fr-ccsd-singlet"):
+        print(f"bench: residual evals of {name}", file=sys.stderr, flush=True)
+        _, W, dt, tim = residual_rate(L, torch, L.default_config(method=name, **base), Bd, Fd, stream, T, args.evals)
+        out[name] = {"residual_evals_per_s": 1.0 / dt, "ms_per_eval": 1e3 * dt, "W": W,
+                     "tflops": sum(fm.values()) / dt / 1e12, "kernels": tim}
     return out
 
 
@@ -386,6 +404,8 @@ def main():
     if args.precisions:
         out["precisions"] = precision_comparison(L, torch, args, Bd, Fd, stream, fm)
         out["mixed_convergence_tiny"] = tiny_convergence(L, torch, stream)
+    if not args.no_fr:
+        out["fixed_reference"] = fixed_reference_timing(L, torch, args, Bd, Fd, stream, fm)
     if not args.no_adjoint:
         print("bench: residual VJP", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_timing(L, torch, args, Bd, Fd, stream)

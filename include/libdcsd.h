@@ -58,7 +58,24 @@ typedef enum {
   DCSD_ERR_STATE = 6       /* call on a context in an error state          */
 } dcsd_status;
 
-enum { DCSD_METHOD_DCSD = 0, DCSD_METHOD_CCSD = 1 };
+/* Methods.  2D-DCSD and 2D-CCSD solve the two-determinant equations (Theory
+ * section): the Phi_A -> Phi_B double is held at zero, the coupling -K_x W
+ * enters every residual, and one solve gives both the open-shell singlet
+ * E_S = dE_A + W and the M_s = 0 triplet E_T = dE_A - W.
+ * The fixed-reference methods (introduction; the FR approach) solve the
+ * single-reference DCSD or CCSD equations of Phi_A with the Phi_A -> Phi_B
+ * double fixed at +1 (singlet: Phi_A + Phi_B) or -1 (M_s = 0 triplet:
+ * Phi_A - Phi_B) and no coupling terms.  One solve gives one state: its
+ * correlation energy dE_A (which includes the fixed amplitude) is reported in
+ * E_S (singlet) or E_T (triplet), the other is NaN, and W is 0. */
+enum {
+  DCSD_METHOD_DCSD = 0,
+  DCSD_METHOD_CCSD = 1,
+  DCSD_METHOD_FR_DCSD_SINGLET = 2,
+  DCSD_METHOD_FR_DCSD_TRIPLET = 3,
+  DCSD_METHOD_FR_CCSD_SINGLET = 4,
+  DCSD_METHOD_FR_CCSD_TRIPLET = 5
+};
 /* Arithmetic of the particle-particle ladder and ring GEMMs (everything else
  * is FP64 in every mode): FP64 MFMA, or FP32 / BF16 MFMA inputs (rounded to
  * nearest even through FP32) with FP32 accumulation, added into FP64. */
@@ -81,7 +98,7 @@ enum {
 
 typedef struct {
   int32_t nc, nv, naux;   /* core (doubly occupied) orbitals, virtuals, DF rank */
-  int32_t method;         /* DCSD_METHOD_DCSD or DCSD_METHOD_CCSD               */
+  int32_t method;         /* DCSD_METHOD_*                                      */
   int32_t precision;      /* DCSD_PREC_FP64, DCSD_PREC_FP32 or DCSD_PREC_BF16   */
   int32_t diis_dim;       /* DIIS subspace size (0 = plain Jacobi)              */
   int32_t diis_start;     /* first iteration that extrapolates                  */
@@ -98,9 +115,12 @@ typedef struct {
 
 typedef struct {
   double dE_A;    /* single-reference correlation energy expression of Phi_A */
-  double W;       /* effective coupling <B| H_N e^T_A |A> (residual element) */
-  double E_S;     /* open-shell singlet correlation energy dE_A + W          */
-  double E_T;     /* M_s = 0 triplet correlation energy dE_A - W             */
+  double W;       /* effective coupling <B| H_N e^T_A |A> (residual element);
+                     0 for the fixed-reference methods                        */
+  double E_S;     /* open-shell singlet correlation energy dE_A + W (fixed
+                     reference: dE_A of a singlet run, NaN otherwise)          */
+  double E_T;     /* M_s = 0 triplet correlation energy dE_A - W (fixed
+                     reference: dE_A of a triplet run, NaN otherwise)          */
   double E_ref_A; /* <A|H|A>                                                 */
 } dcsd_energies;
 
@@ -131,14 +151,16 @@ dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double*
 
 /* Residual of the 2D equations (Theory section, singles and doubles
  * equations): R = <x| e^-T H e^T |A> - [DC dropped terms] - K_x W, with
- * R at the Phi_A -> Phi_B double set to zero.  T_dev and R_dev are packed
+ * R at the Phi_A -> Phi_B double set to zero.  Fixed-reference methods: the
+ * same first two terms with the Phi_A -> Phi_B double of T taken as +1 or -1
+ * (whatever T_dev holds there), no coupling, W = 0.  T_dev and R_dev are packed
  * vectors (may not alias).  If W_host is not NULL it receives W and the call
  * synchronises; otherwise it is asynchronous. */
 dcsd_status dcsd_residual(dcsd_ctx* ctx, const double* T_dev, double* R_dev, double* W_host);
 
 /* Energies for amplitudes T and coupling W (W as returned by dcsd_residual
- * for the same T): dE_A, E_S = dE_A + W, E_T = dE_A - W, E_ref_A.
- * Synchronises. */
+ * for the same T): dE_A, E_S = dE_A + W, E_T = dE_A - W, E_ref_A (the
+ * fixed-reference methods as described at DCSD_METHOD_*).  Synchronises. */
 dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energies* out);
 
 /* Solves the amplitude equations starting from T_inout (zeros = the usual
@@ -192,7 +214,9 @@ dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* 
  * h (G_pq + G_qp)/2.  *out (may be NULL) reports the lambda iterations.
  * Returns DCSD_ERR_NOCONV (gradient from the last lambda) or
  * DCSD_ERR_NONFINITE like dcsd_solve.  FP64 in every precision setting;
- * allocates like dcsd_residual_vjp. */
+ * allocates like dcsd_residual_vjp.  A fixed-reference run has one state:
+ * E = ebar_S dE_A for a singlet method, ebar_T dE_A for a triplet method (the
+ * other weight is ignored). */
 dcsd_status dcsd_backward(dcsd_ctx* ctx, const double* T_dev, double ebar_S, double ebar_T, double* Bbar_dev,
                           double* Fbar_dev, double* lambda_dev, dcsd_report* out);
 

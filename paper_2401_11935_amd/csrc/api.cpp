@@ -109,8 +109,7 @@ dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energ
     const double e = ctx->c.energy_A(T_dev);
     out->dE_A = e;
     out->W = W;
-    out->E_S = e + W;
-    out->E_T = e - W;
+    dcsd::state_energies(ctx->c.cfg.method, e, W, out->E_S, out->E_T);
     out->E_ref_A = ctx->c.e_ref;
     return DCSD_OK;
   });
@@ -152,7 +151,12 @@ dcsd_status dcsd_backward(dcsd_ctx* ctx, const double* T_dev, double ebar_S, dou
       DCSD_HIP(hipMemcpyAsync(c.lam, lambda_dev, c.total * sizeof(double), hipMemcpyDeviceToDevice, c.s));
     else
       dcsd::fill(c.lam, 0.0, c.total, c.s);
-    const double a = ebar_S + ebar_T, b = ebar_S - ebar_T;
+    // E = a dE_A + b W; a fixed-reference run has one state, with energy dE_A and W = 0
+    double a = ebar_S + ebar_T, b = ebar_S - ebar_T;
+    if (dcsd::method_fr(c.cfg.method)) {
+      a = dcsd::ab_amplitude(c.cfg.method) > 0.0 ? ebar_S : ebar_T;
+      b = 0.0;
+    }
     dcsd_report rep{};
     const int rc = c.lambda_solve(a, b, c.lam, &rep);
     if (out) *out = rep;

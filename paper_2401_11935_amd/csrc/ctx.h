@@ -10,6 +10,32 @@
 
 namespace dcsd {
 
+// Method families: CCSD keeps all T2*T2 terms, DCSD drops the distinguishable-cluster set;
+// the fixed-reference methods hold the Phi_A -> Phi_B double at +1 (singlet) or -1
+// (M_s = 0 triplet) and have no coupling terms.
+inline bool method_known(int m) { return m >= DCSD_METHOD_DCSD && m <= DCSD_METHOD_FR_CCSD_TRIPLET; }
+inline bool method_cc(int m) {
+  return m == DCSD_METHOD_CCSD || m == DCSD_METHOD_FR_CCSD_SINGLET || m == DCSD_METHOD_FR_CCSD_TRIPLET;
+}
+inline bool method_fr(int m) { return m >= DCSD_METHOD_FR_DCSD_SINGLET && m <= DCSD_METHOD_FR_CCSD_TRIPLET; }
+// value of the Phi_A -> Phi_B double in the residual and energy
+inline double ab_amplitude(int m) {
+  if (!method_fr(m)) return 0.0;
+  return (m == DCSD_METHOD_FR_DCSD_SINGLET || m == DCSD_METHOD_FR_CCSD_SINGLET) ? 1.0 : -1.0;
+}
+// singlet and triplet correlation energies from dE_A and W
+inline void state_energies(int m, double dEA, double W, double& ES, double& ET) {
+  if (!method_fr(m)) {
+    ES = dEA + W;
+    ET = dEA - W;
+    return;
+  }
+  const double nan = __builtin_nan("");
+  const bool singlet = ab_amplitude(m) > 0.0;
+  ES = singlet ? dEA : nan;
+  ET = singlet ? nan : dEA;
+}
+
 // Device memory owned by the context; every buffer is allocated in dcsd_init.
 struct DevBuf {
   double* p = nullptr;

@@ -223,7 +223,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   cfg = cf;
   s = stream;
   if (cfg.nc < 0 || cfg.nv < 1 || cfg.naux < 1) throw ArgError("nc >= 0, nv >= 1 and naux >= 1 are required");
-  if (cfg.method != DCSD_METHOD_DCSD && cfg.method != DCSD_METHOD_CCSD) throw ArgError("unknown method");
+  if (!method_known(cfg.method)) throw ArgError("unknown method");
   if (cfg.precision != DCSD_PREC_FP64 && cfg.precision != DCSD_PREC_FP32 && cfg.precision != DCSD_PREC_BF16)
     throw ArgError("unknown precision");
   if (cfg.refresh_every < 0) throw ArgError("refresh_every must be >= 0");
@@ -275,7 +275,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   Jpq = alloc(n2);
   Kpq = alloc(n2);
   Isc = alloc(tov * tov);
-  if (cfg.method == DCSD_METHOD_CCSD) {
+  if (method_cc(cfg.method)) {
     Icc = alloc(tov * tov);
     Isf1 = alloc(s2);
     Isf2 = alloc(s2);
@@ -340,7 +340,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     const int64_t sz[Ctx::kSites] = {tov * tov, tov * tov, s2, s2, s2, s2};
     const bool av[Ctx::kSites] = {false, true, false, false, true, true};
     for (int k = 0; k < Ctx::kSites; ++k) {
-      if ((k == 2 || k == 3) && cfg.method != DCSD_METHOD_CCSD) continue;
+      if ((k == 2 || k == 3) && !method_cc(cfg.method)) continue;
       if (av[k]) site[k].Ar = alloc(sz[k]);
       site[k].Br = alloc(sz[k]);
       site[k].Pr = alloc(sz[k]);
@@ -440,7 +440,7 @@ void Ctx::build_constants(bool full) {
   copyN(QY2[1], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {v, vt, tov, 1}, 1.0, 0.0, s);
   // Ikl_ab[(k,L),(c,D)] = (kc|LD)
   copyN(Ikl[2], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
-  if (cfg.method == DCSD_METHOD_CCSD) {
+  if (method_cc(cfg.method)) {
     // <kl||cd> = (kc|ld) - (kd|lc): exchange part on the equal-spin blocks
     rcopy(Icc, Isc, tov * tov, s);
     for (int sp = 0; sp < 2; ++sp) {
@@ -489,15 +489,16 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   }
   const uint32_t mask = cfg.term_mask;
   const int64_t NA = naux, o2 = (int64_t)o * o, vv = (int64_t)v * v, ov2 = o * vv;
-  const bool cc = cfg.method == DCSD_METHOD_CCSD;
+  const bool cc = method_cc(cfg.method);
   const double sdc = cc ? 1.0 : 0.5;  // weight of the Fock-like T2*T2 terms (Q_c, Q_d)
   hipEvent_t ev_res;
   const int rec_res = tbegin(&ev_res);
 
-  // amplitudes with the Phi_A -> Phi_B double forced to zero
+  // amplitudes with the Phi_A -> Phi_B double set: zero in the two-determinant methods,
+  // +1 or -1 in the fixed-reference ones
   rcopy(Tw, T, total, s);
   const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  rfill(Tw + ab_pos, 0.0, 1, s);
+  rfill(Tw + ab_pos, ab_amplitude(cfg.method), 1, s);
   const double* t1[2] = {Tw, Tw + ov};
   const double* t2aa = Tw + 2 * ov;
   const double* t2bb = t2aa + s2;
@@ -761,9 +762,13 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
                       v, s);
   }
 
-  // ---- coupling of the two determinants ---------------------------------------------
-  rcopy(scal, R + ab_pos, 1, s);  // W
-  if (mask & DCSD_TERM_COUPLING) {
+  // ---- coupling of the two determinants (none in the fixed-reference methods) -------
+  const bool fr = method_fr(cfg.method);
+  if (fr)
+    rfill(scal, 0.0, 1, s);  // W
+  else
+    rcopy(scal, R + ab_pos, 1, s);  // W
+  if (!fr && (mask & DCSD_TERM_COUPLING)) {
     if (t_tape) {
       TapeOp op;
       op.kind = OP_COUPLING;
@@ -776,7 +781,8 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
     }
     coupling_apply(coup_launch, Tw, R, scal, nc, nv, s);
   }
-  // the Phi_A -> Phi_B double: its residual is W itself and is not solved for
+  // the Phi_A -> Phi_B double is not solved for (its residual is W in the two-determinant
+  // methods; the fixed-reference methods hold the amplitude fixed)
   rfill(R + ab_pos, 0.0, 1, s);
   if (rec_res) tend(ev_res, 0.0, 2);
   if (W_host) {
@@ -801,7 +807,7 @@ void Ctx::tend(hipEvent_t a, double flops, int cls) {
 double Ctx::energy_A(const double* T) {
   rcopy(Tw, T, total, s);
   const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  rfill(Tw + ab_pos, 0.0, 1, s);
+  rfill(Tw + ab_pos, ab_amplitude(cfg.method), 1, s);
   energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
   double e = 0.0;
   DCSD_HIP(hipMemcpyAsync(&e, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));

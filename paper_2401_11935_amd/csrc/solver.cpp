@@ -152,8 +152,7 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
     r.res_max = host[1];
     r.e.W = host[0];
     r.e.dE_A = host[2];
-    r.e.E_S = host[2] + host[0];
-    r.e.E_T = host[2] - host[0];
+    state_energies(cfg.method, host[2], host[0], r.e.E_S, r.e.E_T);
     r.e.E_ref_A = e_ref;
     r.fp64 = exact ? 1 : 0;
     r.converged = (!bad && exact && host[1] <= cfg.tol_residual) ? 1 : 0;

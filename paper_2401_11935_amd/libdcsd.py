@@ -16,7 +16,8 @@ DEFAULT_PATH = os.path.join(HERE, "lib", "libdcsd.so")
 
 DCSD_OK, DCSD_ERR_ARG, DCSD_ERR_OOM, DCSD_ERR_HIP, DCSD_ERR_NOCONV, DCSD_ERR_NONFINITE, DCSD_ERR_STATE = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_OOM", "ERR_HIP", "ERR_NOCONV", "ERR_NONFINITE", "ERR_STATE"]
-METHODS = {"dcsd": 0, "ccsd": 1}
+METHODS = {"dcsd": 0, "ccsd": 1, "fr-dcsd-singlet": 2, "fr-dcsd-triplet": 3, "fr-ccsd-singlet": 4,
+           "fr-ccsd-triplet": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 TERM = {"driver": 1, "fock": 2, "hh": 4, "pp": 8, "ring": 16, "singles": 32, "coupling": 64}
 TERM_ALL = 0x7F

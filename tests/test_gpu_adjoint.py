@@ -61,7 +61,8 @@ def _objective(B, F, T, nc, method, Rbar, Wbar, Ebar, lb):
 
 
 @pytest.mark.parametrize("nc,nv,naux,method,lb", [(2, 5, 13, "dcsd", 0), (3, 7, 11, "ccsd", 3), (0, 6, 9, "ccsd", 2),
-                                                  (3, 16, 60, "dcsd", 5), (4, 20, 30, "ccsd", 0)])
+                                                  (3, 16, 60, "dcsd", 5), (4, 20, 30, "ccsd", 0),
+                                                  (2, 5, 13, "fr-dcsd-singlet", 0), (3, 7, 11, "fr-ccsd-triplet", 3)])
 def test_residual_vjp_matches_directional_differences(nc, nv, naux, method, lb):
     import torch
     from gpu_util import to_dev
