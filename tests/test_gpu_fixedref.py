@@ -142,3 +142,24 @@ def test_fixed_reference_gradient_matches_finite_differences(name):
         worst = max(worst, abs(fd - an) / max(abs(fd), 1e-3))
         assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-9, (kind, P, p, q, fd, an)
     say(f"  worst |fd - adjoint| / max(|fd|, 1e-3) = {worst:.1e}")
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fixed_reference_mixed_precision_solve_reaches_fci(precision):
+    """The low-precision ladder and rings with FP64 refreshes converge to the
+    same FP64 fixed point: within 1 microhartree of the FCI roots."""
+    from gpu_util import GpuProblem
+    from oracle.brute import DeterminantSpace
+    from oracle.hamiltonian import Hamiltonian
+    B, F, _ = synth.make_z2_inputs(0, 7, 30, 11)
+    ham = Hamiltonian(B, F, 0)
+    ES, ET, _, _ = DeterminantSpace(ham).fci_pair()
+    for name, key, ref in (("fr-dcsd-singlet", "E_S", ES), ("fr-ccsd-triplet", "E_T", ET)):
+        say("fr mixed solve", name, precision)
+        p = GpuProblem(B, F, 0, name, tol_residual=1e-10, precision=precision)
+        rep, _ = p.solve()
+        p.close()
+        err = abs(ham.e_ref() + rep[key] - ref)
+        say(f"  {rep['status']} iterations {rep['iterations']}  |E - FCI| = {err:.2e}")
+        assert rep["status"] == "OK"
+        assert err <= 1e-6
