@@ -610,115 +610,4 @@ void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int6
   }
 }
 
-// ---------------------------------------------------------------------------
-// Strided copy dst[od] = alpha * src[os] + beta * dst[od] over an index box of up to
-// six dimensions (od, os: sums of index times stride).  Two kernels, both HBM-bound:
-//  * rows: one workgroup per row of the box, the row being every dimension but one
-//    (`in`), decomposed once per workgroup from blockIdx (uniform, so in scalar
-//    registers); the threads run along `in`.  Used when the destination and the
-//    source have their unit stride in the same dimension (both accesses coalesced).
-//  * tiles: the destination's unit-stride dimension a and the source's b are tiled
-//    32 x 32 through LDS, so that both the reads (along b) and the writes (along a)
-//    are coalesced; a workgroup per tile and per index of the remaining dimensions.
-struct CopyPlan {
-  int nd;
-  int64_t dims[6], ds[6], ss[6];
-};
-
-// offsets of index `r` of the box with dimensions `skip0` and `skip1` removed
-__device__ inline void copy_outer(const CopyPlan& p, int64_t r, int skip0, int skip1, int64_t& od, int64_t& os) {
-  od = 0;
-  os = 0;
-  for (int d = p.nd - 1; d >= 0; --d) {
-    if (d == skip0 || d == skip1) continue;
-    const int64_t i = r % p.dims[d];
-    r /= p.dims[d];
-    od += i * p.ds[d];
-    os += i * p.ss[d];
-  }
-}
-
-__global__ __launch_bounds__(256) void copy_rows_kernel(double* dst, const double* src, CopyPlan p, int in,
-                                                        double alpha, double beta) {
-  int64_t od, os;
-  copy_outer(p, blockIdx.x, in, -1, od, os);
-  const int64_t n = p.dims[in], sd = p.ds[in], ss = p.ss[in];
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    double v = alpha * src[os + i * ss];
-    if (beta != 0.0) v += beta * dst[od + i * sd];
-    dst[od + i * sd] = v;
-  }
-}
-
-__global__ __launch_bounds__(256) void copy_tiles_kernel(double* dst, const double* src, CopyPlan p, int a, int b,
-                                                         double alpha, double beta) {
-  __shared__ double t[32][33];
-  const int64_t na = p.dims[a], nb = p.dims[b];
-  const int64_t ta = (na + 31) / 32, tb = (nb + 31) / 32;
-  const int64_t bid = blockIdx.x;
-  const int64_t ia0 = (bid % ta) * 32, ib0 = ((bid / ta) % tb) * 32;
-  int64_t od, os;
-  copy_outer(p, bid / (ta * tb), a, b, od, os);
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  // read along b (the source's unit stride)
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t ia = ia0 + r, ib = ib0 + tx;
-    if (ia < na && ib < nb) t[r][tx] = src[os + ia * p.ss[a] + ib * p.ss[b]];
-  }
-  __syncthreads();
-  // write along a (the destination's unit stride)
-  for (int r = ty; r < 32; r += 8) {
-    const int64_t ia = ia0 + tx, ib = ib0 + r;
-    if (ia < na && ib < nb) {
-      const int64_t o = od + ia * p.ds[a] + ib * p.ds[b];
-      double v = alpha * t[tx][r];
-      if (beta != 0.0) v += beta * dst[o];
-      dst[o] = v;
-    }
-  }
-}
-
-void strided_copy(double* dst, const double* src, const Strided& st, double alpha, double beta,
-                  hipStream_t s) {
-  if (st.nd < 1 || st.nd > 6) throw ArgError("strided_copy: 1 to 6 dimensions");
-  CopyPlan p{};
-  p.nd = st.nd;
-  int64_t total = 1;
-  for (int d = 0; d < st.nd; ++d) {
-    p.dims[d] = st.dims[d];
-    p.ds[d] = st.ds[d];
-    p.ss[d] = st.ss[d];
-    total *= st.dims[d];
-  }
-  if (total <= 0) return;
-  // the destination's and the source's unit-stride dimensions (the last, if none)
-  int a = st.nd - 1, b = -1;
-  for (int d = st.nd - 1; d >= 0; --d)
-    if (st.ds[d] == 1) {
-      a = d;
-      break;
-    }
-  for (int d = st.nd - 1; d >= 0; --d)
-    if (st.ss[d] == 1) {
-      b = d;
-      break;
-    }
-  if (b >= 0 && b != a && st.dims[a] >= 16 && st.dims[b] >= 16) {
-    const int64_t tiles = ((st.dims[a] + 31) / 32) * ((st.dims[b] + 31) / 32) * (total / (st.dims[a] * st.dims[b]));
-    if (tiles >= ((int64_t)1 << 31)) throw ArgError("strided_copy: box too large");
-    hipLaunchKernelGGL(copy_tiles_kernel, dim3((unsigned)tiles), dim3(256), 0, s, dst, src, p, a, b, alpha, beta);
-  } else {
-    // a short unit-stride dimension would leave most of each workgroup idle: run the rows
-    // along the longest dimension instead
-    int in = a;
-    if (st.dims[a] < 32)
-      for (int d = 0; d < st.nd; ++d)
-        if (st.dims[d] > st.dims[in]) in = d;
-    const int64_t rows = total / st.dims[in];
-    if (rows >= ((int64_t)1 << 31)) throw ArgError("strided_copy: box too large");
-    hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)rows), dim3(256), 0, s, dst, src, p, in, alpha, beta);
-  }
-  DCSD_CHECK_LAUNCH();
-}
-
 }  // namespace dcsd
