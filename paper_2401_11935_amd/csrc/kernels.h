@@ -8,6 +8,9 @@
 namespace dcsd {
 
 void fill(double* p, double v, int64_t n, hipStream_t s);
+// X <- (1 - t1^T) X for `batch` n x n matrices (slice stride n2), t1 o x v; false (nothing
+// launched) when o is outside the kernel's range
+bool dress_left(double* X, const double* t1, int n, int o, int v, int64_t n2, int64_t batch, hipStream_t s);
 void axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
 void swap_tu(double* dst, const double* src, int64_t batch, int n, int nc, hipStream_t s);
 void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s);

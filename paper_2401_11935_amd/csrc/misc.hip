@@ -439,4 +439,48 @@ void strided_copy(double* dst, const double* src, const Strided& st, double alph
   DCSD_CHECK_LAUNCH();
 }
 
+// ---------------------------------------------------------------------------
+// Left factor of the T1 dressing of a batch of n x n matrices X (slice stride n2),
+// X <- (1 - t1^T) X with t1 an o x v block (rows/cols 0..o-1 occupied, o..n-1 virtual):
+//   X[o+a][j] -= sum_i t1[i][a] X[i][j]   (a < v, every column j)
+// One HBM stream over the virtual rows; the sum runs in ascending i with fused
+// multiply-adds (the order of the MFMA product it replaces, so results are bitwise equal).
+constexpr int kDressMaxO = 32;
+
+__global__ __launch_bounds__(256) void dress_left_kernel(double* X, const double* t1, int n, int o, int v, int64_t n2,
+                                                         int row_blocks) {
+  __shared__ double ts[kDressMaxO][32];
+  double* S = X + (int64_t)(blockIdx.x / row_blocks) * n2;
+  const int a0 = (int)(blockIdx.x % row_blocks) * 32;
+  const int na = v - a0 < 32 ? v - a0 : 32;
+  for (int e = threadIdx.x; e < o * 32; e += 256) {
+    const int i = e >> 5, cc = e & 31;
+    ts[i][cc] = cc < na ? t1[(int64_t)i * v + a0 + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += 256) {
+    double top[kDressMaxO];
+#pragma unroll
+    for (int i = 0; i < kDressMaxO; ++i) top[i] = i < o ? S[(int64_t)i * n + j] : 0.0;
+#pragma unroll 8
+    for (int a = 0; a < na; ++a) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < kDressMaxO; ++i)
+        if (i < o) acc = __builtin_fma(ts[i][a], top[i], acc);
+      double* p = S + (int64_t)(o + a0 + a) * n + j;
+      *p = *p - acc;
+    }
+  }
+}
+
+bool dress_left(double* X, const double* t1, int n, int o, int v, int64_t n2, int64_t batch, hipStream_t s) {
+  if (o < 1 || o > kDressMaxO || batch <= 0) return false;
+  const int lb = (v + 31) / 32;
+  if (batch * lb >= ((int64_t)1 << 31)) return false;
+  hipLaunchKernelGGL(dress_left_kernel, dim3((unsigned)(batch * lb)), dim3(256), 0, s, X, t1, n, o, v, n2, lb);
+  DCSD_CHECK_LAUNCH();
+  return true;
+}
+
 }  // namespace dcsd

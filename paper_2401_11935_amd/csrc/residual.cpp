@@ -215,7 +215,8 @@ static void dress(Ctx& c, double* X, const double* t1, int64_t batch) {
   const int64_t n2 = c.n2;
   // X[:, 0:o] += X[:, o:n] t1^T
   G(n, o, v).A(X + o, n, false).B(t1, v, false).C(X, n).ab(1.0, 1.0).batch(batch, n2, 0, n2).run(c);
-  // X[o:n, :] -= t1^T X[0:o, :]
+  // X[o:n, :] -= t1^T X[0:o, :]: a streaming kernel (under a tape, a recorded GEMM)
+  if (!t_tape && dress_left(X, t1, n, o, v, n2, batch, c.s)) return;
   G(v, n, o).A(t1, v, true).B(X, n, true).C(X + (int64_t)o * n, n).ab(-1.0, 1.0).batch(batch, 0, n2, n2).run(c);
 }
 
