@@ -100,6 +100,9 @@ struct LpGemm {
   bool k_padded = false;  // every row of A and B holds zeros from K up to a multiple of 8 elements
 };
 void lp_gemm(const LpGemm& g, hipStream_t s);
+// C = alpha A B^T + beta C for M, N <= 16, one batch, A [M][K] and B [N][K] K-contiguous and
+// K >= 65536 (long dot products, split over K into `work`); false (nothing launched) otherwise
+bool gemm_f64_small(const GemmArgs& g, double* work, int64_t work_cap, hipStream_t s);
 // Pair-blocked ladder integrals V2[(p,q)][c][d] (row stride kp) = sum_P BlT[(p,c)][P] BlT[(q,d)][P]
 // for p in [p0, p0+np), q in [q0, q0+nq), in the low precision; BlT rows have stride ldk.
 void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_t p0, int64_t np,

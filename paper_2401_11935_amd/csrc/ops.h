@@ -44,6 +44,9 @@ struct G {
   // workgroups of the tile size that will run (128 when both M and N reach it;
   // the 64-wide kernel is capped at 256 splits, beyond which it ran slower).
   void run(Ctx& c) {
+    // a small output over a long K: dot products streamed over K (outside a tape, whose
+    // adjoint replays the recorded GEMMs)
+    if (!t_tape && a.ksplit == 1 && gemm_f64_small(a, c.gws, c.gws_cap, c.s)) return;
     const double* g_ws = c.gws;
     const int64_t g_ws_cap = c.gws_cap;
     if (a.ksplit == 1 && g_ws && a.K >= 2048) {
