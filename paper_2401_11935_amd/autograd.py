@@ -10,7 +10,10 @@ life of the problem).  Two differentiable maps:
 * ``problem.energies(B, F) -> (E_S, E_T)`` (``DCSDEnergy``): the converged
   correlation energies of the singlet and triplet; backward is
   ``dcsd_backward`` (the lambda equations of the energy Lagrangian, then
-  dE/dB and dE/dF as symmetric matrices).
+  dE/dB and dE/dF as symmetric matrices).  With a fixed-reference method the
+  state not computed comes back as NaN (E_T of a singlet run, E_S of a
+  triplet run) and its gradient weight is ignored: build the loss from the
+  computed state only.
 
 B and F are passed again to each call so that autograd can route gradients
 to them; they must be the tensors the problem was built on.
