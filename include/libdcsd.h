@@ -144,8 +144,10 @@ void dcsd_default_config(dcsd_config* cfg);
 
 /* Builds a context: validates sizes, allocates all device work memory, and
  * forms the constant quantities of Phi_A (one-electron Hamiltonian, Fock
- * matrices, (ov|ov) integrals, reference energy).  hip_stream may be NULL
- * (default stream).  On failure *out is NULL. */
+ * matrices, (ov|ov) integrals, reference energy).  B_dev and F_dev are
+ * borrowed, not copied: they must stay allocated and unchanged until
+ * dcsd_destroy.  hip_stream may be NULL (default stream).  On failure *out is
+ * NULL. */
 dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
                       dcsd_ctx** out);
 

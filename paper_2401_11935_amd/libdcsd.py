@@ -153,8 +153,9 @@ class Pointers:
 class Context:
     """One problem (B, F, sizes) bound to one HIP stream.
 
-    B_ptr, F_ptr, T_ptr, R_ptr are integer addresses; use ``torch_context``
-    for torch tensors."""
+    B_ptr, F_ptr, T_ptr, R_ptr are integer device addresses, e.g. the
+    ``data_ptr()`` of contiguous float64 torch tensors on the GPU; B and F must
+    stay allocated while the context is open."""
 
     def __init__(self, cfg: Config, B_ptr: int, F_ptr: int, stream: int = 0, lib=None):
         self.lib = lib or load()
