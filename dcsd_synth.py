@@ -209,3 +209,39 @@ def sample_indices(count: int, total: int, seed: int) -> np.ndarray:
     """Distinct sorted sample positions of a packed vector (for sampled parity)."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(total, size=min(count, total), replace=False))
+
+
+def subset_inputs(B: np.ndarray, F: np.ndarray, nc: int, keep) -> tuple[np.ndarray, np.ndarray]:
+    """B and F restricted to the orbitals [core | t | u | virt[keep]], where keep
+    holds sorted positions among the nv virtuals."""
+    idx = np.concatenate([np.arange(nc + 2), nc + 2 + np.asarray(keep, dtype=np.int64)])
+    return np.ascontiguousarray(B[:, idx][:, :, idx]), np.ascontiguousarray(F[np.ix_(idx, idx)])
+
+
+def _vir_positions(keep) -> np.ndarray:
+    """Per-spin virtual index (u or t first, then virt) of each virtual of a subset."""
+    return np.concatenate([[0], 1 + np.asarray(keep, dtype=np.int64)])
+
+
+def embed_amplitudes(vec_sub: np.ndarray, nc: int, keep, nv: int) -> np.ndarray:
+    """Packed full-space amplitudes equal to vec_sub (amplitudes over the subset
+    [core | t | u | virt[keep]]) on the kept virtuals and zero elsewhere."""
+    sub = unpack(vec_sub, nc, len(keep))
+    m = _vir_positions(keep)
+    out = np.zeros(amplitude_count(nc, nv))
+    for k, blk in unpack(out, nc, nv).items():
+        if k.startswith("t1"):
+            blk[:, m] = sub[k]
+        else:
+            for i in range(blk.shape[0]):
+                blk[i][:, m[:, None], m[None, :]] = sub[k][i]
+    return out
+
+
+def restrict_amplitudes(vec: np.ndarray, nc: int, nv: int, keep) -> np.ndarray:
+    """The elements of a packed full-space vector whose virtual indices lie on the
+    subset [t | u | virt[keep]], packed for that subset."""
+    full = unpack(vec, nc, nv)
+    m = _vir_positions(keep)
+    return pack({k: (b[:, m] if k.startswith("t1") else b[:, :, m[:, None], m[None, :]]) for k, b in full.items()},
+                nc, len(keep))

@@ -1,0 +1,123 @@
+"""GPU: every term of the residual at full size, element by element, through
+virtual-subset locality.
+
+With T zero outside a subset S of the virtuals, the residual elements whose
+virtual indices lie in {t, u} and S, and W and the energies, equal those of the
+problem restricted to core, t, u and S (each summed virtual index of the
+singles and doubles equations is an amplitude index; pinned on the oracle in
+tests/test_oracle_subset.py).  The library runs at the full sizes, in the
+benchmark's launch configuration (automatic ladder blocking). The oracle runs
+on the reduced problem, which takes seconds. S holds the first and last
+virtuals, those at the 128-wide tile edges of the pair dimension, and random
+ones.  Bars, relative to max(1, magnitude): residual 1e-10 (of max|R|), W and
+energies 1e-11."""
+import sys
+
+import numpy as np
+import pytest
+
+import dcsd_synth as synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_11935_amd import libdcsd
+    libdcsd.load()
+
+
+def _keep(nv: int, seed: int) -> list[int]:
+    # virt position k is pair-dimension index k + 2 (t, u first): tile edges at 128 m
+    edges = [k for m in range(1, nv // 128 + 1) for k in (128 * m - 3, 128 * m - 2) if k < nv]
+    rng = np.random.default_rng(seed)
+    extra = rng.choice(nv, size=18, replace=False).tolist()
+    return sorted(set([0, 1, nv - 2, nv - 1] + edges + extra))
+
+
+def _oracle(method, B, F, nc):
+    if method.startswith("fr-"):
+        from oracle.fixedref import FixedRef
+        _, m, state = method.split("-")
+        return FixedRef(B, F, nc, m, state)
+    from oracle.twodet import TwoDet
+    return TwoDet(B, F, nc, method)
+
+
+CASES = [(synth.MIXED, "dcsd"), (synth.MIXED, "ccsd"), (synth.MIXED, "fr-ccsd-singlet"),
+         (synth.LARGEST, "dcsd")]
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("cfg,method", CASES, ids=[f"{c.name}-{m}" for c, m in CASES])
+def test_full_size_residual_on_virtual_subset(cfg, method):
+    from gpu_util import GpuProblem
+    nc, nv = cfg.nc, cfg.nv
+    say("subset residual", cfg.name, method, "inputs")
+    B, F = synth.make_config_inputs(cfg)
+    keep = _keep(nv, cfg.seed + 31)
+    Bs, Fs = synth.subset_inputs(B, F, nc, keep)
+    Ts = synth.random_amplitudes(nc, len(keep), cfg.seed + 32, 0.05)
+    say("subset residual", cfg.name, method, f"oracle on {len(keep)} virtuals")
+    orc = _oracle(method, Bs, Fs, nc)
+    Rs, Ws = orc.residual(Ts)
+    es = orc.energies(Ts, Ws)
+    T = synth.embed_amplitudes(Ts, nc, keep, nv)
+    say("subset residual", cfg.name, method, "library")
+    p = GpuProblem(B, F, nc, method)
+    R, W = p.residual(T)
+    e = p.energy(T, W)
+    p.close()
+    del T
+    Rsub = synth.restrict_amplitudes(R, nc, nv, keep)
+    err = float(np.abs(Rsub - Rs).max())
+    say(f"  max|dR| = {err:.3e} over {Rs.size} elements (max|R| {np.abs(Rs).max():.3e}), |dW| = {abs(W - Ws):.2e}")
+    assert err <= 1e-10 * max(1.0, float(np.abs(Rs).max()))
+    close = lambda a, b: abs(a - b) <= 1e-11 * max(1.0, abs(b))  # noqa: E731
+    assert close(W, Ws)
+    for k in ("dE_A", "E_ref_A"):
+        assert close(e[k], es[k]), k
+    for k in ("E_S", "E_T"):
+        assert (np.isnan(e[k]) and np.isnan(es[k])) or close(e[k], es[k]), k
+
+
+LOWP_BARS = {"fp32": 2e-6, "bf16": 1e-2}
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_full_size_lowp_residual_on_virtual_subset(precision):
+    """The residual with FP32 or BF16 ladder and ring GEMMs at the metric size (as
+    the benchmark times it), on the virtual subset, against the FP64 oracle of the
+    reduced problem.  Bars as for the low-precision residual at small sizes:
+    2e-6 s (FP32) and 1e-2 s (BF16), s = max(1, max|R|)."""
+    from gpu_util import GpuProblem
+    cfg = synth.MIXED
+    nc, nv = cfg.nc, cfg.nv
+    say("subset lowp residual", precision, "inputs")
+    B, F = synth.make_config_inputs(cfg)
+    keep = _keep(nv, cfg.seed + 41)
+    Bs, Fs = synth.subset_inputs(B, F, nc, keep)
+    Ts = synth.random_amplitudes(nc, len(keep), cfg.seed + 42, 0.05)
+    say("subset lowp residual", precision, f"oracle on {len(keep)} virtuals")
+    Rs, Ws = _oracle("dcsd", Bs, Fs, nc).residual(Ts)
+    T = synth.embed_amplitudes(Ts, nc, keep, nv)
+    say("subset lowp residual", precision, "library")
+    p = GpuProblem(B, F, nc, "dcsd", precision=precision)
+    R, W = p.residual(T)
+    p.close()
+    del T
+    err = float(np.abs(synth.restrict_amplitudes(R, nc, nv, keep) - Rs).max())
+    s = max(1.0, float(np.abs(Rs).max()))
+    say(f"  max|dR| = {err:.3e} (bar {LOWP_BARS[precision] * s:.1e}), |dW| = {abs(W - Ws):.2e}")
+    assert err <= LOWP_BARS[precision] * s
+    assert abs(W - Ws) <= LOWP_BARS[precision] * s
+    assert err > 1e-13  # the low-precision path ran
