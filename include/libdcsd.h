@@ -196,8 +196,11 @@ dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_it
  *   Bbar = the same with respect to every entry of B[naux][n][n] as stored,
  *   Fbar = the same with respect to F[n][n],
  * each output optional (NULL: not computed; Bbar and Fbar NULL skips the pass
- * through the constants).  B and F are differentiated entry by entry, not as
- * symmetric matrices.  Always FP64.  The first call allocates the tape's
+ * through the constants).  T, B and F are differentiated entry by entry as
+ * stored: the packed same-spin doubles hold both t_ij^ab and t_ji^ab (and both
+ * orders of a, b), so Tbar.dT is the derivative along an amplitude change only
+ * for dT with that antisymmetry, and B and F are not treated as symmetric
+ * matrices.  Always FP64.  The first call allocates the tape's
  * cotangent arrays (kept until dcsd_destroy, about the size of the context's
  * work memory again); every call allocates and frees operand snapshots. */
 dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* Rbar_dev, double Wbar, double EAbar,

@@ -121,3 +121,74 @@ def test_full_size_lowp_residual_on_virtual_subset(precision):
     assert err <= LOWP_BARS[precision] * s
     assert abs(W - Ws) <= LOWP_BARS[precision] * s
     assert err > 1e-13  # the low-precision path ran
+
+
+VJP_CASES = [(synth.MIXED, "dcsd"), (synth.MIXED, "fr-ccsd-triplet")]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cfg,method", VJP_CASES, ids=[f"{c.name}-{m}" for c, m in VJP_CASES])
+def test_full_size_residual_vjp_on_virtual_subset(cfg, method):
+    """The residual VJP (dcsd_residual_vjp) at the metric size with T and Rbar on the
+    virtual subset.  The objective Rbar.R + Wbar W + Ebar dE_A then depends on the
+    reduced B, F and T only, so (1) Bbar and Fbar vanish outside the reduced orbital
+    block (bar 1e-10 of their largest entry), and (2) along random directions in the
+    reduced space, Tbar.dT, Bbar.dB and Fbar.dF equal the oracle's complex-step
+    derivatives of the reduced objective (h = 1e-20; relative bar 1e-9)."""
+    import torch
+    from paper_2401_11935_amd import libdcsd as L
+    from gpu_util import stream, to_dev
+    nc, nv = cfg.nc, cfg.nv
+    say("subset vjp", cfg.name, method, "inputs")
+    B, F = synth.make_config_inputs(cfg)
+    keep = _keep(nv, cfg.seed + 51)
+    idx = np.concatenate([np.arange(nc + 2), nc + 2 + np.asarray(keep)])
+    Bs, Fs = synth.subset_inputs(B, F, nc, keep)
+    Ts = synth.random_amplitudes(nc, len(keep), cfg.seed + 52, 0.05)
+    orc = _oracle(method, Bs, Fs, nc)
+    rng = np.random.default_rng(cfg.seed + 53)
+    Rbar_s = rng.normal(size=Ts.size)
+    Rbar_s[orc.ab] = 0.0
+    Wbar, Ebar = 0.7, -1.3
+
+    say("subset vjp", cfg.name, method, "library")
+    Bd, Fd = to_dev(B), to_dev(F)
+    ctx = L.Context(L.default_config(nc=nc, nv=nv, naux=cfg.naux, method=method), Bd.data_ptr(), Fd.data_ptr(),
+                    stream())
+    Td = to_dev(synth.embed_amplitudes(Ts, nc, keep, nv))
+    Rb = to_dev(synth.embed_amplitudes(Rbar_s, nc, keep, nv))
+    Tb, Bb, Fb = torch.empty_like(Td), torch.empty_like(Bd), torch.empty_like(Fd)
+    ctx.residual_vjp(Td.data_ptr(), Rb.data_ptr(), Wbar, Ebar, Tb.data_ptr(), Bb.data_ptr(), Fb.data_ptr())
+    ctx.close()
+    Tb_s = synth.restrict_amplitudes(Tb.cpu().numpy(), nc, nv, keep)
+    Bb, Fb = Bb.cpu().numpy(), Fb.cpu().numpy()
+    del Td, Rb, Tb, Bd, Fd
+    Bb_s, Fb_s = Bb[:, idx][:, :, idx], Fb[np.ix_(idx, idx)]
+    Bb[:, idx[:, None], idx[None, :]] = 0.0
+    Fb[np.ix_(idx, idx)] = 0.0
+    say(f"  outside the reduced block: max|Bbar| {np.abs(Bb).max():.2e} (inside {np.abs(Bb_s).max():.2e}), "
+        f"max|Fbar| {np.abs(Fb).max():.2e} (inside {np.abs(Fb_s).max():.2e})")
+    assert np.abs(Bb).max() <= 1e-10 * np.abs(Bb_s).max()
+    assert np.abs(Fb).max() <= 1e-10 * np.abs(Fb_s).max()
+    del Bb, Fb
+
+    def objective(p, T):
+        R, W = p.residual(T)
+        return Rbar_s @ R + Wbar * W + Ebar * p.energy_A(T)
+
+    h = 1e-20
+    # a direction of amplitudes: same-spin doubles antisymmetric, the A->B double zero (Tbar is
+    # the derivative with respect to the packed entries, which include both (i,j) and (j,i))
+    dT = synth.random_amplitudes(nc, len(keep), cfg.seed + 54, 1.0)
+    dB = rng.normal(size=Bs.shape)
+    dB = 0.5 * (dB + dB.transpose(0, 2, 1))
+    dF = rng.normal(size=Fs.shape)
+    dF = 0.5 * (dF + dF.T)
+    for name, an, make in (("T", float(Tb_s @ dT), lambda: objective(orc, Ts + 1j * h * dT)),
+                           ("B", float((Bb_s * dB).sum()), lambda: objective(_oracle(method, Bs + 1j * h * dB, Fs, nc), Ts)),
+                           ("F", float((Fb_s * dF).sum()), lambda: objective(_oracle(method, Bs + 0j, Fs + 1j * h * dF, nc), Ts))):
+        say("subset vjp", cfg.name, method, "oracle complex step", name)
+        cs = float(np.imag(make())) / h
+        rel = abs(cs - an) / max(abs(cs), 1e-12)
+        say(f"  {name}: oracle {cs:.12e} vjp {an:.12e} rel {rel:.1e}")
+        assert rel <= 1e-9
