@@ -97,7 +97,8 @@ enum {
 };
 
 typedef struct {
-  int32_t nc, nv, naux;   /* core (doubly occupied) orbitals, virtuals, DF rank */
+  int32_t nc, nv, naux;   /* core (doubly occupied) orbitals, virtuals, DF rank;
+                             nc >= 0, nv >= 1, naux >= 1 (else DCSD_ERR_ARG) */
   int32_t method;         /* DCSD_METHOD_*                                      */
   int32_t precision;      /* DCSD_PREC_FP64, DCSD_PREC_FP32 or DCSD_PREC_BF16   */
   int32_t diis_dim;       /* DIIS subspace size (0 = plain Jacobi)              */
