@@ -282,7 +282,9 @@ dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t 
  * (B_dev[n + k*ldb]) or k-contiguous otherwise (B_dev[n*ldb + k]); C is M x N
  * row-major with leading dimension ldc and is read when beta != 0.  ksplit > 1
  * splits K into that many chunks summed by a second kernel (the library
- * allocates and frees the partial sums).  Returns DCSD_ERR_ARG on
+ * allocates and frees the partial sums).  With ksplit = 1, outputs of at most
+ * 16 x 16 over K >= 65536 with both operands k-contiguous take the split dot
+ * product kernels, as in the method's products.  Returns DCSD_ERR_ARG on
  * non-positive sizes, ksplit < 1 or leading dimensions smaller than the
  * stored extents. */
 dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const double* A_dev, int64_t lda,

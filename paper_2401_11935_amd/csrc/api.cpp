@@ -305,12 +305,19 @@ dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const dou
     g.C = C_dev; g.ldc = ldc; g.c_nc = true;
     g.alpha = alpha; g.beta = beta;
     g.ksplit = ksplit;
-    if (ksplit > 1) {
-      if (hipMalloc((void**)&w, (size_t)ksplit * M * ldc * sizeof(double)) != hipSuccess)
-        throw dcsd::HipError("allocation failed");
-      g.work = w;
+    // the library's dispatch: small outputs over a long K take the split dot products
+    const int64_t small = ksplit == 1 ? dcsd::gemm_f64_small_work(g) : 0;
+    if (small > 0) {
+      if (hipMalloc((void**)&w, (size_t)small * sizeof(double)) != hipSuccess) throw dcsd::HipError("allocation failed");
+      if (!dcsd::gemm_f64_small(g, w, small, st)) throw dcsd::HipError("small-output product refused");
+    } else {
+      if (ksplit > 1) {
+        if (hipMalloc((void**)&w, (size_t)ksplit * M * ldc * sizeof(double)) != hipSuccess)
+          throw dcsd::HipError("allocation failed");
+        g.work = w;
+      }
+      dcsd::gemm_f64(g, st);
     }
-    dcsd::gemm_f64(g, st);
     if (hipStreamSynchronize(st) != hipSuccess) st_out = DCSD_ERR_HIP;
   } catch (const dcsd::ArgError&) {
     st_out = DCSD_ERR_ARG;

@@ -13,6 +13,7 @@ namespace dcsd {
 namespace {
 
 constexpr int kSmall = 16, kSlice = 128;
+constexpr int64_t kChunk = 2048;  // K per workgroup of the first kernel (a multiple of kSlice)
 
 __global__ __launch_bounds__(256) void small_dots_kernel(const double* A, int64_t lda, const double* B, int64_t ldb,
                                                          int M, int N, int64_t K, int64_t kchunk, double* W) {
@@ -62,12 +63,17 @@ __global__ __launch_bounds__(256) void small_reduce_kernel(const double* W, doub
 
 }  // namespace
 
-bool gemm_f64_small(const GemmArgs& g, double* work, int64_t work_cap, hipStream_t s) {
+int64_t gemm_f64_small_work(const GemmArgs& g) {
   if (g.M < 1 || g.N < 1 || g.M > kSmall || g.N > kSmall || g.batch != 1 || g.a_mc || g.b_nc || g.K < 65536)
-    return false;
-  const int64_t kchunk = 2048;
-  const int64_t nsplit = (g.K + kchunk - 1) / kchunk;
-  if (!work || nsplit * g.M * g.N > work_cap || nsplit >= ((int64_t)1 << 31)) return false;
+    return 0;
+  const int64_t nsplit = (g.K + kChunk - 1) / kChunk;
+  return nsplit < ((int64_t)1 << 31) ? nsplit * g.M * g.N : 0;
+}
+
+bool gemm_f64_small(const GemmArgs& g, double* work, int64_t work_cap, hipStream_t s) {
+  const int64_t need = gemm_f64_small_work(g);
+  if (need == 0 || !work || need > work_cap) return false;
+  const int64_t kchunk = kChunk, nsplit = (g.K + kchunk - 1) / kchunk;
   hipLaunchKernelGGL(small_dots_kernel, dim3((unsigned)nsplit), dim3(256), 0, s, g.A, g.lda, g.B, g.ldb, (int)g.M,
                      (int)g.N, g.K, kchunk, work);
   DCSD_CHECK_LAUNCH();

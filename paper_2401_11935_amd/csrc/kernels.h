@@ -102,6 +102,8 @@ struct LpGemm {
 void lp_gemm(const LpGemm& g, hipStream_t s);
 // C = alpha A B^T + beta C for M, N <= 16, one batch, A [M][K] and B [N][K] K-contiguous and
 // K >= 65536 (long dot products, split over K into `work`); false (nothing launched) otherwise
+// Work (doubles) gemm_f64_small needs for g; 0 if g is not a small-output product it takes.
+int64_t gemm_f64_small_work(const GemmArgs& g);
 bool gemm_f64_small(const GemmArgs& g, double* work, int64_t work_cap, hipStream_t s);
 // Pair-blocked ladder integrals V2[(p,q)][c][d] (row stride kp) = sum_P BlT[(p,c)][P] BlT[(q,d)][P]
 // for p in [p0, p0+np), q in [q0, q0+nq), in the low precision; BlT rows have stride ldk.

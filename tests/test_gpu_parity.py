@@ -65,7 +65,12 @@ LAYOUTS = [(1536, 1536, 37, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1408, 100, 1, 1, 3,
            (1536, 1536, 40, 0, 1, 1, 1.0, 0.5, 0, 0), (1536, 1536, 64, 0, 0, 3, 1.0, 0.0, 0, 0),
            (1536, 1280, 34, 1, 0, 1, 2.0, 0.0, 2, 0), (1501, 1527, 50, 0, 0, 1, -0.5, 1.0, 4, 0),
            (1500, 1530, 26, 0, 1, 2, 1.0, 1.0, 0, 0), (1500, 1530, 120, 1, 1, 8, 0.5, 1.0, 0, 0),
-           (338, 1024, 1000, 0, 0, 16, 1.0, 0.0, 0, 0)]
+           (338, 1024, 1000, 0, 0, 16, 1.0, 0.0, 0, 0),
+           # small outputs over a long K (split dot products): full, ragged, single row and
+           # column, padded rows, an 8-byte shifted base, K not a multiple of the 2048 chunk
+           (16, 16, 65536, 0, 0, 1, 1.0, 0.0, 0, 0), (13, 13, 67769, 0, 0, 1, 1.0, 1.0, 0, 0),
+           (1, 16, 100003, 0, 0, 1, -0.5, 0.0, 3, 1), (16, 1, 70001, 0, 0, 1, 2.0, 0.5, 0, 1),
+           (7, 11, 131073, 0, 0, 1, 1.0, 0.0, 5, 0)]
 
 
 @pytest.mark.parametrize("M,N,K,a_mc,b_nc,ks,alpha,beta,pad,shift", LAYOUTS)
