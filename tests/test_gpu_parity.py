@@ -104,7 +104,8 @@ def test_gemm_layouts_match_numpy(M, N, K, a_mc, b_nc, ks, alpha, beta, pad, shi
 
 SMALL = [(2, 5, 13, "dcsd", 0), (2, 5, 13, "ccsd", 0), (0, 4, 7, "dcsd", 0), (0, 6, 9, "ccsd", 3),
          (3, 7, 11, "dcsd", 4), (3, 7, 11, "ccsd", 5), (1, 9, 17, "dcsd", 2), (4, 3, 5, "ccsd", 1),
-         (5, 40, 37, "dcsd", 16), (6, 33, 70, "ccsd", 0)]
+         (5, 40, 37, "dcsd", 16), (6, 33, 70, "ccsd", 0),
+         (32, 2, 10, "dcsd", 0)]  # o = 33: more occupied orbitals than the T1-dressing kernel takes
 
 
 @pytest.mark.parametrize("nc,nv,naux,method,lb", SMALL)
