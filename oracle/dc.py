@@ -24,8 +24,9 @@ dropped terms cancel).  The reading is listed among the readings of the
 paper in the design notes.
 
 Pinned by: the dropped terms vanish identically for every two-electron
-input and random T2 (tests/test_oracle_dc.py); converged 2D-DCSD reproduces
-two-electron FCI.
+input and random T2, and beyond two electrons the four terms add up to the
+T2*T2 part of the CCSD residual (tests/test_oracle_dc.py); converged 2D-DCSD
+reproduces two-electron FCI.
 """
 from __future__ import annotations
 

@@ -45,3 +45,29 @@ def test_dropped_terms_nonzero_beyond_two_electrons():
     # antisymmetric like any doubles residual
     assert np.abs(D + D.swapaxes(0, 1)).max() < 1e-15
     assert np.abs(D + D.swapaxes(2, 3)).max() < 1e-15
+
+
+@pytest.mark.parametrize("nc,nv,seed", [(2, 5, 5), (3, 4, 6)])
+def test_quadratic_terms_are_the_ccsd_t2_t2_part(nc, nv, seed):
+    """Beyond two electrons: with T1 = 0 the CCSD doubles residual is quadratic in T2,
+    so R(2t) - 2R(t) + R(0) = 2 (its T2*T2 part), and that part is Q_a + Q_b + Q_c + Q_d.
+    The CCSD residual is pinned to brute force, so this ties the four terms the DC
+    selection splits to the exact equations where an index or factor error in one of
+    them need not show with two electrons; a planted half factor in Q_c fails it."""
+    from oracle.ccsd import SlabSource, ccsd_residual, integrals
+    B, F = synth.make_inputs(nc, nv, 20, seed)
+    ham = Hamiltonian(B, F, nc)
+    ints, slabs = integrals(ham), SlabSource(ham)
+    vec = synth.random_amplitudes(nc, nv, seed + 20, 0.1)
+    blocks = synth.unpack(vec, nc, nv)
+    blocks["t1a"][:] = 0.0
+    blocks["t1b"][:] = 0.0
+    t1, t2 = ham.to_so(vec)
+    R2 = lambda s: ccsd_residual(ham, t1, s * t2, ints, slabs)[1]  # noqa: E731
+    quad = 0.5 * (R2(2.0) - 2.0 * R2(1.0) + R2(0.0))
+    q = quadratic_terms(ints["oovv"], ham.direct(ham.O, ham.O, ham.V, ham.V), t2)
+    total = q["Qa"] + q["Qb"] + q["Qc"] + q["Qd"]
+    assert np.abs(total).max() > 1e-3
+    assert np.abs(quad - total).max() < 1e-12
+    planted = q["Qa"] + q["Qb"] + 0.5 * q["Qc"] + q["Qd"]
+    assert np.abs(quad - planted).max() > 1e-4
