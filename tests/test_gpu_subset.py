@@ -53,7 +53,7 @@ def _oracle(method, B, F, nc):
 
 
 CASES = [(synth.MIXED, "dcsd"), (synth.MIXED, "ccsd"), (synth.MIXED, "fr-ccsd-singlet"),
-         (synth.LARGEST, "dcsd")]
+         (synth.LARGEST, "dcsd"), (synth.LARGEST, "ccsd")]
 
 
 @pytest.mark.timeout(400)
