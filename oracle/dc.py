@@ -25,8 +25,12 @@ paper in the design notes.
 
 Pinned by: the dropped terms vanish identically for every two-electron
 input and random T2, and beyond two electrons the four terms add up to the
-T2*T2 part of the CCSD residual (tests/test_oracle_dc.py); converged 2D-DCSD
-reproduces two-electron FCI.
+T2*T2 part of the CCSD residual (tests/test_oracle_dc.py); on a closed-shell
+state the kept T2*T2 terms reduce to the closed-shell distinguishable-cluster
+form (Coulomb-type (kc|ld) only, contravariant 2T - T^T amplitudes, the direct
+ring whole and the two Fock-like terms halved), which fixes which half of Q_b
+is kept; converged 2D-DCSD reproduces two-electron FCI and is size consistent
+(tests/test_oracle_size_consistency.py).
 """
 from __future__ import annotations
 

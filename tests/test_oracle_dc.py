@@ -71,3 +71,90 @@ def test_quadratic_terms_are_the_ccsd_t2_t2_part(nc, nv, seed):
     assert np.abs(quad - total).max() < 1e-12
     planted = q["Qa"] + q["Qb"] + 0.5 * q["Qc"] + q["Qd"]
     assert np.abs(quad - planted).max() > 1e-4
+
+
+def _closed_shell_problem(no: int, nv: int, seed: int):
+    """A closed-shell system in spin orbitals, written out from the definitions:
+    spatial integrals (pq|rs) = sum_P B[P,p,q] B[P,r,s] with B symmetric in p,q;
+    spin-orbital lists occ = [alpha 0..no-1, beta 0..no-1], vir likewise;
+    <kl|cd> = (kc|ld) delta(s_k,s_c) delta(s_l,s_d).  The spin-orbital doubles of a
+    closed-shell state follow from one spatial T with T_ij^ab = T_ji^ba:
+    t(i s, j s', a s, b s') = T_ij^ab and t(i s, j s', a s', b s) = -T_ij^ba."""
+    rng = np.random.default_rng(seed)
+    n = no + nv
+    B = rng.normal(0.0, 0.3, (12, n, n))
+    B = B + B.transpose(0, 2, 1)
+    ovov = np.einsum("Pkc,Pld->kcld", B[:, :no, no:], B[:, :no, no:])
+    T = rng.normal(0.0, 0.1, (no, no, nv, nv))
+    T = T + T.transpose(1, 0, 3, 2)
+    so = np.array([0] * no + [1] * no)
+    sv = np.array([0] * nv + [1] * nv)
+    occ = np.concatenate([np.arange(no), np.arange(no)])
+    vir = np.concatenate([np.arange(nv), np.arange(nv)])
+    direct = (ovov[occ][:, vir][:, :, occ][:, :, :, vir].transpose(0, 2, 1, 3)
+              * (so[:, None, None, None] == sv[None, None, :, None])
+              * (so[None, :, None, None] == sv[None, None, None, :]))
+    asym = direct - direct.transpose(0, 1, 3, 2)
+    same = lambda x, y: (x[:, None] == y[None, :])  # noqa: E731
+    t2 = (T[occ][:, occ][:, :, vir][:, :, :, vir]
+          * same(so, sv)[:, None, :, None] * same(so, sv)[None, :, None, :]
+          - T[occ][:, occ][:, :, vir][:, :, :, vir].transpose(0, 1, 3, 2)
+          * same(so, sv)[:, None, None, :] * same(so, sv)[None, :, :, None])
+    return T, ovov, direct, asym, t2
+
+
+class _ClosedShellIntegrals:
+    """The two integral lists dropped_terms reads, for the closed-shell system."""
+
+    def __init__(self, direct, asym):
+        self._d, self._a = direct, asym
+        self.O = self.V = None
+
+    def direct(self, *_):
+        return self._d
+
+    def asym(self, *_):
+        return self._a
+
+
+@pytest.mark.parametrize("no,nv,seed", [(3, 4, 1), (4, 5, 2)])
+def test_closed_shell_reduction_fixes_the_kept_ring(no, nv, seed):
+    """Beyond two electrons: on a closed-shell state the T2*T2 part of the DCSD doubles
+    residual must reduce to the closed-shell distinguishable-cluster form, with the
+    contravariant amplitudes T~_ij^ab = 2 T_ij^ab - T_ij^ba and only Coulomb-type
+    (kc|ld) integrals joining the two amplitudes, each term symmetrised by
+    P(ia,jb) X_ij^ab = X_ij^ab + X_ji^ba:
+
+        1/2 P(ia,jb) [ sum T~_ik^ac (kc|ld) T~_lj^db            (the direct ring)
+                      - sum T~_il^cd (kc|ld) T_kj^ab            (half the hole Fock-like term)
+                      - sum T~_kl^ca (kc|ld) T_ij^db ]          (half the particle one)
+
+    while CCSD also has sum (kc|ld) T_ij^cd T_kl^ab and the exchange ring.  The
+    two-electron identities cannot tell the direct ring from the exchange one (both
+    equal B there); this reduction can: keeping the exchange half of Q_b instead
+    gives a different closed-shell form, so a swap in the DC selection fails here."""
+    T, ovov, direct, asym, t2 = _closed_shell_problem(no, nv, seed)
+    q = quadratic_terms(asym, direct, t2)
+    dropped = dropped_terms(_ClosedShellIntegrals(direct, asym), t2)
+    kept = q["Qa"] + q["Qb"] + q["Qc"] + q["Qd"] - dropped
+    ab = lambda X: X[:no, no:, :nv, nv:]  # noqa: E731  alpha-beta block
+    aa = lambda X: X[:no, :no, :nv, :nv]  # noqa: E731
+
+    Tt = 2.0 * T - T.transpose(0, 1, 3, 2)
+    sym = lambda X: X + X.transpose(1, 0, 3, 2)  # noqa: E731  P(ia,jb)
+    ring = np.einsum("ikac,kcld,ljdb->ijab", Tt, ovov, Tt)
+    hole = np.einsum("ilcd,kcld,kjab->ijab", Tt, ovov, T)
+    part = np.einsum("klca,kcld,ijdb->ijab", Tt, ovov, T)
+    expect = 0.5 * sym(ring - hole - part)
+    scale = np.abs(expect).max()
+    assert scale > 1e-2
+    assert np.abs(ab(kept) - expect).max() < 1e-13 * scale
+    # the same-spin block is the antisymmetrised opposite-spin one (a singlet)
+    assert np.abs(aa(kept) - (ab(kept) - ab(kept).transpose(0, 1, 3, 2))).max() < 1e-13 * scale
+    # the direct half of Q_b alone is the closed-shell ring
+    assert np.abs(ab(q["Qb_dir"]) - 0.5 * sym(ring)).max() < 1e-13 * scale
+    # planted swap: keep the exchange half of Q_b and drop the direct one
+    swapped = q["Qa"] + q["Qb"] + q["Qc"] + q["Qd"] - (q["Qa"] + q["Qb_dir"] + 0.5 * q["Qc"] + 0.5 * q["Qd"])
+    assert np.abs(ab(swapped) - expect).max() > 1e-2 * scale
+    # and CCSD: the full four terms carry the (kc|ld) T_ij^cd T_kl^ab ladder-like term
+    assert np.abs(ab(q["Qa"]) - np.einsum("ijcd,kcld,klab->ijab", T, ovov, T)).max() < 1e-13 * scale
