@@ -258,7 +258,7 @@ def adjoint_timing(L, torch, args, Bd, Fd, stream):
     through the constants to B and F; each call re-records the tape (one
     forward residual plus the constants)."""
     base = dict(nc=args.nc, nv=args.nv, naux=args.naux, method=args.method, ladder_block=args.ladder_block)
-    ctx = L.Context(L.default_config(max_iter=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
+    ctx = L.Context(L.default_config(max_iter=1, adjoint=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
     T = torch.zeros(ctx.size, dtype=torch.float64, device=Bd.device)
     ctx.solve(T.data_ptr())
     Rbar = torch.randn(ctx.size, dtype=torch.float64, device=Bd.device, generator=torch.Generator(Bd.device).manual_seed(7))
@@ -270,7 +270,7 @@ def adjoint_timing(L, torch, args, Bd, Fd, stream):
     ctx.residual(T.data_ptr(), R.data_ptr())
     out["forward_residual_ms"] = 1e3 * (time.perf_counter() - t0)
     for name, full in (("vjp_amplitudes_ms", False), ("vjp_full_ms", True)):
-        for rep in range(2):  # the first call allocates the cotangent arrays
+        for rep in range(2):  # the first call loads the sweep's kernels
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             ctx.residual_vjp(T.data_ptr(), Rbar.data_ptr(), 0.5, 1.0, Tb.data_ptr(),
@@ -341,8 +341,11 @@ def main():
         torch.cuda.synchronize()
         print(f"bench: calibration copy of {args.copy_calibration_mib} MiB done", file=sys.stderr, flush=True)
         del src, dst
+    # the divergence guard stays off here: these iterations diverge (see solver_note) and
+    # every step must be a full solver step
     cfg = L.default_config(nc=nc, nv=nv, naux=naux, method=args.method, max_iter=max(args.warmup, 1),
-                           ladder_block=args.ladder_block, precond=args.precond, level_shift=args.level_shift)
+                           ladder_block=args.ladder_block, precond=args.precond, level_shift=args.level_shift,
+                           guard_iters=0)
     t0 = time.perf_counter()
     ctx = L.Context(cfg, Bd.data_ptr(), Fd.data_ptr(), stream)
     torch.cuda.synchronize()

@@ -27,6 +27,16 @@ import numpy as np
 
 SIGMA_B = 0.05          # standard deviation of the DF factors
 SIGMA_F_OFF = 1.0e-3    # standard deviation of off-diagonal Fock elements
+# Weak-integral variants: DF factors with naux * sigma^2 = 0.015 Eh, the mean
+# exchange integral (pq|qp).  With sigma = 0.05 that mean is 1.5 Eh (nc=8, nv=200)
+# or 3 Eh (nc=12, nv=400): far stronger correlation than a molecule's, and the
+# amplitude iterations diverge.  At 0.015 Eh the correlation energies are
+# molecule-sized (about -0.4 and -1.7 Eh) and the iterations converge.
+WEAK_EXCHANGE = 0.015
+
+
+def weak_sigma(naux: int) -> float:
+    return float(np.sqrt(WEAK_EXCHANGE / naux))
 
 
 @dataclass(frozen=True)
@@ -36,6 +46,7 @@ class Config:
     nv: int
     naux: int
     seed: int
+    sigma: float = SIGMA_B
 
     @property
     def n(self) -> int:
@@ -57,6 +68,11 @@ ADJOINT = Config("adjoint", nc=8, nv=200, naux=600, seed=1)
 MIXED = Config("mixed", nc=12, nv=400, naux=1200, seed=2)
 LARGEST = Config("largest", nc=20, nv=600, naux=1800, seed=3)
 CONFIGS = {c.name: c for c in (TINY, MEDIUM, ADJOINT, MIXED, LARGEST)}
+# The same shapes and seeds with weak integrals (added configurations).
+MEDIUM_WEAK = Config("medium-weak", nc=8, nv=200, naux=600, seed=1, sigma=weak_sigma(600))
+MIXED_WEAK = Config("mixed-weak", nc=12, nv=400, naux=1200, seed=2, sigma=weak_sigma(1200))
+LARGEST_WEAK = Config("largest-weak", nc=20, nv=600, naux=1800, seed=3, sigma=weak_sigma(1800))
+WEAK_CONFIGS = {c.name: c for c in (MEDIUM_WEAK, MIXED_WEAK, LARGEST_WEAK)}
 
 
 def amplitude_count(nc: int, nv: int) -> int:
@@ -117,22 +133,23 @@ def _fock(rng, nc: int, nv: int) -> np.ndarray:
     return F
 
 
-def make_inputs(nc: int, nv: int, naux: int, seed: int):
+def make_inputs(nc: int, nv: int, naux: int, seed: int, sigma: float = SIGMA_B):
     """DF factors B[P,p,q] (naux, n, n) and spin-averaged Fock F (n, n).
 
-    B entries ~ N(0, 0.05^2), symmetric in (p,q); F diagonal: core U[-2,-0.5],
-    t and u U[-0.4,-0.2], virtuals U[0.2,3]; off-diagonal N(0, 1e-3^2),
-    symmetric.  Generator: numpy PCG64 seeded with ``seed``; B is drawn first.
+    B entries ~ N(0, sigma^2) (0.05 unless given), symmetric in (p,q); F
+    diagonal: core U[-2,-0.5], t and u U[-0.4,-0.2], virtuals U[0.2,3];
+    off-diagonal N(0, 1e-3^2), symmetric.  Generator: numpy PCG64 seeded with
+    ``seed``; B is drawn first.
     """
     rng = np.random.default_rng(seed)
     n = nc + 2 + nv
-    B = _symmetric_draw(rng, naux, n, SIGMA_B)
+    B = _symmetric_draw(rng, naux, n, sigma)
     F = _fock(rng, nc, nv)
     return B, F
 
 
 def make_config_inputs(cfg: Config):
-    return make_inputs(cfg.nc, cfg.nv, cfg.naux, cfg.seed)
+    return make_inputs(cfg.nc, cfg.nv, cfg.naux, cfg.seed, cfg.sigma)
 
 
 def make_z2_inputs(nc: int, nv: int, naux: int, seed: int):

@@ -15,7 +15,8 @@
  *   B[P][p][q]  (naux x n x n) DF factors defining (pq|rs) = sum_P B[P,p,q] B[P,r,s];
  *               must be symmetric in p,q.
  *   F[p][q]     (n x n) spin-averaged Fock matrix of the open-shell reference;
- *               the one-electron Hamiltonian is h = F - G_avg[B] (see DESIGN).
+ *               the one-electron Hamiltonian is h = F - G_avg[B] with
+ *               G_avg = sum_core [2 J_k - K_k] + sum_{x = t,u} [J_x - K_x / 2].
  *   Orbital order [core 0..nc-1 | t = nc | u = nc+1 | virtuals], n = nc+2+nv.
  *
  * Packed amplitude / residual vector (length dcsd_amplitude_count), with
@@ -53,9 +54,10 @@ typedef enum {
   DCSD_ERR_ARG = 1,        /* invalid argument or configuration            */
   DCSD_ERR_OOM = 2,        /* device allocation failed in dcsd_init        */
   DCSD_ERR_HIP = 3,        /* HIP runtime error (context becomes unusable) */
-  DCSD_ERR_NOCONV = 4,     /* dcsd_solve reached max_iter                  */
+  DCSD_ERR_NOCONV = 4,     /* not converged (max_iter or divergence guard) */
   DCSD_ERR_NONFINITE = 5,  /* a residual contained Inf/NaN                 */
-  DCSD_ERR_STATE = 6       /* call on a context in an error state          */
+  DCSD_ERR_STATE = 6       /* context in an error state, or adjoint call
+                              on a context built without cfg.adjoint     */
 } dcsd_status;
 
 /* Methods.  2D-DCSD and 2D-CCSD solve the two-determinant equations (Theory
@@ -112,6 +114,17 @@ typedef struct {
   int32_t refresh_every;  /* low precision only: FP64 residual every k-th iteration of
                              dcsd_solve (0 = only when the corrected residual
                              reaches tol_residual)                               */
+  int32_t adjoint;        /* 1: dcsd_init also reserves the memory of
+                             dcsd_residual_vjp and dcsd_backward (tape operand
+                             snapshots, cotangent arrays, sweep work space), so
+                             that those calls allocate nothing; 0: those calls
+                             return DCSD_ERR_STATE                               */
+  int32_t guard_iters;    /* divergence guard of dcsd_solve: after this many
+                             consecutive growths of max |R| the DIIS history is
+                             cleared, the level shift raised to 2 shift + 1 and
+                             the iterations restart from the best amplitudes;
+                             the third such event ends the solve with
+                             DCSD_ERR_NOCONV (0 = off)                           */
 } dcsd_config;
 
 typedef struct {
@@ -128,8 +141,10 @@ typedef struct {
 typedef struct {
   int32_t iterations; /* residual evaluations performed                      */
   int32_t converged;  /* 1 if max |R| <= tol_residual                        */
-  double res_max;     /* max |R| of the last residual                        */
-  dcsd_energies e;    /* energies of the last amplitudes                     */
+  double res_max;     /* max |R| of the residual the report describes        */
+  double res_rms;     /* root mean square of that residual over the packed
+                         vector (sqrt(sum R^2 / dcsd_amplitude_count))       */
+  dcsd_energies e;    /* energies of the amplitudes the report describes     */
   int32_t fp64;       /* 1 if res_max and e come from an FP64 residual (every
                          record in FP64 mode; refresh records otherwise)     */
 } dcsd_report;
@@ -140,15 +155,21 @@ typedef void (*dcsd_iter_cb)(const dcsd_report* it, void* user);
 int64_t dcsd_amplitude_count(int32_t nc, int32_t nv);
 
 /* Fills *cfg with defaults (DCSD, FP64, DIIS 8 from iteration 2, max_iter 200,
- * tol 1e-10, no shift, all terms). */
+ * tol 1e-10, no shift, all terms, no adjoint reservation, guard_iters 10). */
 void dcsd_default_config(dcsd_config* cfg);
 
-/* Builds a context: validates sizes, allocates all device work memory, and
- * forms the constant quantities of Phi_A (one-electron Hamiltonian, Fock
- * matrices, (ov|ov) integrals, reference energy).  B_dev and F_dev are
+/* Builds a context for the reference determinant Phi_A of the open-shell
+ * singlet (Theory section, the two determinants of Fig. 1, with the
+ * Hamiltonian given by the DF factors and the spin-averaged Fock matrix):
+ * validates sizes, allocates all device work memory (with cfg->adjoint, also
+ * that of the adjoint, sized by recording one residual at T = 0), and forms
+ * the constant quantities of Phi_A (one-electron Hamiltonian, spin Fock
+ * matrices, (ov|ov) integrals, reference energy <A|H|A>).  B_dev and F_dev are
  * borrowed, not copied: they must stay allocated and unchanged until
- * dcsd_destroy.  hip_stream may be NULL (default stream).  On failure *out is
- * NULL. */
+ * dcsd_destroy.  hip_stream may be NULL (default stream).  Returns
+ * DCSD_ERR_ARG on invalid sizes or settings, DCSD_ERR_OOM when device memory
+ * runs out; on failure *out is NULL and dcsd_last_error(NULL) gives the
+ * reason. */
 dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
                       dcsd_ctx** out);
 
@@ -161,17 +182,30 @@ dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double*
  * synchronises; otherwise it is asynchronous. */
 dcsd_status dcsd_residual(dcsd_ctx* ctx, const double* T_dev, double* R_dev, double* W_host);
 
-/* Energies for amplitudes T and coupling W (W as returned by dcsd_residual
- * for the same T): dE_A, E_S = dE_A + W, E_T = dE_A - W, E_ref_A (the
- * fixed-reference methods as described at DCSD_METHOD_*).  Synchronises. */
-dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energies* out);
+/* Energies of amplitudes T (Theory section: the single-reference energy
+ * expression dE_A of Phi_A, the effective coupling W = the Phi_A -> Phi_B
+ * element of the doubles residual at T, and the 2x2 effective Hamiltonian
+ * [[dE_A, W], [W, dE_A]] whose roots are E_S = dE_A + W and E_T = dE_A - W),
+ * plus E_ref_A = <A|H|A>.  W is computed from T itself by one FP64 residual
+ * evaluation into the context's work memory (whatever the precision
+ * setting), so the call costs about one FP64 dcsd_residual; the
+ * fixed-reference methods (W = 0, see DCSD_METHOD_*) need no residual.
+ * T_dev is a packed device vector.  Synchronises.  DCSD_ERR_ARG on NULL
+ * arguments. */
+dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, dcsd_energies* out);
 
 /* Solves the amplitude equations starting from T_inout (zeros = the usual
  * start): Jacobi steps with orbital-energy denominators plus Pulay DIIS, all
  * vectors in FP64 on the device, until max |R| <= tol_residual.  T_inout
- * receives the final amplitudes; *out the final report; cb (may be NULL) is
- * called after every residual evaluation.  Returns DCSD_ERR_NOCONV after
- * max_iter evaluations, DCSD_ERR_NONFINITE on Inf/NaN.
+ * receives the converged amplitudes and *out their report; cb (may be NULL)
+ * is called after every residual evaluation.  Without convergence (max_iter
+ * evaluations, or the divergence guard of cfg.guard_iters giving up) the call
+ * returns DCSD_ERR_NOCONV with the best amplitudes seen in T_inout (smallest
+ * max |R| among FP64 evaluations, or among all evaluations if none was FP64)
+ * and *out describing exactly those amplitudes (iterations = evaluations
+ * performed).  DCSD_ERR_NONFINITE on Inf/NaN (T_inout then holds the best
+ * amplitudes too).  Checkpoint/resume: T is the whole solver state apart from
+ * the DIIS history, which a new call starts afresh.
  *
  * With precision FP32 or BF16 the iterations use the low-precision residual.
  * A refresh evaluates the FP64 residual at the current amplitudes T_r, takes
@@ -201,9 +235,12 @@ dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_it
  * stored: the packed same-spin doubles hold both t_ij^ab and t_ji^ab (and both
  * orders of a, b), so Tbar.dT is the derivative along an amplitude change only
  * for dT with that antisymmetry, and B and F are not treated as symmetric
- * matrices.  Always FP64.  The first call allocates the tape's
- * cotangent arrays (kept until dcsd_destroy, about the size of the context's
- * work memory again); every call allocates and frees operand snapshots. */
+ * matrices.  Always FP64.  Needs a context built with cfg.adjoint = 1
+ * (DCSD_ERR_STATE otherwise); allocates nothing: the tape's snapshots,
+ * cotangent arrays and work space were reserved by dcsd_init (about the
+ * context's work memory again, plus the snapshots).  A term_mask changed
+ * after init whose tape needs more snapshot memory than was reserved gives
+ * DCSD_ERR_ARG. */
 dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* Rbar_dev, double Wbar, double EAbar,
                               double* Tbar_dev, double* Bbar_dev, double* Fbar_dev);
 
@@ -220,7 +257,7 @@ dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* 
  * h (G_pq + G_qp)/2.  *out (may be NULL) reports the lambda iterations.
  * Returns DCSD_ERR_NOCONV (gradient from the last lambda) or
  * DCSD_ERR_NONFINITE like dcsd_solve.  FP64 in every precision setting;
- * allocates like dcsd_residual_vjp.  A fixed-reference run has one state:
+ * needs cfg.adjoint = 1 and allocates nothing, like dcsd_residual_vjp.  A fixed-reference run has one state:
  * E = ebar_S dE_A for a singlet method, ebar_T dE_A for a triplet method (the
  * other weight is ignored). */
 dcsd_status dcsd_backward(dcsd_ctx* ctx, const double* T_dev, double ebar_S, double ebar_T, double* Bbar_dev,
@@ -251,13 +288,19 @@ typedef struct {
   dcsd_kernel_time ring;        /* ring GEMMs (2ov x 2ov and ov x ov blocks)   */
 } dcsd_timing;
 
-/* Starts recording (clears earlier records).  The first call creates the
- * event pool (host-side HIP events, no device memory); at most 16384 events
- * are recorded per start. */
+/* Starts recording (clears earlier records).  Events come from a pool of
+ * host-side HIP events (no device memory) that grows when a recording needs
+ * more, so no interval is dropped. */
 dcsd_status dcsd_timing_start(dcsd_ctx* ctx);
 
 /* Synchronises the stream, stops recording and sums the recorded intervals. */
 dcsd_status dcsd_timing_stop(dcsd_ctx* ctx, dcsd_timing* out);
+
+/* Device memory held by the context: *bytes (may be NULL) receives the bytes
+ * it has allocated, *allocations (may be NULL) the number of device
+ * allocation calls it has made since dcsd_init began.  Both stay constant
+ * after dcsd_init returns (no call allocates), which is what this reports. */
+dcsd_status dcsd_device_memory(const dcsd_ctx* ctx, int64_t* bytes, int64_t* allocations);
 
 /* Message of the last error on this context ("" if none). */
 const char* dcsd_last_error(const dcsd_ctx* ctx);

@@ -13,6 +13,10 @@ to zero reaches the same amplitudes.  The one used on both sides:
   used once ``k >= diis_start``: minimise |sum c_i e_i| with sum c_i = 1 and
   take T = sum c_i T_new_i.
 
+Besides the last step's T the result holds ``T_best``, the evaluated amplitudes
+with the smallest max |R|, which is what the device solver returns when it
+does not converge.
+
 The fixed point does not depend on the shift or on the DIIS settings; the
 iteration path does, so per-iteration comparisons use the same settings.
 """
@@ -42,12 +46,15 @@ def solve(model, tol: float = 1e-10, max_iter: int = 200, diis_dim: int = 8,
     T = np.zeros(model.size) if T0 is None else np.array(T0, dtype=np.float64)
     hist_T, hist_e, records = [], [], []
     converged = False
+    T_best, best = None, None  # the evaluated amplitudes with the smallest max |R|
     for it in range(max_iter):
         R, W = model.residual(T)
         rmax = float(np.max(np.abs(R)))
         e = model.energies(T, W)
         rec = {"iter": it, "res_max": rmax, **e}
         records.append(rec)
+        if np.isfinite(rmax) and (best is None or rmax < best["res_max"]):
+            T_best, best = T.copy(), rec
         if callback is not None:
             callback(rec)
         if not np.isfinite(rmax):
@@ -71,4 +78,4 @@ def solve(model, tol: float = 1e-10, max_iter: int = 200, diis_dim: int = 8,
                 Tn = sum(ci * ti for ci, ti in zip(c, hist_T))
         T = Tn
     return {"T": T, "converged": converged, "iterations": len(records), "records": records,
-            **records[-1]}
+            "T_best": T_best, "best": best, **records[-1]}

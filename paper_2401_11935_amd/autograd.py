@@ -16,7 +16,12 @@ life of the problem).  Two differentiable maps:
   computed state only.
 
 B and F are passed again to each call so that autograd can route gradients
-to them; they must be the tensors the problem was built on.
+to them; they must be the tensors the problem was built on.  The library
+works on the torch stream that was current when the problem was built; every
+call checks that it is still the current stream, so torch's own work on the
+inputs (zero fills, copies) is ordered before the library's.  The context
+reserves the adjoint's memory at construction (``adjoint=1``), so backward
+passes allocate no device memory in the library.
 """
 from __future__ import annotations
 
@@ -34,6 +39,7 @@ class Problem:
         naux, n, _ = B.shape
         self.B, self.F, self.nc = B, F, nc
         self.stream = torch.cuda.current_stream(B.device).cuda_stream
+        config.setdefault("adjoint", 1)
         cfg = L.default_config(nc=nc, nv=n - nc - 2, naux=naux, **config)
         self.ctx = L.Context(cfg, B.data_ptr(), F.data_ptr(), self.stream)
         self.size = self.ctx.size
@@ -43,6 +49,11 @@ class Problem:
     def _check(self, B, F):
         if B.data_ptr() != self.B.data_ptr() or F.data_ptr() != self.F.data_ptr():
             raise ValueError("B and F must be the tensors the problem was built on")
+        self.check_stream()
+
+    def check_stream(self):
+        if torch.cuda.current_stream(self.B.device).cuda_stream != self.stream:
+            raise RuntimeError("the current torch stream differs from the one the problem was built on")
 
     def residual(self, T: torch.Tensor, B: torch.Tensor, F: torch.Tensor):
         self._check(B, F)
@@ -62,7 +73,7 @@ class DCSDResidual(torch.autograd.Function):
         T = T.detach().contiguous()
         R = torch.empty_like(T)
         W = problem.ctx.residual(T.data_ptr(), R.data_ptr())
-        e = problem.ctx.energy(T.data_ptr(), W)["dE_A"]
+        e = problem.ctx.energy(T.data_ptr())["dE_A"]
         ctx.problem = problem
         ctx.save_for_backward(T)
         scal = dict(dtype=torch.float64, device=T.device)
@@ -79,7 +90,7 @@ class DCSDResidual(torch.autograd.Function):
         Bb = torch.empty_like(p.B) if ctx.needs_input_grad[1] else None
         Fb = torch.empty_like(p.F) if ctx.needs_input_grad[2] else None
         ptr = lambda x: 0 if x is None else x.data_ptr()  # noqa: E731
-        torch.cuda.current_stream(T.device).synchronize()
+        p.check_stream()
         p.ctx.residual_vjp(T.data_ptr(), gR.data_ptr(), wbar, ebar, ptr(Tb), ptr(Bb), ptr(Fb))
         return Tb, Bb, Fb, None
 
@@ -101,6 +112,7 @@ class DCSDEnergy(torch.autograd.Function):
     def backward(ctx, gS, gT):
         (T,) = ctx.saved_tensors
         p = ctx.problem
+        p.check_stream()
         Bb, Fb = torch.empty_like(p.B), torch.empty_like(p.F)
         lam = torch.zeros_like(T)
         rep = p.ctx.backward(T.data_ptr(), 0.0 if gS is None else float(gS), 0.0 if gT is None else float(gT),

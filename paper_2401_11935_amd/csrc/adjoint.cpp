@@ -27,6 +27,8 @@ void Tape::clear() {
   snaps.clear();
   ops.clear();
   temp_need = 0;
+  arena_used = 0;
+  need = 0;
 }
 
 namespace {
@@ -59,11 +61,22 @@ const double* tape_value(const double* p, int64_t count) {
   for (const Snapshot& sn : t.snaps)
     if (sn.buf == id && sn.version == b.version && sn.lo <= p && hi <= sn.hi) return sn.copy + (p - sn.lo);
   double* cp = nullptr;
-  if (hipMalloc((void**)&cp, (size_t)count * sizeof(double)) != hipSuccess) {
-    (void)hipGetLastError();
-    throw std::bad_alloc();
+  const int64_t padded = (count + 31) / 32 * 32;  // 256-byte granules
+  t.need += padded;
+  if (t.arena) {
+    if (t.arena_used + padded > t.arena_cap)
+      throw ArgError("adjoint: the tape needs more snapshot memory than dcsd_init reserved");
+    cp = t.arena + t.arena_used;
+    t.arena_used += padded;
+  } else {
+    // only while dcsd_init sizes the reservation
+    ++c.alloc_calls;
+    if (hipMalloc((void**)&cp, (size_t)count * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+    t.scratch.push_back(cp);
   }
-  t.scratch.push_back(cp);
   DCSD_HIP(hipMemcpyAsync(cp, p, (size_t)count * sizeof(double), hipMemcpyDeviceToDevice, c.s));
   t.snaps.push_back({id, b.version, p, hi, cp});
   return cp;
@@ -157,9 +170,28 @@ void Ctx::adj_setup() {
   lam = alloc(total);
 }
 
-void Ctx::record(const double* T) {
+// Reserves everything the adjoint calls need (called by dcsd_init): one
+// recording at T = 0 allocates the cotangent arrays and the sweep's work space
+// and measures the operand snapshots of each tape, which then move into one
+// arena per tape.  The tapes' operation sequence and snapshot sizes depend only
+// on the sizes, the method and the term mask, not on the amplitude values.
+void Ctx::adj_reserve() {
   adj_setup();
-  DCSD_HIP(hipMemcpyAsync(Tin, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+  fill(Tin, 0.0, total, s);
+  record(Tin);
+  for (Tape* t : {&tape_init, &tape_res}) {
+    const int64_t need = t->need;
+    t->clear();
+    t->arena = (double*)alloc_raw((size_t)std::max<int64_t>(need, 32) * sizeof(double));
+    t->arena_cap = std::max<int64_t>(need, 32);
+  }
+  adj_ready = true;
+  DCSD_HIP(hipStreamSynchronize(s));
+}
+
+void Ctx::record(const double* T) {
+  if (!Tin) throw ArgError("adjoint memory was not reserved (set cfg.adjoint at dcsd_init)");
+  if (T != Tin) DCSD_HIP(hipMemcpyAsync(Tin, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
   tape_init.clear();
   tape_res.clear();
   for (auto& b : bufs) {
@@ -202,13 +234,18 @@ void Ctx::record(const double* T) {
   std::vector<std::pair<double*, int64_t>> need_bar;
   for (const auto& b : bufs)
     if (b.used && !b.bar) need_bar.push_back({b.p, b.n});
+  const int64_t vu2 = (int64_t)vu * vu;
+  int64_t need = std::max<int64_t>(2 * (int64_t)lb * lb * vu2, rows_main * ((int64_t)v * v + (int64_t)n * v));
+  need = std::max(need, std::max(tape_init.temp_need, tape_res.temp_need));
+  if (adj_ready) {  // after dcsd_init nothing may be allocated
+    if (!need_bar.empty() || need > temp_cap)
+      throw ArgError("adjoint: the tape needs memory that dcsd_init did not reserve (term_mask changed?)");
+    return;
+  }
   for (const auto& x : need_bar) {
     double* q = alloc(x.second);  // registers q: find the owner afterwards
     bufs[find_buf(x.first)].bar = q;
   }
-  const int64_t vu2 = (int64_t)vu * vu;
-  int64_t need = std::max<int64_t>(2 * (int64_t)lb * lb * vu2, rows_main * ((int64_t)v * v + (int64_t)n * v));
-  need = std::max(need, std::max(tape_init.temp_need, tape_res.temp_need));
   if (need > temp_cap) {
     temp = alloc(need);
     temp_cap = need;
@@ -426,12 +463,15 @@ int Ctx::lambda_solve(double a, double b, double* L, dcsd_report* rep) {
     int zero = 0, bad = 0;
     DCSD_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
     maxabs(Rw, total, scal + 1, flag, part, s);
-    double rmax = 0.0;
+    dot(Rw, Rw, total, scal + 3, part, s);
+    double rmax = 0.0, ss = 0.0;
     DCSD_HIP(hipMemcpyAsync(&rmax, scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    DCSD_HIP(hipMemcpyAsync(&ss, scal + 3, sizeof(double), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipStreamSynchronize(s));
     r.iterations = it + 1;
     r.res_max = rmax;
+    r.res_rms = std::sqrt(std::max(ss, 0.0) / (double)total);
     r.fp64 = 1;
     r.converged = (!bad && rmax <= cfg.tol_residual) ? 1 : 0;
     if (bad || !std::isfinite(rmax)) {

@@ -59,6 +59,8 @@ void dcsd_default_config(dcsd_config* c) {
   c->term_mask = DCSD_TERM_ALL;
   c->precond = DCSD_PRECOND_ORBITAL;
   c->refresh_every = 0;
+  c->adjoint = 0;
+  c->guard_iters = 10;
 }
 
 dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
@@ -103,14 +105,10 @@ dcsd_status dcsd_residual(dcsd_ctx* ctx, const double* T_dev, double* R_dev, dou
   });
 }
 
-dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, double W, dcsd_energies* out) {
+dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, dcsd_energies* out) {
   return guarded(ctx, [&] {
     if (!T_dev || !out) throw dcsd::ArgError("T and out are required");
-    const double e = ctx->c.energy_A(T_dev);
-    out->dE_A = e;
-    out->W = W;
-    dcsd::state_energies(ctx->c.cfg.method, e, W, out->E_S, out->E_T);
-    out->E_ref_A = ctx->c.e_ref;
+    ctx->c.energies(T_dev, out);
     return DCSD_OK;
   });
 }
@@ -130,6 +128,10 @@ dcsd_status dcsd_residual_vjp(dcsd_ctx* ctx, const double* T_dev, const double* 
   return guarded(ctx, [&] {
     if (!T_dev || !Rbar_dev) throw dcsd::ArgError("T and Rbar are required");
     dcsd::Ctx& c = ctx->c;
+    if (!c.adj_ready) {
+      c.err = "the adjoint needs a context built with cfg.adjoint = 1";
+      return DCSD_ERR_STATE;
+    }
     c.record(T_dev);
     c.sweep(Rbar_dev, Wbar, EAbar, Bbar_dev || Fbar_dev);
     if (Tbar_dev) DCSD_HIP(hipMemcpyAsync(Tbar_dev, c.bar(c.Tin), c.total * sizeof(double), hipMemcpyDeviceToDevice, c.s));
@@ -146,6 +148,10 @@ dcsd_status dcsd_backward(dcsd_ctx* ctx, const double* T_dev, double ebar_S, dou
   return guarded(ctx, [&] {
     if (!T_dev || !Bbar_dev || !Fbar_dev) throw dcsd::ArgError("T, Bbar and Fbar are required");
     dcsd::Ctx& c = ctx->c;
+    if (!c.adj_ready) {
+      c.err = "the adjoint needs a context built with cfg.adjoint = 1";
+      return DCSD_ERR_STATE;
+    }
     c.record(T_dev);
     if (lambda_dev)
       DCSD_HIP(hipMemcpyAsync(c.lam, lambda_dev, c.total * sizeof(double), hipMemcpyDeviceToDevice, c.s));
@@ -182,7 +188,9 @@ dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg) {
     if (cfg->nc != c.nc || cfg->nv != c.nv || cfg->naux != c.naux || cfg->method != c.method ||
         cfg->precision != c.precision || cfg->diis_dim != c.diis_dim || cfg->ladder_block != c.ladder_block)
       throw dcsd::ArgError("only solver settings may change after dcsd_init");
+    if (cfg->adjoint != c.adjoint) throw dcsd::ArgError("adjoint is fixed at dcsd_init");
     if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0) || cfg->refresh_every < 0 ||
+        cfg->guard_iters < 0 ||
         (cfg->precond != DCSD_PRECOND_ORBITAL && cfg->precond != DCSD_PRECOND_EN))
       throw dcsd::ArgError("invalid solver settings");
     ctx->c.cfg = *cfg;
@@ -194,7 +202,7 @@ dcsd_status dcsd_timing_start(dcsd_ctx* ctx) {
   return guarded(ctx, [&] {
     dcsd::Ctx& c = ctx->c;
     if (c.pool.empty()) {
-      c.pool.resize(16384);
+      c.pool.resize(4096);
       for (auto& e : c.pool) DCSD_HIP(hipEventCreate(&e));
     }
     DCSD_HIP(hipStreamSynchronize(c.s));
@@ -224,6 +232,13 @@ dcsd_status dcsd_timing_stop(dcsd_ctx* ctx, dcsd_timing* out) {
     if (out) *out = t;
     return DCSD_OK;
   });
+}
+
+dcsd_status dcsd_device_memory(const dcsd_ctx* ctx, int64_t* bytes, int64_t* allocations) {
+  if (!ctx) return DCSD_ERR_ARG;
+  if (bytes) *bytes = (int64_t)ctx->c.bytes;
+  if (allocations) *allocations = ctx->c.alloc_calls;
+  return DCSD_OK;
 }
 
 const char* dcsd_last_error(const dcsd_ctx* ctx) {

@@ -84,7 +84,7 @@ struct Ctx {
   double *Bov = nullptr, *Bvo = nullptr, *Boo = nullptr;
   double *Tsc = nullptr, *Tsf1 = nullptr, *Z = nullptr, *out1 = nullptr, *out2 = nullptr, *fvec = nullptr;
   double *KCBJ = nullptr, *Dvo = nullptr, *KJPQ[2] = {nullptr, nullptr}, *OOOO = nullptr;
-  double *Tmp = nullptr, *Ring = nullptr;
+  double* Ring = nullptr;
   double *Wsf1 = nullptr, *Wsf2 = nullptr, *Rsf1 = nullptr, *Rsf2 = nullptr;
   double *P1 = nullptr, *P2 = nullptr;
   double *Xv[2] = {nullptr, nullptr}, *Yo[2] = {nullptr, nullptr}, *Fvv[2] = {nullptr, nullptr},
@@ -123,6 +123,7 @@ struct Ctx {
   int* flag = nullptr;
   // solver
   double *Tn = nullptr, *Ev = nullptr, *histT = nullptr, *histE = nullptr, *coef = nullptr, *Rw = nullptr;
+  double* Tbest = nullptr;  // best amplitudes of a solve (smallest max |R|)
 
   // timing (HIP events on the context's stream)
   bool timing = false;
@@ -138,7 +139,8 @@ struct Ctx {
   void tend(hipEvent_t a, double flops, int cls);
 
   std::vector<void*> allocs;
-  size_t bytes = 0;
+  size_t bytes = 0;         // device bytes allocated by the context (kept until dcsd_destroy)
+  int64_t alloc_calls = 0;  // device allocation calls made, including the adjoint's sizing pass
 
   // Registry of the FP64 device arrays (context buffers and the borrowed B, F)
   // for the adjoint: tape bookkeeping (constant flag, write version) and the
@@ -157,12 +159,13 @@ struct Ctx {
   double* bar(const void* p);             // shadow address of p
   bool wants(const void* p, bool params);  // cotangent needed in this sweep?
 
-  // adjoint state (allocated by the first dcsd_backward / dcsd_residual_vjp)
+  // adjoint state (reserved by dcsd_init when cfg.adjoint is set)
   Tape tape_init, tape_res;
   double *Tin = nullptr, *Rt = nullptr, *temp = nullptr, *lam = nullptr;
   int64_t temp_cap = 0;
-  std::vector<double*> adj_allocs;
+  bool adj_ready = false;
   void adj_setup();
+  void adj_reserve();
   void record(const double* T);
   void sweep(const double* Rbar, double Wbar, double Ebar, bool params);
   void adjoint_op(const TapeOp& op, bool params);
@@ -173,6 +176,7 @@ struct Ctx {
 
   double* alloc(int64_t count);
   int* alloc_int(int64_t count);
+  void* alloc_raw(size_t bytes);  // owned, not in the adjoint's array registry
   void release();
 
   void init(const dcsd_config& c, const double* B, const double* F, hipStream_t stream);
@@ -181,6 +185,7 @@ struct Ctx {
   void residual(const double* T, double* R, double* W_host, int prec = -1, int mode = PLAIN);
   double energy_A(const double* T);
   int solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user);
+  void energies(const double* T, dcsd_energies* out);
   void jacobi_diis(int it, double* X, const double* R, std::vector<double>& gram, std::vector<int>& order,
                    int& count);
 };

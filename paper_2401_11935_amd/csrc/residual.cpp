@@ -169,8 +169,21 @@ double* Ctx::alloc(int64_t count) {
   }
   allocs.push_back(p);
   bytes += b;
+  ++alloc_calls;
   reg((double*)p, std::max<int64_t>(count, 1), true);
   return (double*)p;
+}
+
+void* Ctx::alloc_raw(size_t b) {
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(b, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  allocs.push_back(p);
+  bytes += b;
+  ++alloc_calls;
+  return p;
 }
 
 int* Ctx::alloc_int(int64_t count) {
@@ -182,6 +195,7 @@ int* Ctx::alloc_int(int64_t count) {
   }
   allocs.push_back(p);
   bytes += b;
+  ++alloc_calls;
   return (int*)p;
 }
 
@@ -228,6 +242,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   if (cfg.precision != DCSD_PREC_FP64 && cfg.precision != DCSD_PREC_FP32 && cfg.precision != DCSD_PREC_BF16)
     throw ArgError("unknown precision");
   if (cfg.refresh_every < 0) throw ArgError("refresh_every must be >= 0");
+  if (cfg.guard_iters < 0) throw ArgError("guard_iters must be >= 0");
+  if (cfg.adjoint != 0 && cfg.adjoint != 1) throw ArgError("adjoint must be 0 or 1");
   if (cfg.diis_dim < 0 || cfg.diis_dim > 64) throw ArgError("diis_dim must be in [0, 64]");
   if (cfg.max_iter < 1) throw ArgError("max_iter must be >= 1");
   if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
@@ -298,7 +314,6 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   KCBJ = alloc(tov * tov);
   Dvo = alloc(tov * tov);
   OOOO = alloc(4 * o2 * o2);
-  Tmp = alloc(tov * tov);
   Ring = alloc(tov * tov);
   Wsf1 = alloc(s2);
   Wsf2 = alloc(s2);
@@ -360,6 +375,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   }
   Tn = alloc(total);
   Ev = alloc(total);
+  Tbest = alloc(total);
   {
     std::vector<int> pi, pj;
     for (int i = 0; i < o; ++i)
@@ -382,6 +398,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   reg(const_cast<double*>(B), NA * n2, false);
   reg(const_cast<double*>(F), n2, false);
   build_constants(true);
+  if (cfg.adjoint) adj_reserve();
 }
 
 // Quantities of Phi_A built from (B, F) once per context; re-run under a tape
@@ -793,7 +810,12 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
 }
 
 int Ctx::tbegin(hipEvent_t* ev) {
-  if (!timing || pool_next + 2 > pool.size()) return 0;
+  if (!timing) return 0;
+  if (pool_next + 2 > pool.size()) {  // grow the pool: no interval is dropped
+    const size_t old = pool.size(), grown = std::max<size_t>(1024, 2 * old);
+    pool.resize(grown);
+    for (size_t k = old; k < grown; ++k) DCSD_HIP(hipEventCreate(&pool[k]));
+  }
   *ev = pool[pool_next++];
   DCSD_HIP(hipEventRecord(*ev, s));
   return 1;
@@ -803,6 +825,18 @@ void Ctx::tend(hipEvent_t a, double flops, int cls) {
   hipEvent_t b = pool[pool_next++];
   DCSD_HIP(hipEventRecord(b, s));
   recs.push_back({a, b, flops, cls});
+}
+
+// dE_A and W of amplitudes T: W from an FP64 residual into the solver's work
+// vector (the fixed-reference methods have W = 0 and need none).
+void Ctx::energies(const double* T, dcsd_energies* out) {
+  double W = 0.0;
+  if (!method_fr(cfg.method)) residual(T, Rw, &W, DCSD_PREC_FP64, PLAIN);
+  const double e = energy_A(T);
+  out->dE_A = e;
+  out->W = W;
+  state_energies(cfg.method, e, W, out->E_S, out->E_T);
+  out->E_ref_A = e_ref;
 }
 
 double Ctx::energy_A(const double* T) {

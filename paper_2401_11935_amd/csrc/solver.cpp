@@ -6,6 +6,7 @@
 // products at the refresh point plus low-precision products of the operand
 // changes); refreshes are FP64 evaluations and convergence is only accepted
 // on one of them.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -105,20 +106,47 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
   double ref_res = 0.0;   // FP64 max |R| at the last refresh
   double best = 0.0;      // smallest corrected max |R| since the last refresh, and its iteration
   int best_it = -1;
-  // max |Rw|, energies of Tw and W; one synchronisation
-  auto measure = [&](double host[3], int& bad) {
+  // Best amplitudes of the solve (returned without convergence): smallest max |R|
+  // among FP64 evaluations, or among all evaluations while none was FP64.
+  dcsd_report best_rep{};
+  bool have_best = false;
+  // Divergence guard: consecutive growths of max |R|, and how often it has acted.
+  // The raised level shift lasts for this solve only.
+  struct ShiftRestore {
+    dcsd_config& c;
+    double v;
+    ~ShiftRestore() { c.level_shift = v; }
+  } restore{cfg, cfg.level_shift};
+  double prev_res = -1.0;
+  int growths = 0, guard_events = 0;
+  // max |Rw|, sum Rw^2, energies of Tw and W; one synchronisation
+  auto measure = [&](double host[4], int& bad) {
     int zero = 0;
     DCSD_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
     DCSD_HIP(hipStreamSynchronize(s));
     maxabs(Rw, total, scal + 1, flag, part, s);
     energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
-    DCSD_HIP(hipMemcpyAsync(host, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    dot(Rw, Rw, total, scal + 3, part, s);
+    DCSD_HIP(hipMemcpyAsync(host, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipStreamSynchronize(s));
   };
+  // without convergence: hand back the best amplitudes and the report that describes them
+  auto give_up = [&](int status) {
+    if (have_best) {
+      DCSD_HIP(hipMemcpyAsync(T, Tbest, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+      DCSD_HIP(hipStreamSynchronize(s));
+      best_rep.iterations = r.iterations;
+      best_rep.converged = 0;
+      if (rep) *rep = best_rep;
+    } else if (rep) {
+      *rep = r;
+    }
+    return status;
+  };
   for (int it = 0; it < cfg.max_iter; ++it) {
     residual(T, Rw, nullptr, -1, low && have_ref ? DELTA : PLAIN);
-    double host[3];
+    double host[4];
     int bad = 0;
     measure(host, bad);
     bool exact = !low;
@@ -150,6 +178,7 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
     }
     r.iterations = it + 1;
     r.res_max = host[1];
+    r.res_rms = std::sqrt(std::max(host[3], 0.0) / (double)total);
     r.e.W = host[0];
     r.e.dE_A = host[2];
     state_energies(cfg.method, host[2], host[0], r.e.E_S, r.e.E_T);
@@ -157,18 +186,35 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
     r.fp64 = exact ? 1 : 0;
     r.converged = (!bad && exact && host[1] <= cfg.tol_residual) ? 1 : 0;
     if (cb) cb(&r, user);
-    if (bad || !std::isfinite(host[0]) || !std::isfinite(host[2])) {
-      if (rep) *rep = r;
-      return DCSD_ERR_NONFINITE;
-    }
+    if (bad || !std::isfinite(host[0]) || !std::isfinite(host[2])) return give_up(DCSD_ERR_NONFINITE);
     if (r.converged) {
       if (rep) *rep = r;
       return DCSD_OK;
     }
+    if (!have_best || (r.fp64 && !best_rep.fp64) || (r.fp64 == best_rep.fp64 && r.res_max < best_rep.res_max)) {
+      DCSD_HIP(hipMemcpyAsync(Tbest, T, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+      best_rep = r;
+      have_best = true;
+    }
+    if (cfg.guard_iters > 0) {
+      growths = (prev_res >= 0.0 && host[1] > prev_res) ? growths + 1 : 0;
+      prev_res = host[1];
+      if (growths >= cfg.guard_iters) {
+        if (++guard_events > 2) return give_up(DCSD_ERR_NOCONV);
+        // restart from the best amplitudes with a fresh DIIS history and a larger shift
+        order.clear();
+        count = 0;
+        std::fill(gram.begin(), gram.end(), 0.0);
+        cfg.level_shift = 2.0 * cfg.level_shift + 1.0;
+        DCSD_HIP(hipMemcpyAsync(T, Tbest, total * sizeof(double), hipMemcpyDeviceToDevice, s));
+        growths = 0;
+        prev_res = -1.0;
+        continue;
+      }
+    }
     jacobi_diis(it, T, Rw, gram, order, count);
   }
-  if (rep) *rep = r;
-  return DCSD_ERR_NOCONV;
+  return give_up(DCSD_ERR_NOCONV);
 }
 
 }  // namespace dcsd

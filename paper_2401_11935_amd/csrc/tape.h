@@ -64,8 +64,13 @@ struct Snapshot {
 struct Tape {
   std::vector<TapeOp> ops;
   std::vector<Snapshot> snaps;
-  std::vector<double*> scratch;  // device memory owned by the tape (snapshots)
+  std::vector<double*> scratch;  // device memory owned by the tape (snapshots taken while sizing)
   int64_t temp_need = 0;         // largest temporary (doubles) the sweep needs
+  // Snapshot memory reserved by the context: once `arena` is set, snapshots are
+  // carved from it (256-byte aligned) and nothing is allocated; `need` is the
+  // arena size the last recording required.
+  double* arena = nullptr;
+  int64_t arena_cap = 0, arena_used = 0, need = 0;
   void clear();
 };
 

@@ -29,7 +29,7 @@ class Config(ctypes.Structure):
                 ("diis_start", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_residual", ctypes.c_double), ("level_shift", ctypes.c_double),
                 ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32), ("precond", ctypes.c_int32),
-                ("refresh_every", ctypes.c_int32)]
+                ("refresh_every", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("guard_iters", ctypes.c_int32)]
 
 
 class Energies(ctypes.Structure):
@@ -42,11 +42,11 @@ class Energies(ctypes.Structure):
 
 class Report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("res_max", ctypes.c_double),
-                ("e", Energies), ("fp64", ctypes.c_int32)]
+                ("res_rms", ctypes.c_double), ("e", Energies), ("fp64", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         d = {"iterations": self.iterations, "converged": bool(self.converged), "res_max": self.res_max,
-             "fp64": bool(self.fp64)}
+             "res_rms": self.res_rms, "fp64": bool(self.fp64)}
         d.update(self.e.as_dict())
         return d
 
@@ -95,10 +95,12 @@ def load(path: str | None = None):
     lib.dcsd_init.restype = ctypes.c_int
     lib.dcsd_residual.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_double)]
     lib.dcsd_residual.restype = ctypes.c_int
-    lib.dcsd_energy.argtypes = [vp, dp, ctypes.c_double, ctypes.POINTER(Energies)]
+    lib.dcsd_energy.argtypes = [vp, dp, ctypes.POINTER(Energies)]
     lib.dcsd_energy.restype = ctypes.c_int
     lib.dcsd_solve.argtypes = [vp, dp, ctypes.POINTER(Report), ITER_CB, vp]
     lib.dcsd_solve.restype = ctypes.c_int
+    lib.dcsd_device_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    lib.dcsd_device_memory.restype = ctypes.c_int
     lib.dcsd_last_error.argtypes = [vp]
     lib.dcsd_last_error.restype = ctypes.c_char_p
     lib.dcsd_destroy.argtypes = [vp]
@@ -139,6 +141,8 @@ def default_config(lib=None, **kw) -> Config:
             v = {"mp": 0, "orbital": 0, "en": 1}[v]
         if k == "precision" and isinstance(v, str):
             v = PRECISIONS[v]
+        if k == "adjoint":
+            v = int(bool(v))
         setattr(c, k, v)
     return c
 
@@ -176,9 +180,10 @@ class Context:
         self._check(self.lib.dcsd_residual(self.h, T_ptr, R_ptr, ctypes.byref(W) if want_W else None))
         return W.value if want_W else None
 
-    def energy(self, T_ptr: int, W: float) -> dict:
+    def energy(self, T_ptr: int) -> dict:
+        """dE_A, W (from an FP64 residual at T), E_S, E_T and E_ref_A of amplitudes T."""
         e = Energies()
-        self._check(self.lib.dcsd_energy(self.h, T_ptr, W, ctypes.byref(e)))
+        self._check(self.lib.dcsd_energy(self.h, T_ptr, ctypes.byref(e)))
         return e.as_dict()
 
     def solve(self, T_ptr: int, callback=None) -> dict:
@@ -217,6 +222,12 @@ class Context:
         if st not in (DCSD_OK, DCSD_ERR_NOCONV):
             raise DcsdError(st, self.lib.dcsd_last_error(self.h).decode())
         return out
+
+    def device_memory(self) -> tuple:
+        """(bytes, allocation calls) of device memory held by the context."""
+        b, n = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self.lib.dcsd_device_memory(self.h, ctypes.byref(b), ctypes.byref(n)))
+        return b.value, n.value
 
     def update_config(self, **kw):
         c = Config()

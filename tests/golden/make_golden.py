@@ -11,6 +11,13 @@ small:  converged energies at nc=8, nv=20, naux=60, seed 1 (the largest of
 medium: nc=8, nv=200, naux=600, seed 1: residual at seeded random amplitudes
         sampled at 4096 seeded positions (for both methods), and the converged
         energies of both methods.
+medium-weak: the medium shape and seed with weak integrals (DF factors with
+        naux sigma^2 = 0.015 Eh, dcsd_synth.MEDIUM_WEAK), on which the iterations
+        converge: converged energies and trajectory of both methods (tol 1e-10)
+        and the converged amplitudes at 4096 seeded positions.  Hours on a few
+        CPU cores (about 20 oracle residuals per method).
+
+    python tests/golden/make_golden.py medium-weak [dcsd|ccsd]
 """
 import json
 import os
@@ -62,7 +69,39 @@ def sampled_residual(cfg, method):
 SMALL = synth.Config("small", nc=8, nv=20, naux=60, seed=1)
 
 
+def converged_with_amplitudes(cfg, method, tol):
+    B, F = synth.make_config_inputs(cfg)
+    model = TwoDet(B, F, cfg.nc, method)
+    t0 = time.time()
+    r = solve(model, tol=tol, max_iter=300,
+              callback=lambda rec: print(method, rec["iter"], "%.3e" % rec["res_max"], rec["E_S"],
+                                         "%.0f s" % (time.time() - t0), flush=True))
+    idx = synth.sample_indices(NSAMPLE, r["T"].size, SAMPLE_SEED)
+    return {
+        "converged": r["converged"], "iterations": r["iterations"], "tol": tol,
+        "E_S": r["E_S"], "E_T": r["E_T"], "dE_A": r["dE_A"], "W": r["W"], "E_ref_A": r["E_ref_A"],
+        "res_max": r["res_max"], "seconds": time.time() - t0,
+        "trajectory": [{k: rec[k] for k in ("iter", "res_max", "E_S", "E_T", "W")} for rec in r["records"]],
+        "sample_seed": SAMPLE_SEED, "positions": idx.tolist(), "T": r["T"][idx].tolist(),
+        "T_max": float(np.abs(r["T"]).max()),
+    }
+
+
+def main_weak(methods):
+    cfg = synth.MEDIUM_WEAK
+    path = os.path.join(HERE, "medium_weak.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    out["config"] = {"nc": cfg.nc, "nv": cfg.nv, "naux": cfg.naux, "seed": cfg.seed, "sigma": cfg.sigma}
+    for method in methods:
+        out[method] = converged_with_amplitudes(cfg, method, 1e-10)
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+        print("wrote", path, flush=True)
+
+
 def main(which):
+    if which == "medium-weak":
+        return main_weak([m for m in ("dcsd", "ccsd") if m in sys.argv[2:]] or ["dcsd", "ccsd"])
     cfg = {"tiny": synth.TINY, "small": SMALL, "medium": synth.MEDIUM}[which]
     out = {"config": {"nc": cfg.nc, "nv": cfg.nv, "naux": cfg.naux, "seed": cfg.seed}}
     for method in ("dcsd", "ccsd"):

@@ -32,9 +32,9 @@ class GpuProblem:
         W = self.ctx.residual(Td.data_ptr(), Rd.data_ptr())
         return Rd.cpu().numpy(), W
 
-    def energy(self, T: np.ndarray, W: float) -> dict:
+    def energy(self, T: np.ndarray) -> dict:
         Td = to_dev(T)
-        return self.ctx.energy(Td.data_ptr(), W)
+        return self.ctx.energy(Td.data_ptr())
 
     def solve(self, T0=None, callback=None):
         Td = to_dev(np.zeros(self.size) if T0 is None else T0)

@@ -55,7 +55,7 @@ def _objective(B, F, T, nc, method, Rbar, Wbar, Ebar, lb):
     Td = to_dev(T)
     Rd = torch.empty_like(Td)
     W = ctx.residual(Td.data_ptr(), Rd.data_ptr())
-    e = ctx.energy(Td.data_ptr(), W)["dE_A"]
+    e = ctx.energy(Td.data_ptr())["dE_A"]
     ctx.close()
     return float(Rbar @ Rd.cpu().numpy() + Wbar * W + Ebar * e)
 
@@ -76,7 +76,7 @@ def test_residual_vjp_matches_directional_differences(nc, nv, naux, method, lb):
     Rbar = rng.normal(size=size)
     Rbar[ab] = 0.0
     Wbar, Ebar = 0.7, -1.3
-    ctx, Bd, Fd = _ctx(B, F, nc, method, ladder_block=lb)
+    ctx, Bd, Fd = _ctx(B, F, nc, method, ladder_block=lb, adjoint=1)
     Td, Rb = to_dev(T), to_dev(Rbar)
     Tb, Bb, Fb = torch.empty_like(Td), torch.empty_like(Bd), torch.empty_like(Fd)
     ctx.residual_vjp(Td.data_ptr(), Rb.data_ptr(), Wbar, Ebar, Tb.data_ptr(), Bb.data_ptr(), Fb.data_ptr())
@@ -104,7 +104,7 @@ def test_residual_vjp_matches_directional_differences(nc, nv, naux, method, lb):
 
 def _gradients(B, F, nc, method, tol):
     import torch
-    ctx, Bd, Fd = _ctx(B, F, nc, method, tol_residual=tol, max_iter=400)
+    ctx, Bd, Fd = _ctx(B, F, nc, method, tol_residual=tol, max_iter=400, adjoint=1)
     T = torch.zeros(ctx.size, dtype=torch.float64, device="cuda:0")
     rep = ctx.solve(T.data_ptr())
     assert rep["status"] == "OK", rep["status"]
@@ -241,7 +241,7 @@ def test_residual_vjp_at_adjoint_size():
     Rbar = rng.normal(size=size)
     Rbar[ab] = 0.0
     say("vjp adjoint size")
-    ctx, Bd, Fd = _ctx(B, F, c.nc, "dcsd")
+    ctx, Bd, Fd = _ctx(B, F, c.nc, "dcsd", adjoint=1)
     Td, Rb = to_dev(T), to_dev(Rbar)
     Tb, Bb = torch.empty_like(Td), torch.empty_like(Bd)
     ctx.residual_vjp(Td.data_ptr(), Rb.data_ptr(), 0.3, 0.9, Tb.data_ptr(), Bb.data_ptr(), 0)
@@ -256,7 +256,7 @@ def test_residual_vjp_at_adjoint_size():
         Txd = to_dev(Tx)
         Rx = torch.empty_like(Txd)
         W = cx.residual(Txd.data_ptr(), Rx.data_ptr())
-        e = cx.energy(Txd.data_ptr(), W)["dE_A"]
+        e = cx.energy(Txd.data_ptr())["dE_A"]
         cx.close()
         return float(Rbar @ Rx.cpu().numpy() + 0.3 * W + 0.9 * e)
 

@@ -49,7 +49,7 @@ def test_library_on_fcidump_inputs_matches_original_factors(tmp_path, method):
     for Bx, Fx in ((B, F), (prob["B"], prob["F"])):
         p = GpuProblem(Bx, Fx, nc, method)
         R, W = p.residual(T)
-        e = p.energy(T, W)
+        e = p.energy(T)
         p.close()
         out.append((R, W, e))
     (Ra, Wa, ea), (Rb, Wb, eb) = out

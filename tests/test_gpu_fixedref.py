@@ -52,7 +52,7 @@ def test_fixed_reference_residual_and_energy_match_oracle(name, nc, nv, naux, lb
     T = synth.random_amplitudes(nc, nv, nc + nv + 5, 0.05)
     p = GpuProblem(B, F, nc, name, ladder_block=lb)
     R, W = p.residual(T)
-    e = p.energy(T, W)
+    e = p.energy(T)
     p.close()
     m = _oracle(B, F, nc, name)
     Ro, _ = m.residual(T)
@@ -101,7 +101,8 @@ def test_fixed_reference_gradient_matches_finite_differences(name):
 
     def ctx_for(Bx, Fx):
         Bd, Fd = to_dev(Bx), to_dev(Fx)
-        cfg = L.default_config(nc=nc, nv=n - 2, naux=Bx.shape[0], method=name, tol_residual=1e-12, max_iter=400)
+        cfg = L.default_config(nc=nc, nv=n - 2, naux=Bx.shape[0], method=name, tol_residual=1e-12, max_iter=400,
+                               adjoint=1)
         return L.Context(cfg, Bd.data_ptr(), Fd.data_ptr(), stream()), Bd, Fd
 
     def solve_E(Bx, Fx):

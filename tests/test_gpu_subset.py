@@ -74,7 +74,7 @@ def test_full_size_residual_on_virtual_subset(cfg, method):
     say("subset residual", cfg.name, method, "library")
     p = GpuProblem(B, F, nc, method)
     R, W = p.residual(T)
-    e = p.energy(T, W)
+    e = p.energy(T)
     if method == "dcsd":
         # run to run, the full-size launches (split-K, skipped diagonal tiles and their mirror,
         # fixed-order reductions) give the same bits
@@ -159,8 +159,8 @@ def test_full_size_residual_vjp_on_virtual_subset(cfg, method):
 
     say("subset vjp", cfg.name, method, "library")
     Bd, Fd = to_dev(B), to_dev(F)
-    ctx = L.Context(L.default_config(nc=nc, nv=nv, naux=cfg.naux, method=method), Bd.data_ptr(), Fd.data_ptr(),
-                    stream())
+    ctx = L.Context(L.default_config(nc=nc, nv=nv, naux=cfg.naux, method=method, adjoint=1), Bd.data_ptr(),
+                    Fd.data_ptr(), stream())
     Td = to_dev(synth.embed_amplitudes(Ts, nc, keep, nv))
     Rb = to_dev(synth.embed_amplitudes(Rbar_s, nc, keep, nv))
     Tb, Bb, Fb = torch.empty_like(Td), torch.empty_like(Bd), torch.empty_like(Fd)
