@@ -302,7 +302,9 @@ dcsd_status dcsd_timing_stop(dcsd_ctx* ctx, dcsd_timing* out);
  * after dcsd_init returns (no call allocates), which is what this reports. */
 dcsd_status dcsd_device_memory(const dcsd_ctx* ctx, int64_t* bytes, int64_t* allocations);
 
-/* Message of the last error on this context ("" if none). */
+/* Message of the last error on this context ("" if none); with ctx NULL, the
+ * reason the calling thread's last failed dcsd_init or
+ * dcsd_selftest_gemm_layout_noalloc gave. */
 const char* dcsd_last_error(const dcsd_ctx* ctx);
 
 /* Releases all device memory of the context (NULL is allowed). */
@@ -333,6 +335,23 @@ dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t 
 dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const double* A_dev, int64_t lda,
                                       int32_t a_mc, const double* B_dev, int64_t ldb, int32_t b_nc, double* C_dev,
                                       int64_t ldc, double alpha, double beta, int32_t ksplit, void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as dcsd_selftest_gemm_layout, with the same arguments, kernels and
+ * results, allocating nothing.  The scratch that call allocates (ksplit > 1:
+ * ksplit * M * ldc partial sums; small outputs over a long K: one partial per
+ * 2048-long K chunk and output element) comes from a per-GPU device array of
+ * 4194304 doubles (32 MiB) that the library holds on each GPU it has run this
+ * call on until the process ends; a call needing more returns DCSD_ERR_ARG
+ * (dcsd_last_error(NULL) says why) without launching anything.  Every call on
+ * one GPU uses that GPU's one array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * array needs no clearing: each call writes every partial it reads. */
+dcsd_status dcsd_selftest_gemm_layout_noalloc(int64_t M, int64_t N, int64_t K, const double* A_dev, int64_t lda,
+                                              int32_t a_mc, const double* B_dev, int64_t ldb, int32_t b_nc,
+                                              double* C_dev, int64_t ldc, double alpha, double beta, int32_t ksplit,
+                                              void* hip_stream);
 
 #ifdef __cplusplus
 }

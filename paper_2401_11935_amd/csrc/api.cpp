@@ -10,7 +10,7 @@ struct dcsd_ctx {
 };
 
 namespace {
-thread_local std::string g_init_error;
+thread_local std::string g_init_error;  // last failed dcsd_init or context-free call of this thread
 
 template <class Fn>
 dcsd_status guarded(dcsd_ctx* h, Fn&& fn) {
@@ -36,6 +36,10 @@ dcsd_status guarded(dcsd_ctx* h, Fn&& fn) {
   }
 }
 }  // namespace
+
+namespace dcsd {
+void set_call_error(const char* msg) { g_init_error = msg; }
+}  // namespace dcsd
 
 extern "C" {
 

@@ -122,6 +122,8 @@ def load(path: str | None = None):
                                               ctypes.c_int32, dp, ctypes.c_int64, ctypes.c_int32, dp, ctypes.c_int64,
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]
     lib.dcsd_selftest_gemm_layout.restype = ctypes.c_int
+    lib.dcsd_selftest_gemm_layout_noalloc.argtypes = lib.dcsd_selftest_gemm_layout.argtypes
+    lib.dcsd_selftest_gemm_layout_noalloc.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -273,3 +275,13 @@ def selftest_gemm_layout(M: int, N: int, K: int, A_ptr: int, lda: int, a_mc: boo
                                                    alpha, beta, ksplit, stream or None)
     if st != DCSD_OK:
         raise DcsdError(st, "selftest_gemm_layout")
+
+def selftest_gemm_layout_noalloc(M: int, N: int, K: int, A_ptr: int, lda: int, a_mc: bool, B_ptr: int, ldb: int,
+                                 b_nc: bool, C_ptr: int, ldc: int, alpha: float = 1.0, beta: float = 0.0,
+                                 ksplit: int = 1, stream: int = 0, lib=None):
+    """selftest_gemm_layout without any device allocation (per-GPU static scratch)."""
+    lib = lib or load()
+    st = lib.dcsd_selftest_gemm_layout_noalloc(M, N, K, A_ptr, lda, int(a_mc), B_ptr, ldb, int(b_nc), C_ptr, ldc,
+                                               alpha, beta, ksplit, stream or None)
+    if st != DCSD_OK:
+        raise DcsdError(st, lib.dcsd_last_error(None).decode())
