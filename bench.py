@@ -6,8 +6,14 @@ the energies, the Jacobi update and the DIIS extrapolation, on seeded
 synthetic DF factors and Fock matrix of the nc=12, nv=400, naux=1200 open-shell
 singlet workload (inputs resident in HBM before timing starts).
 
+The line also carries: the ladder assembly's roofline (algorithmic flops per
+launch over the measured launch time); FP64, FP32 and BF16 solves of the same
+shape with weak integrals (which converge), with per-iteration energy errors and
+solve-time speed-ups; fixed-reference and adjoint timings; and the CPU oracle's
+residual rate on this host (cpu_baseline).
+
 Prints one JSON line.  ``--gpus N`` with N > 1 is not supported (one GPU per
-run); the driver-side multi-GPU design is described with the sharding notes.
+run).
 """
 from __future__ import annotations
 
@@ -84,8 +90,8 @@ def load_traffic(path):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nc", type=int, default=12)
     ap.add_argument("--nv", type=int, default=400)
     ap.add_argument("--naux", type=int, default=1200)
@@ -94,24 +100,31 @@ def parse():
     ap.add_argument("--ladder-block", type=int, default=0)
     ap.add_argument("--precond", default="en", choices=["en", "orbital"])
     ap.add_argument("--level-shift", type=float, default=1.0)
-    ap.add_argument("--cpu-slabs", type=int, default=6, help="oracle ladder slabs timed for cpu_baseline (0 = skip)")
+    ap.add_argument("--cpu-subsets", default="48,96",
+                    help="virtual-subset sizes on which the oracle residual is timed for cpu_baseline ('' = skip)")
     ap.add_argument("--traffic", type=str, default=TRAFFIC_JSON,
                     help="JSON record of the measured HBM bytes per assembly launch (ignored if the kernel changed)")
     ap.add_argument("--traffic-from-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic record from two rocprofv3 --pmc counter_collection CSVs "
                          "(FETCH_SIZE, WRITE_SIZE) of a run with --copy-calibration-mib, then exit")
     ap.add_argument("--precisions", default="fp32,bf16",
-                    help="low precisions compared with FP64 (residual evals at the same amplitudes; '' = skip)")
-    ap.add_argument("--evals", type=int, default=3, help="timed residual evaluations per precision")
+                    help="low precisions run beside FP64 on the weak-integral inputs ('' = skip)")
+    ap.add_argument("--tol", type=float, default=1e-10, help="convergence of the weak-integral solves")
+    ap.add_argument("--evals", type=int, default=3, help="timed single residual evaluations per precision")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the residual VJP")
     ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
+    ap.add_argument("--no-weak", action="store_true", help="skip the weak-integral solves")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
 
 
 def flop_model(nc, nv, naux, lb):
-    """Algorithmic flops of one residual (2 per multiply-add) by part."""
+    """Executed flops of one residual (2 per multiply-add) by part, as the library
+    runs them: the assembly over the distinct orbital pairs of each batch, with the
+    pair rows over all orbitals (occupied rows feed the T1 back-transformation); the
+    contraction over every stacked amplitude row; the ring, integral-class, dressing
+    and remaining GEMMs."""
     n, o, v, vu = nc + 2 + nv, nc + 1, nv + 1, nv + 2
     nb = [min(lb, n - p0) for p0 in range(0, n, lb)]
     asm = 0.0
@@ -132,49 +145,74 @@ def flop_model(nc, nv, naux, lb):
             "dressing": dressing, "rest": rest}
 
 
-def cpu_baseline(nc, nv, naux, seed, slabs):
-    """The oracle's particle-particle ladder on a few spatial-virtual slabs,
-    scaled to one full residual evaluation (the oracle's other terms are not
-    timed, so this over-states the oracle's rate)."""
+def algorithmic_flops(nc, nv, naux):
+    """What one residual must compute with DF integrals (2 flops per multiply-add):
+    the vvvv integrals over the spatial virtual space V_u = nv + 2 ([t, u, virt]),
+    assembled once for the distinct (ac),(bd) pairs, naux * V_u^4; the ladder
+    contraction 2 o^2 v^4 (opposite spins) plus 4 P_o P_v^2 for the two same-spin
+    blocks over distinct pairs (P_o = o(o-1)/2, P_v = v(v-1)/2); ten particle-hole
+    ring products 2 (ov)^3.  T1 corrections and small terms are left out."""
+    o, v, vu = nc + 1, nv + 1, nv + 2
+    po, pv = o * (o - 1) / 2.0, v * (v - 1) / 2.0
+    asm = float(naux) * vu ** 4
+    con = 2.0 * o * o * float(v) ** 4 + 4.0 * po * pv * pv
+    ring = 10 * 2.0 * float(o * v) ** 3
+    return {"assembly": asm, "contraction": con, "rings": ring, "total": asm + con + ring}
+
+
+def host_info():
+    """CPU model, BLAS library and the thread count numpy's BLAS uses."""
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas, threads = "unknown", int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    try:
+        from threadpoolctl import threadpool_info
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            threads = int(info[0].get("num_threads", threads))
+    except Exception:
+        pass
+    return {"cpu_model": model, "blas": blas, "threads": threads, "os_cpu_count": os.cpu_count()}
+
+
+def cpu_baseline(B, F, nc, nv, subsets):
+    """The oracle's whole residual (oracle.twodet.TwoDet.residual: CCSD terms, DC
+    selection, coupling) on two virtual subsets of the benchmark's own inputs (the
+    first S virtuals, S from `subsets`), timed on this host; the full-size time is
+    extrapolated with the power law the two timings give in the spatial virtual
+    count V_u = S + 2 (the oracle's set-up, which does not depend on T, is not timed)."""
+    import math
+
     import numpy as np
 
     import dcsd_synth as synth
-    from oracle.ccsd import SlabSource, es
-    from oracle.hamiltonian import Hamiltonian
+    from oracle.twodet import TwoDet
 
-    B, F = synth.make_inputs(nc, nv, naux, seed)
-    ham = Hamiltonian(B, F, nc)
-    src = SlabSource(ham)
-    T = synth.random_amplitudes(nc, nv, 5, 0.01)
-    _, t2 = ham.to_so(T)
-    vs = ham.vir_spin
-    spins = [np.where(vs == s)[0] for s in (0, 1)]
-    sp_all = np.unique(ham.vir_sp)
-    pick = sp_all[:: max(1, len(sp_all) // slabs)][:slabs]
-    out = np.zeros((t2.shape[0], t2.shape[1], len(spins[1])))
-    t0 = time.perf_counter()
-    for a_sp in pick:
-        pos = a_sp - ham.nc
-        S = es("Pe,Pbf->ebf", src.Bvv[:, pos, :], src.Bvv)
-        for a in np.where(ham.vir_sp == a_sp)[0]:
-            E = spins[vs[a]]
-            for Fb in spins:
-                blk = S[src.vmap[E]][:, src.vmap[Fb]][:, :, src.vmap[Fb]]
-                out[:, :, : len(Fb)] += es("ijef,ebf->ijb", t2[:, :, E][:, :, :, Fb], blk)
-    dt = time.perf_counter() - t0
-    per_eval = dt * len(sp_all) / len(pick)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    try:
-        from threadpoolctl import threadpool_info
-        info = threadpool_info()
-        if info:
-            threads = max(int(i.get("num_threads", 1)) for i in info)
-    except Exception:
-        pass
-    return {"value": 1.0 / per_eval, "unit": "residual evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle pp-ladder (vvvv term) on {len(pick)} of {len(sp_all)} spatial virtual slabs, "
-                      f"{dt:.1f} s, scaled linearly to all slabs; other oracle terms not timed",
-            "seconds_sampled": dt}
+    times = []
+    for S in subsets:
+        Bs, Fs = synth.subset_inputs(B, F, nc, np.arange(S))
+        model = TwoDet(Bs, Fs, nc, "dcsd")
+        T = synth.random_amplitudes(nc, S, 5, 0.01)
+        t0 = time.perf_counter()
+        model.residual(T)
+        times.append(time.perf_counter() - t0)
+        print(f"bench: oracle residual on {S} virtuals: {times[-1]:.1f} s", file=sys.stderr, flush=True)
+    (s1, s2), (t1, t2) = subsets, times
+    p = math.log(t2 / t1) / math.log((s2 + 2.0) / (s1 + 2.0))
+    t_full = t2 * ((nv + 2.0) / (s2 + 2.0)) ** p
+    info = host_info()
+    return {"value": 1.0 / t_full, "unit": "residual evals/s", "cores": info["threads"], "kind": "oracle",
+            "sample": (f"oracle 2D-DCSD residual (all terms) on the first {s1} and {s2} of the {nv} virtuals of "
+                       f"the benchmark inputs: {t1:.1f} s and {t2:.1f} s; extrapolated to {nv} virtuals as "
+                       f"V_u^{p:.2f} (fitted), {t_full:.0f} s per residual"),
+            "seconds_sampled": t1 + t2, "exponent": p, "extrapolated_s_per_eval": t_full, **info}
 
 
 def residual_rate(L, torch, cfg, Bd, Fd, stream, T, evals):
@@ -195,47 +233,107 @@ def residual_rate(L, torch, cfg, Bd, Fd, stream, T, evals):
     return R, W, dt, tim
 
 
-def precision_comparison(L, torch, args, Bd, Fd, stream, fm):
-    """FP64 against low-precision ladder/ring GEMMs on the same amplitudes: the
-    first Jacobi iterate from T = 0 (first-order amplitudes), where the
-    solver spends its first step."""
-    nc, nv, naux = args.nc, args.nv, args.naux
-    base = dict(nc=nc, nv=nv, naux=naux, method=args.method, ladder_block=args.ladder_block, precond=args.precond,
-                level_shift=args.level_shift)
-    ctx = L.Context(L.default_config(max_iter=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
+def timed_solve(L, torch, cfg, Bd, Fd, stream, label):
+    """dcsd_solve from T = 0 with the wall time of every iteration (callback to callback)."""
+    ctx = L.Context(cfg, Bd.data_ptr(), Fd.data_ptr(), stream)
     T = torch.zeros(ctx.size, dtype=torch.float64, device=Bd.device)
-    ctx.solve(T.data_ptr())
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    last = [t0]
+
+    def cb(r):
+        now = time.perf_counter()
+        recs.append({**r, "dt": now - last[0]})
+        last[0] = now
+        if r["iterations"] % 10 == 0 or r["converged"]:
+            print(f"bench: {label} iter {r['iterations']} |R|={r['res_max']:.2e} E_S={r['E_S']:.12f}",
+                  file=sys.stderr, flush=True)
+
+    rep = ctx.solve(T.data_ptr(), cb)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
     ctx.close()
-    out = {"amplitudes": "first Jacobi iterate from T = 0 (first-order doubles)", "evals_timed": args.evals}
-    R64, W64, dt64, tim64 = residual_rate(L, torch, L.default_config(**base), Bd, Fd, stream, T, args.evals)
+    return rep, T, recs, elapsed
+
+
+def weak_integral_run(L, torch, args, stream, alg):
+    """The metric shape (nc, nv, naux, seed as the headline) with weak integrals
+    (dcsd_synth.MIXED_WEAK, naux sigma^2 = 0.015 Eh), on which the iterations
+    converge: FP64, FP32 and BF16 solves from T = 0 to tol, per-iteration energy
+    errors against the converged FP64 energies, end-to-end solve times, and single
+    residual evaluations of each precision at the converged FP64 amplitudes."""
+    import statistics
+
+    import dcsd_synth as synth
+    cfgw = synth.MIXED_WEAK
+    print(f"bench: weak-integral inputs nc={cfgw.nc} nv={cfgw.nv} naux={cfgw.naux} sigma={cfgw.sigma:.6f}",
+          file=sys.stderr, flush=True)
+    B, F = synth.make_config_inputs(cfgw)
+    dev = torch.device("cuda:0")
+    Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
+    del B
+    base = dict(nc=cfgw.nc, nv=cfgw.nv, naux=cfgw.naux, method=args.method, ladder_block=args.ladder_block,
+                tol_residual=args.tol, max_iter=300)
+    out = {"config": {"workload": f"2D-{args.method.upper()} nc={cfgw.nc} open-shell=2 nv={cfgw.nv} "
+                                  f"naux={cfgw.naux} seed={cfgw.seed}, DF factors N(0, sigma^2) with "
+                                  f"naux sigma^2 = {synth.WEAK_EXCHANGE} Eh", "sigma": cfgw.sigma,
+                      "tol_residual": args.tol, "preconditioner": "orbital-energy denominators, DIIS 8"},
+           "reference": "the converged FP64 solve of the library (validated against the oracle per residual "
+                        "at this size and by converged parity at nc=8 nv=200)"}
+    solves = {}
+    precs = ["fp64"] + [p for p in args.precisions.split(",") if p]
+    for prec in precs:
+        rep, T, recs, elapsed = timed_solve(L, torch, L.default_config(precision=prec, **base), Bd, Fd, stream,
+                                            f"weak {prec}")
+        solves[prec] = (rep, T, recs, elapsed)
+    r64 = solves["fp64"][0]
+    for prec in precs:
+        rep, T, recs, elapsed = solves[prec]
+        first_ref = next((k for k, r in enumerate(recs) if r["fp64"]), None)
+        delta = [r["dt"] for k, r in enumerate(recs) if not r["fp64"] and first_ref is not None and k > first_ref]
+        refresh = [r["dt"] for r in recs if r["fp64"]] if prec != "fp64" else []
+        d = {"status": rep["status"], "iterations": rep["iterations"],
+             "fp64_evaluations": sum(1 for r in recs if r["fp64"]), "solve_s": elapsed,
+             "E_S": rep["E_S"], "E_T": rep["E_T"], "W": rep["W"], "res_max": rep["res_max"],
+             "abs_dE_S_vs_fp64": abs(rep["E_S"] - r64["E_S"]), "abs_dE_T_vs_fp64": abs(rep["E_T"] - r64["E_T"]),
+             "speedup_solve_vs_fp64": solves["fp64"][3] / elapsed,
+             "median_iteration_ms": 1e3 * statistics.median([r["dt"] for r in recs[1:]] or [0.0]),
+             # per iteration: [fp64 evaluation?, max|R|, E_S - E_S(FP64, converged), E_T - E_T(FP64, converged)]
+             "per_iteration": [[int(r["fp64"]), float(f"{r['res_max']:.3e}"), float(f"{r['E_S'] - r64['E_S']:.3e}"),
+                                float(f"{r['E_T'] - r64['E_T']:.3e}")] for r in recs]}
+        if prec != "fp64":
+            d["median_delta_iteration_ms"] = 1e3 * statistics.median(delta) if delta else None
+            d["median_refresh_iteration_ms"] = 1e3 * statistics.median(refresh) if refresh else None
+        out[prec] = d
+    # single evaluations at the converged FP64 amplitudes (plain mode: the operands themselves rounded)
+    T64 = solves["fp64"][1]
+    single = {"amplitudes": "converged FP64 amplitudes", "mode": "one residual evaluation, plain (no delta "
+              "against a refresh point)", "evals_timed": args.evals}
+    R64, W64, dt64, tim64 = residual_rate(L, torch, L.default_config(**base), Bd, Fd, stream, T64, args.evals)
     rmax = float(R64.abs().max())
-    out["fp64"] = {"residual_evals_per_s": 1.0 / dt64, "ms_per_eval": 1e3 * dt64, "max_abs_R": rmax, "W": W64,
-                   "kernels": tim64}
-    for prec in [p for p in args.precisions.split(",") if p]:
-        print(f"bench: residual evals in {prec}", file=sys.stderr, flush=True)
-        R, W, dt, tim = residual_rate(L, torch, L.default_config(precision=prec, **base), Bd, Fd, stream, T,
+    single["fp64"] = {"ms_per_eval": 1e3 * dt64, "tflops_algorithmic": alg["total"] / dt64 / 1e12,
+                      "max_abs_R": rmax, "kernels": tim64}
+    for prec in precs[1:]:
+        print(f"bench: single residual evals in {prec}", file=sys.stderr, flush=True)
+        R, W, dt, tim = residual_rate(L, torch, L.default_config(precision=prec, **base), Bd, Fd, stream, T64,
                                       args.evals)
         asm = tim["assembly"]
         ach = asm["flops"] / (asm["ms"] * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
-        con = tim["contraction"]
-        ring = tim["ring"]
-        out[prec] = {
-            "residual_evals_per_s": 1.0 / dt, "ms_per_eval": 1e3 * dt, "speedup_vs_fp64": dt64 / dt,
-            "tflops": sum(fm.values()) / dt / 1e12,
-            "max_abs_dR": float((R - R64).abs().max()), "rel_dR": float((R - R64).abs().max()) / max(rmax, 1e-300),
-            "abs_dW": abs(W - W64),
+        single[prec] = {
+            "ms_per_eval": 1e3 * dt, "speedup_vs_fp64": dt64 / dt, "tflops_algorithmic": alg["total"] / dt / 1e12,
+            "max_abs_dR": float((R - R64).abs().max()), "abs_dW": abs(W - W64),
             "note": "dE_A is FP64 in every mode, so |dE_S| = |dE_T| = |dW| at the same amplitudes",
-            "roofline_assembly": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                                  "frac": ach / PEAK_TFLOPS[prec],
+            "roofline_assembly": {"bound": "mfma", "achieved_executed": ach, "peak": PEAK_TFLOPS[prec],
+                                  "unit": "TFLOP/s", "frac_executed": ach / PEAK_TFLOPS[prec],
                                   "avg_launch_ms": asm["ms"] / max(asm["launches"], 1)},
-            "contraction_tflops": con["flops"] / (con["ms"] * 1e-3) / 1e12 if con["ms"] > 0 else 0.0,
-            "ring_tflops": ring["flops"] / (ring["ms"] * 1e-3) / 1e12 if ring["ms"] > 0 else 0.0,
-            "kernels": tim,
-        }
+            "kernels": tim}
+    out["single_evaluation"] = single
+    del Bd, Fd
     return out
 
 
-def fixed_reference_timing(L, torch, args, Bd, Fd, stream, fm):
+def fixed_reference_timing(L, torch, args, Bd, Fd, stream, alg):
     """FP64 residual evaluations of the fixed-reference methods (singlet) at the
     metric size: the same kernels as 2D without the coupling terms."""
     base = dict(nc=args.nc, nv=args.nv, naux=args.naux, ladder_block=args.ladder_block, precond=args.precond,
@@ -248,23 +346,26 @@ def fixed_reference_timing(L, torch, args, Bd, Fd, stream, fm):
         print(f"bench: residual evals of {name}", file=sys.stderr, flush=True)
         _, W, dt, tim = residual_rate(L, torch, L.default_config(method=name, **base), Bd, Fd, stream, T, args.evals)
         out[name] = {"residual_evals_per_s": 1.0 / dt, "ms_per_eval": 1e3 * dt, "W": W,
-                     "tflops": sum(fm.values()) / dt / 1e12, "kernels": tim}
+                     "tflops_algorithmic": alg["total"] / dt / 1e12, "kernels": tim}
     return out
 
 
 def adjoint_timing(L, torch, args, Bd, Fd, stream):
-    """One residual VJP (dcsd_residual_vjp) at the first-order amplitudes: the
-    amplitude-only sweep that each lambda iteration runs, and the full sweep
-    through the constants to B and F; each call re-records the tape (one
-    forward residual plus the constants)."""
+    """One residual VJP (dcsd_residual_vjp) at random amplitudes: the amplitude-only
+    sweep that each lambda iteration runs, and the full sweep through the constants
+    to B and F; each call re-records the tape (one forward residual plus the
+    constants) into the memory dcsd_init reserved."""
+    import dcsd_synth as synth
     base = dict(nc=args.nc, nv=args.nv, naux=args.naux, method=args.method, ladder_block=args.ladder_block)
-    ctx = L.Context(L.default_config(max_iter=1, adjoint=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
-    T = torch.zeros(ctx.size, dtype=torch.float64, device=Bd.device)
-    ctx.solve(T.data_ptr())
-    Rbar = torch.randn(ctx.size, dtype=torch.float64, device=Bd.device, generator=torch.Generator(Bd.device).manual_seed(7))
+    t0 = time.perf_counter()
+    ctx = L.Context(L.default_config(adjoint=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
+    torch.cuda.synchronize()
+    out = {"init_with_adjoint_s": time.perf_counter() - t0}
+    T = torch.from_numpy(synth.random_amplitudes(args.nc, args.nv, 5, 0.01)).to(Bd.device)
+    Rbar = torch.randn(ctx.size, dtype=torch.float64, device=Bd.device,
+                       generator=torch.Generator(Bd.device).manual_seed(7))
     Tb, Bb, Fb = torch.empty_like(T), torch.empty_like(Bd), torch.empty_like(Fd)
     R = torch.empty_like(T)
-    out = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.residual(T.data_ptr(), R.data_ptr())
@@ -277,36 +378,11 @@ def adjoint_timing(L, torch, args, Bd, Fd, stream):
                              Bb.data_ptr() if full else 0, Fb.data_ptr() if full else 0)
             dt = 1e3 * (time.perf_counter() - t0)
         out[name] = dt
+    out["device_memory_gib"] = ctx.device_memory()[0] / 2 ** 30
     out["note"] = ("record (forward residual + constants, operand snapshots) and one backward sweep, FP64; "
                    "ladder integral batches recomputed in the sweep")
     ctx.close()
     return out
-
-
-def tiny_convergence(L, torch, stream):
-    """Mixed-precision solves of the tiny configuration (nc=3, nv=16, naux=60)
-    to max|R| <= 1e-10 beside the FP64 solve."""
-    import dcsd_synth as synth
-    cfg = synth.TINY
-    B, F = synth.make_config_inputs(cfg)
-    dev = torch.device("cuda:0")
-    Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
-    res = {"config": "nc=3 nv=16 naux=60 seed=0, 2D-DCSD, tol 1e-10"}
-    for prec in ("fp64", "fp32", "bf16"):
-        ctx = L.Context(L.default_config(nc=cfg.nc, nv=cfg.nv, naux=cfg.naux, precision=prec, tol_residual=1e-10),
-                        Bd.data_ptr(), Fd.data_ptr(), stream)
-        T = torch.zeros(ctx.size, dtype=torch.float64, device=dev)
-        t0 = time.perf_counter()
-        rep = ctx.solve(T.data_ptr())
-        torch.cuda.synchronize()
-        ctx.close()
-        res[prec] = {"status": rep["status"], "iterations": rep["iterations"],
-                     "fp64_evals": sum(r["fp64"] for r in rep["records"]), "E_S": rep["E_S"], "E_T": rep["E_T"],
-                     "seconds": time.perf_counter() - t0}
-    for prec in ("fp32", "bf16"):
-        res[prec]["abs_dE_S_vs_fp64"] = abs(res[prec]["E_S"] - res["fp64"]["E_S"])
-        res[prec]["abs_dE_T_vs_fp64"] = abs(res[prec]["E_T"] - res["fp64"]["E_T"])
-    return res
 
 
 def main():
@@ -318,7 +394,6 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus > 1 is not supported"}))
         sys.exit(2)
-    import numpy as np
     import torch
 
     import dcsd_synth as synth
@@ -330,7 +405,6 @@ def main():
     dev = torch.device("cuda:0")
     Bd = torch.from_numpy(B).to(dev)
     Fd = torch.from_numpy(F).to(dev)
-    del B
     stream = torch.cuda.current_stream(dev).cuda_stream
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 8
@@ -366,9 +440,13 @@ def main():
     steps = len(rep["records"])
     lb = ctx.cfg.ladder_block or min(32, nc + 2 + nv)
     fm = flop_model(nc, nv, naux, lb)
-    flops_eval = sum(fm.values())
+    alg = algorithmic_flops(nc, nv, naux)
+    executed = sum(fm.values())
     asm = tim["assembly"]
-    achieved = asm["flops"] / (asm["ms"] * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
+    launches_per_eval = asm["launches"] / max(steps, 1)
+    avg_ms = asm["ms"] / max(asm["launches"], 1)
+    achieved = alg["assembly"] / launches_per_eval / (avg_ms * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
+    achieved_exec = asm["flops"] / (asm["ms"] * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
     traffic = load_traffic(args.traffic)
     out = {
         "metric": METRIC,
@@ -387,34 +465,39 @@ def main():
                                f"nc={nc} open-shell=2 nv={nv} naux={naux}, seeded synthetic DF integrals",
                    "nc": nc, "nv": nv, "naux": naux, "method": args.method, "precision": "fp64",
                    "ladder_block": lb},
-        "tflops": flops_eval * steps / elapsed / 1e12,
-        "flops_per_eval": flops_eval,
+        "tflops": alg["total"] * steps / elapsed / 1e12,
+        "flops_per_eval": alg["total"],
+        "flops_per_eval_parts": alg,
+        "tflops_executed": executed * steps / elapsed / 1e12,
+        "flops_per_eval_executed": executed,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "ladder integral assembly (FP64 MFMA GEMM, K = naux)",
-                     "launches": asm["launches"], "avg_launch_ms": asm["ms"] / max(asm["launches"], 1)},
+                     "algorithmic_flops_per_launch": alg["assembly"] / launches_per_eval,
+                     "launches": asm["launches"], "avg_launch_ms": avg_ms,
+                     "achieved_executed": achieved_exec, "frac_executed": achieved_exec / FP64_PEAK_TFLOPS,
+                     "executed_flops_per_launch": asm["flops"] / max(asm["launches"], 1)},
         "kernels": tim,
         "converged": rep["converged"],
-        "E_S": rep["E_S"], "E_T": rep["E_T"],
-        "solver_note": ("energies after the timed steps, as computed: with the prescribed synthetic DF "
-                        "factors (entries N(0, 0.05^2)) every exchange integral is about naux*0.05^2 = 3 Eh, "
-                        "so this system is far more strongly correlated than a molecule and its Jacobi/DIIS "
-                        "iterations do not converge; the work of a step does not depend on the amplitude "
-                        "values. Convergence and energies are checked on the configurations that converge "
-                        "(see mixed_convergence_tiny and the tests)"),
+        "solver_note": ("with the prescribed synthetic DF factors (entries N(0, 0.05^2)) every exchange integral "
+                        "is about naux*0.05^2 = 3 Eh, so this system is far more strongly correlated than a "
+                        "molecule and its Jacobi/DIIS iterations diverge; the work of a step does not depend on the "
+                        "amplitude values. Converged energies and the mixed-precision solves are on the same shape "
+                        "with weak integrals (weak_integrals)"),
     }
     ctx.close()
-    if args.precisions:
-        out["precisions"] = precision_comparison(L, torch, args, Bd, Fd, stream, fm)
-        out["mixed_convergence_tiny"] = tiny_convergence(L, torch, stream)
+    if not args.no_weak:
+        out["weak_integrals"] = weak_integral_run(L, torch, args, stream, alg)
     if not args.no_fr:
-        out["fixed_reference"] = fixed_reference_timing(L, torch, args, Bd, Fd, stream, fm)
+        out["fixed_reference"] = fixed_reference_timing(L, torch, args, Bd, Fd, stream, alg)
     if not args.no_adjoint:
         print("bench: residual VJP", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_timing(L, torch, args, Bd, Fd, stream)
-    if args.cpu_slabs > 0:
-        print("bench: timing the oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(nc, nv, naux, args.seed, args.cpu_slabs)
+    if args.cpu_subsets:
+        print("bench: timing the oracle", file=sys.stderr, flush=True)
+        del Bd, Fd
+        subsets = [int(x) for x in args.cpu_subsets.split(",")]
+        out["cpu_baseline"] = cpu_baseline(B, F, nc, nv, subsets)
     print(json.dumps(out), flush=True)
 
 
