@@ -204,6 +204,56 @@ def add_fragment(B: np.ndarray, F: np.ndarray, nc: int, nf_vir: int, seed: int):
     return B2, F2, nc + 1, {"B": Bf, "F": Ff}
 
 
+# ---- high-spin (M_s = 1) triplet reference Phi_T = |core, t alpha, u alpha> ----------
+# Per-spin orders: alpha-occ = [core, t, u], beta-occ = [core], alpha-vir = [virt],
+# beta-vir = [t, u, virt]; packed [t1a | t1b | t2aa | t2bb | t2ab] with
+# oa = nc + 2, ob = nc, va = nv, vb = nv + 2.
+def hs_dims(nc: int, nv: int):
+    return nc + 2, nc, nv, nv + 2
+
+
+def hs_block_offsets(nc: int, nv: int) -> dict:
+    oa, ob, va, vb = hs_dims(nc, nv)
+    out, off = {}, 0
+    for name, shape in (("t1a", (oa, va)), ("t1b", (ob, vb)), ("t2aa", (oa, oa, va, va)),
+                        ("t2bb", (ob, ob, vb, vb)), ("t2ab", (oa, ob, va, vb))):
+        size = int(np.prod(shape))
+        out[name] = (off, shape)
+        off += size
+    return out
+
+
+def hs_amplitude_count(nc: int, nv: int) -> int:
+    oa, ob, va, vb = hs_dims(nc, nv)
+    return oa * va + ob * vb + oa * oa * va * va + ob * ob * vb * vb + oa * ob * va * vb
+
+
+def hs_unpack(vec: np.ndarray, nc: int, nv: int) -> dict:
+    return {k: vec[off:off + int(np.prod(shape))].reshape(shape)
+            for k, (off, shape) in hs_block_offsets(nc, nv).items()}
+
+
+def hs_pack(blocks: dict, nc: int, nv: int) -> np.ndarray:
+    dt = np.result_type(np.float64, *[np.asarray(b) for b in blocks.values()])
+    out = np.zeros(hs_amplitude_count(nc, nv), dt)
+    for k, (off, shape) in hs_block_offsets(nc, nv).items():
+        out[off:off + int(np.prod(shape))] = np.asarray(blocks[k], dtype=dt).ravel()
+    return out
+
+
+def hs_random_amplitudes(nc: int, nv: int, seed: int, scale: float = 0.05) -> np.ndarray:
+    """Random packed high-spin amplitudes, same-spin doubles antisymmetric."""
+    rng = np.random.default_rng(seed)
+    oa, ob, va, vb = hs_dims(nc, nv)
+    blocks = {"t1a": rng.normal(0, scale, (oa, va)), "t1b": rng.normal(0, scale, (ob, vb))}
+    for name, (o, v) in (("t2aa", (oa, va)), ("t2bb", (ob, vb))):
+        x = rng.normal(0, scale, (o, o, v, v))
+        x = x - x.transpose(1, 0, 2, 3)
+        blocks[name] = x - x.transpose(0, 1, 3, 2)
+    blocks["t2ab"] = rng.normal(0, scale, (oa, ob, va, vb))
+    return hs_pack(blocks, nc, nv)
+
+
 def random_amplitudes(nc: int, nv: int, seed: int, scale: float = 0.05) -> np.ndarray:
     """Random packed amplitudes with the layout's symmetries: same-spin
     doubles antisymmetric in (i,j) and (a,b); the Phi_A -> Phi_B element zero."""

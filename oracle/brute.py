@@ -1,7 +1,8 @@
 """Determinant-space engine: exact second quantisation on small systems (oracle).
 
 Everything is evaluated from its definition in the full determinant space of
-fixed N_alpha = N_beta = nc + 1 electrons:
+the reference's N_alpha and N_beta (nc + 1 each for Phi_A; nc + 2 and nc for
+the M_s = 1 determinant Phi_T):
 
 * H = sum h_pq E_pq + 1/2 sum (pq|rs) (E_pq E_rs - delta_qr E_ps), the
   spin-free Hamiltonian of the DF integrals (spin-summed E_pq);
@@ -50,7 +51,9 @@ class DeterminantSpace:
         n = ham.n
         self.n = n
         self.nso = 2 * n
-        na = nb = ham.nc + 1
+        # electrons of each spin in the reference (Phi_A: nc + 1 each; Phi_T: nc + 2 and nc)
+        na = int(np.sum(np.asarray(ham.occ_spin) == 0))
+        nb = int(np.sum(np.asarray(ham.occ_spin) == 1))
         dets = []
         for occa in itertools.combinations(range(n), na):
             for occb in itertools.combinations(range(n), nb):

@@ -267,3 +267,67 @@ def test_residual_vjp_at_adjoint_size():
         rel = abs(fd - an) / max(abs(fd), 1e-12)
         say(f"  {name}: fd {fd:.10e} vjp {an:.10e} rel {rel:.1e}")
         assert rel <= 1e-6
+
+
+def test_backward_at_the_adjoint_shape_with_weak_integrals():
+    """The adjoint configuration's shape (nc=8, nv=200, naux=600, seed 1) with weak
+    integrals (naux sigma^2 = 0.015 Eh), on which the amplitude equations converge:
+    dcsd_backward against central differences (h = 1e-5) of re-converged solves
+    (tol 1e-12, started from the converged amplitudes) on 64 seeded entries of B and
+    8 of F, for E_S and E_T, to 1e-6 relative."""
+    import torch
+    from gpu_util import to_dev
+    cfg = synth.MEDIUM_WEAK
+    B, F = synth.make_config_inputs(cfg)
+    nc, n = cfg.nc, cfg.n
+    say("backward vs finite differences, nc=8 nv=200 naux=600 weak integrals")
+    ctx, Bd, Fd = _ctx(B, F, nc, "dcsd", tol_residual=1e-12, max_iter=400, adjoint=1)
+    T = torch.zeros(ctx.size, dtype=torch.float64, device="cuda:0")
+    rep = ctx.solve(T.data_ptr())
+    assert rep["status"] == "OK", rep
+    g = {}
+    for key, (eS, eT) in (("E_S", (1.0, 0.0)), ("E_T", (0.0, 1.0))):
+        Bb, Fb, lam = torch.empty_like(Bd), torch.empty_like(Fd), torch.zeros_like(T)
+        lrep = ctx.backward(T.data_ptr(), eS, eT, Bb.data_ptr(), Fb.data_ptr(), lam.data_ptr())
+        assert lrep["status"] == "OK", lrep
+        g[key] = (Bb.cpu().numpy(), Fb.cpu().numpy())
+    ctx.close()
+    T0 = T.cpu().numpy()
+    say(f"  converged in {rep['iterations']} iterations, E_S {rep['E_S']:.12f}")
+    rng = np.random.default_rng(5)
+    picks = set()
+    while len(picks) < 64:
+        P, p, q = int(rng.integers(cfg.naux)), int(rng.integers(n)), int(rng.integers(n))
+        picks.add(("B", P, min(p, q), max(p, q)))
+    fpicks = set()
+    while len(fpicks) < 8:
+        p, q = int(rng.integers(n)), int(rng.integers(n))
+        fpicks.add(("F", 0, min(p, q), max(p, q)))
+    h = 1e-5
+
+    def solve_E(Bx, Fx):
+        cx, Bxd, Fxd = _ctx(Bx, Fx, nc, "dcsd", tol_residual=1e-12, max_iter=400)  # borrowed: keep alive
+        Tx = to_dev(T0)
+        r = cx.solve(Tx.data_ptr())
+        cx.close()
+        assert r["status"] == "OK", r["status"]
+        return r["E_S"], r["E_T"]
+
+    worst = 0.0
+    for (kind, P, p, q) in sorted(picks) + sorted(fpicks):
+        d = np.zeros_like(B[0] if kind == "F" else B)
+        tgt = d if kind == "F" else d[P]
+        if p == q:
+            tgt[p, p] = 1.0
+        else:
+            tgt[p, q] = tgt[q, p] = 0.5
+        if kind == "B":
+            ep, em = solve_E(B + h * d, F), solve_E(B - h * d, F)
+        else:
+            ep, em = solve_E(B, F + h * d), solve_E(B, F - h * d)
+        for k, key in enumerate(("E_S", "E_T")):
+            fd = (ep[k] - em[k]) / (2 * h)
+            an = g[key][0][P, p, q] if kind == "B" else g[key][1][p, q]
+            worst = max(worst, abs(fd - an) / max(abs(fd), 1e-3))
+            assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-9, ((kind, P, p, q), key, fd, an)
+    say(f"  72 entries: worst |fd - adjoint| / max(|fd|, 1e-3) = {worst:.1e}")
