@@ -273,15 +273,18 @@ def test_backward_at_the_adjoint_shape_with_weak_integrals():
     """The adjoint configuration's shape (nc=8, nv=200, naux=600, seed 1) with weak
     integrals (naux sigma^2 = 0.015 Eh), on which the amplitude equations converge:
     dcsd_backward against central differences (h = 1e-5) of re-converged solves
-    (tol 1e-12, started from the converged amplitudes) on 64 seeded entries of B and
-    8 of F, for E_S and E_T, to 1e-6 relative."""
+    (tol 1e-14, started from the converged amplitudes) on 64 seeded entries of B and
+    8 of F, for E_S and E_T, to 1e-6 relative plus 2e-10 (the differences' noise:
+    energies converged to ~1e-15, over 2h).  The B entries have a core or open-shell
+    row (B[P, i, q], q any): entries with two virtual indices have gradients of
+    ~4e-7 (median), below what the differences resolve at 1e-6."""
     import torch
     from gpu_util import to_dev
     cfg = synth.MEDIUM_WEAK
     B, F = synth.make_config_inputs(cfg)
     nc, n = cfg.nc, cfg.n
     say("backward vs finite differences, nc=8 nv=200 naux=600 weak integrals")
-    ctx, Bd, Fd = _ctx(B, F, nc, "dcsd", tol_residual=1e-12, max_iter=400, adjoint=1)
+    ctx, Bd, Fd = _ctx(B, F, nc, "dcsd", tol_residual=1e-14, max_iter=400, adjoint=1)
     T = torch.zeros(ctx.size, dtype=torch.float64, device="cuda:0")
     rep = ctx.solve(T.data_ptr())
     assert rep["status"] == "OK", rep
@@ -297,7 +300,7 @@ def test_backward_at_the_adjoint_shape_with_weak_integrals():
     rng = np.random.default_rng(5)
     picks = set()
     while len(picks) < 64:
-        P, p, q = int(rng.integers(cfg.naux)), int(rng.integers(n)), int(rng.integers(n))
+        P, p, q = int(rng.integers(cfg.naux)), int(rng.integers(nc + 2)), int(rng.integers(n))
         picks.add(("B", P, min(p, q), max(p, q)))
     fpicks = set()
     while len(fpicks) < 8:
@@ -306,7 +309,7 @@ def test_backward_at_the_adjoint_shape_with_weak_integrals():
     h = 1e-5
 
     def solve_E(Bx, Fx):
-        cx, Bxd, Fxd = _ctx(Bx, Fx, nc, "dcsd", tol_residual=1e-12, max_iter=400)  # borrowed: keep alive
+        cx, Bxd, Fxd = _ctx(Bx, Fx, nc, "dcsd", tol_residual=1e-14, max_iter=400)  # borrowed: keep alive
         Tx = to_dev(T0)
         r = cx.solve(Tx.data_ptr())
         cx.close()
@@ -329,5 +332,5 @@ def test_backward_at_the_adjoint_shape_with_weak_integrals():
             fd = (ep[k] - em[k]) / (2 * h)
             an = g[key][0][P, p, q] if kind == "B" else g[key][1][p, q]
             worst = max(worst, abs(fd - an) / max(abs(fd), 1e-3))
-            assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-9, ((kind, P, p, q), key, fd, an)
+            assert abs(fd - an) <= 1e-6 * abs(fd) + 2e-10, ((kind, P, p, q), key, fd, an)
     say(f"  72 entries: worst |fd - adjoint| / max(|fd|, 1e-3) = {worst:.1e}")
