@@ -70,13 +70,28 @@ typedef enum {
  * Phi_A - Phi_B) and no coupling terms.  One solve gives one state: its
  * correlation energy dE_A (which includes the fixed amplitude) is reported in
  * E_S (singlet) or E_T (triplet), the other is NaN, and W is 0. */
+/* The high-spin methods solve the single-reference DCSD or CCSD equations of
+ * the M_s = 1 triplet determinant Phi_T = |core, t alpha, u alpha> (the
+ * component the paper's single-reference triplets use for singlet-triplet
+ * gaps; Computational Details and Results): no coupling, no fixed amplitude;
+ * the triplet's correlation energy dE (the CC energy expression of Phi_T) is
+ * reported in E_T and in dE_A, E_S is NaN, W is 0, and E_ref_A is <T|H|T>.
+ * Their packed amplitudes use per-spin orders alpha-occ = [core, t, u],
+ * beta-occ = [core], alpha-vir = [virt], beta-vir = [t, u, virt]:
+ *   [ t1a (nc+2, nv) | t1b (nc, nv+2) | t2aa (nc+2, nc+2, nv, nv) |
+ *     t2bb (nc, nc, nv+2, nv+2) | t2ab (nc+2, nc, nv, nv+2) ]
+ * of length dcsd_method_amplitude_count(nc, nv, method).  They need nc >= 1
+ * and run in every precision; the adjoint (cfg.adjoint) is not available for
+ * them (DCSD_ERR_ARG). */
 enum {
   DCSD_METHOD_DCSD = 0,
   DCSD_METHOD_CCSD = 1,
   DCSD_METHOD_FR_DCSD_SINGLET = 2,
   DCSD_METHOD_FR_DCSD_TRIPLET = 3,
   DCSD_METHOD_FR_CCSD_SINGLET = 4,
-  DCSD_METHOD_FR_CCSD_TRIPLET = 5
+  DCSD_METHOD_FR_CCSD_TRIPLET = 5,
+  DCSD_METHOD_HS_DCSD = 6,
+  DCSD_METHOD_HS_CCSD = 7
 };
 /* Arithmetic of the particle-particle ladder and ring GEMMs (everything else
  * is FP64 in every mode): FP64 MFMA, or FP32 / BF16 MFMA inputs (rounded to
@@ -151,8 +166,13 @@ typedef struct {
 
 typedef void (*dcsd_iter_cb)(const dcsd_report* it, void* user);
 
-/* Length of the packed amplitude vector: 2 o v + 3 o^2 v^2. */
+/* Length of the packed amplitude vector of the two-determinant and
+ * fixed-reference methods: 2 o v + 3 o^2 v^2. */
 int64_t dcsd_amplitude_count(int32_t nc, int32_t nv);
+
+/* Length of the packed amplitude vector of a method (the high-spin methods
+ * have their own layout, see DCSD_METHOD_HS_*); -1 on invalid arguments. */
+int64_t dcsd_method_amplitude_count(int32_t nc, int32_t nv, int32_t method);
 
 /* Fills *cfg with defaults (DCSD, FP64, DIIS 8 from iteration 2, max_iter 200,
  * tol 1e-10, no shift, all terms, no adjoint reservation, guard_iters 10). */

@@ -223,7 +223,7 @@ void Ctx::record(const double* T) {
     op.src = Tw;
     op.val[0] = tape_value(Tw, total);
     tape_op(op);
-    energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
+    energy(Tw, Isc, f[0], f[1], L, scal + 2, part, s);
     for (const double* p : {(const double*)Isc, (const double*)f[0], (const double*)f[1]}) buf_of(p);
   } catch (...) {
     t_tape = nullptr;

@@ -49,6 +49,21 @@ int64_t dcsd_amplitude_count(int32_t nc, int32_t nv) {
   return 2 * o * v + 3 * o * o * v * v;
 }
 
+int64_t dcsd_method_amplitude_count(int32_t nc, int32_t nv, int32_t method) {
+  if (!dcsd::method_known(method)) return -1;
+  if (!dcsd::method_hs(method)) return dcsd_amplitude_count(nc, nv);
+  if (nc < 1 || nv < 1) return -1;
+  dcsd::SpinLayout L;
+  L.nc = nc;
+  L.n = nc + 2 + nv;
+  L.swap_tu = 0;
+  L.o[0] = nc + 2;
+  L.o[1] = nc;
+  L.v[0] = nv;
+  L.v[1] = nv + 2;
+  return L.total();
+}
+
 void dcsd_default_config(dcsd_config* c) {
   if (!c) return;
   *c = dcsd_config{};

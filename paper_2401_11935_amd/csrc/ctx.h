@@ -13,11 +13,16 @@ namespace dcsd {
 // Method families: CCSD keeps all T2*T2 terms, DCSD drops the distinguishable-cluster set;
 // the fixed-reference methods hold the Phi_A -> Phi_B double at +1 (singlet) or -1
 // (M_s = 0 triplet) and have no coupling terms.
-inline bool method_known(int m) { return m >= DCSD_METHOD_DCSD && m <= DCSD_METHOD_FR_CCSD_TRIPLET; }
+// The high-spin methods solve the single-reference equations of the M_s = 1 determinant.
+inline bool method_known(int m) { return m >= DCSD_METHOD_DCSD && m <= DCSD_METHOD_HS_CCSD; }
 inline bool method_cc(int m) {
-  return m == DCSD_METHOD_CCSD || m == DCSD_METHOD_FR_CCSD_SINGLET || m == DCSD_METHOD_FR_CCSD_TRIPLET;
+  return m == DCSD_METHOD_CCSD || m == DCSD_METHOD_FR_CCSD_SINGLET || m == DCSD_METHOD_FR_CCSD_TRIPLET ||
+         m == DCSD_METHOD_HS_CCSD;
 }
 inline bool method_fr(int m) { return m >= DCSD_METHOD_FR_DCSD_SINGLET && m <= DCSD_METHOD_FR_CCSD_TRIPLET; }
+inline bool method_hs(int m) { return m == DCSD_METHOD_HS_DCSD || m == DCSD_METHOD_HS_CCSD; }
+// the methods whose residual has a Phi_A -> Phi_B element (held at 0 or +-1)
+inline bool method_ab(int m) { return !method_hs(m); }
 // value of the Phi_A -> Phi_B double in the residual and energy
 inline double ab_amplitude(int m) {
   if (!method_fr(m)) return 0.0;
@@ -25,6 +30,11 @@ inline double ab_amplitude(int m) {
 }
 // singlet and triplet correlation energies from dE_A and W
 inline void state_energies(int m, double dEA, double W, double& ES, double& ET) {
+  if (method_hs(m)) {
+    ES = __builtin_nan("");
+    ET = dEA;
+    return;
+  }
   if (!method_fr(m)) {
     ES = dEA + W;
     ET = dEA - W;
@@ -49,9 +59,19 @@ struct Ctx {
   hipStream_t s = nullptr;
   int device = 0;
 
-  // sizes
+  // sizes.  o, v, ov, s2 and npair describe Phi_A (both spins alike, as the adjoint and
+  // the coupling use them); the residual runs on the per-spin layout L, whose spins
+  // differ for the high-spin methods.
   int nc = 0, nv = 0, naux = 0, n = 0, o = 0, v = 0, vu = 0, npair = 0;
   int64_t ov = 0, tov = 0, s2 = 0, n2 = 0, total = 0;
+  SpinLayout L;
+  int os[2] = {0, 0}, vs[2] = {0, 0};   // per-spin occupied / virtual counts (= L.o, L.v)
+  int64_t ovs[2] = {0, 0};              // o v per spin (ph block widths)
+  int64_t oos[2] = {0, 0};              // o^2 per spin, and too2 = oos[0] + oos[1]
+  int64_t too2 = 0;
+  int npairs[2] = {0, 0};               // same-spin occupied pairs i < j per spin
+  int64_t sfr = 0, sfc = 0;             // spin-flip ph dimensions: (alpha occ, beta vir), (beta occ, alpha vir)
+  int64_t wmax = 0;                     // largest of the per-block ph and doubles sizes
 
   // borrowed inputs
   const double* B = nullptr;

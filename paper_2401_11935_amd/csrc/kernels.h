@@ -7,26 +7,58 @@
 
 namespace dcsd {
 
+// Per-spin orbital spaces of the reference determinant.  In the orbital order
+// of spin s the first o[s] orbitals are occupied and the next v[s] virtual.
+// swap_tu = 1: Phi_A (alpha order [core, t | u, virt], beta order [core, u |
+// t, virt], the beta order exchanging t and u); 0: the M_s = 1 determinant
+// Phi_T (both spins in the spatial order, alpha [core, t, u | virt], beta
+// [core | t, u, virt]).  Packed amplitudes: [t1a | t1b | t2aa | t2bb | t2ab]
+// with blocks (o0,v0), (o1,v1), (o0,o0,v0,v0), (o1,o1,v1,v1), (o0,o1,v0,v1).
+struct SpinLayout {
+  int nc = 0, n = 0;
+  int o[2] = {0, 0}, v[2] = {0, 0};
+  int swap_tu = 1;
+  __host__ __device__ int64_t ov(int s) const { return (int64_t)o[s] * v[s]; }
+  __host__ __device__ int64_t t1_off(int s) const { return s ? ov(0) : 0; }
+  __host__ __device__ int64_t t2_size(int b) const {  // 0 aa, 1 bb, 2 ab
+    return b == 2 ? ov(0) * ov(1) : ov(b) * ov(b);
+  }
+  __host__ __device__ int64_t t2_off(int b) const {
+    int64_t x = ov(0) + ov(1);
+    for (int k = 0; k < b; ++k) x += t2_size(k);
+    return x;
+  }
+  __host__ __device__ int64_t total() const { return t2_off(2) + t2_size(2); }
+  // spatial index of occupied i / virtual a of spin s
+  __host__ __device__ int occ(int s, int i) const { return swap_tu ? (i < nc ? i : nc + s) : i; }
+  __host__ __device__ int vir(int s, int a) const { return swap_tu ? (a > 0 ? nc + 1 + a : nc + 1 - s) : o[s] + a; }
+};
+
 void fill(double* p, double v, int64_t n, hipStream_t s);
 // X <- (1 - t1^T) X for `batch` n x n matrices (slice stride n2), t1 o x v; false (nothing
 // launched) when o is outside the kernel's range
 bool dress_left(double* X, const double* t1, int n, int o, int v, int64_t n2, int64_t batch, hipStream_t s);
 void axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
 void swap_tu(double* dst, const double* src, int64_t batch, int n, int nc, hipStream_t s);
-void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s);
+// J[P] = sum_{k < oa} Ba[P,k,k] + sum_{k < ob} Bb[P,k,k]
+void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int oa, int ob, hipStream_t s);
 void batch_reduce(double* dst, const double* src, int64_t nb, int64_t bstride, int rows, int cols, int64_t ld,
                   int64_t ldd, bool transpose, double alpha, hipStream_t s);
 
 // ladder
 void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int64_t p0, int64_t np, int64_t q0,
                     int64_t nq, double* V2, hipStream_t s);
+// Stack rows: [ab (o0 o1) | aa pairs i<j (P0) | bb pairs i<j (P1) | ab transposed (o0 o1)], each a
+// Vu x Vu matrix over the spatial virtual space [t, u, virt]; pair_i/pair_j list the alpha
+// pairs, then the beta pairs.
 void ladder_stack(double* S, const double* t2aa, const double* t2bb, const double* t2ab, const int* pair_i,
-                  const int* pair_j, int o, int v, int vu, int npair, int64_t rows, hipStream_t s);
+                  const int* pair_j, const SpinLayout& L, int vu, int64_t rows, hipStream_t s);
 void ladder_scatter(double* Rp, const double* Rb, int64_t rows_used, int64_t nrow_main, int64_t nsame_begin, int n,
                     int p0, int np, int q0, int nq, bool diag, hipStream_t s);
+// S: work of rows * n * max(v0, v1) doubles
 void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, const double* Rp, const double* t1a,
-                       const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
-                       int64_t npair, int n, int nc, int o, int v, hipStream_t s);
+                       const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, const SpinLayout& L,
+                       hipStream_t s);
 
 // Coupling between the two determinants: R -= K(T) * W (the caller sets R at the A->B double to 0).
 // coupling_prepare lists the patterns of the problem's sizes and checks each against its
@@ -65,13 +97,13 @@ void energy_adj(double* Tbar, double* Ibar, double* fabar, double* fbbar, const 
 // reductions (deterministic); `part` needs 1024 doubles
 void dot(const double* x, const double* y, int64_t n, double* out_dev, double* part, hipStream_t s);
 void maxabs(const double* x, int64_t n, double* out_dev, int* nonfinite_dev, double* part, hipStream_t s);
-void energy(const double* T, const double* Isc, const double* fa, const double* fb, int nc, int o, int v, int n,
+// Isc: (kc|ld) as the (ov0 + ov1) x (ov0 + ov1) spin-conserving particle-hole matrix
+void energy(const double* T, const double* Isc, const double* fa, const double* fb, const SpinLayout& L,
             double* out_dev, double* part, hipStream_t s);
 // Jacobi step Tn = T + R/(D - s - shift); J, K (spatial (pp|qq), (pq|qp)) enable the
 // Epstein-Nesbet diagonal s (NULL: s = 0).  E (may be NULL) receives Tn - T.
 void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb,
-            const double* J, const double* K, int nc, int o, int v, int n, double shift, int64_t total,
-            hipStream_t s);
+            const double* J, const double* K, const SpinLayout& L, double shift, hipStream_t s);
 // ---- low precision: FP32 or BF16 MFMA inputs, FP32 accumulation ---------------------
 // Storage element size of a low precision (4 for DCSD_PREC_FP32, 2 for DCSD_PREC_BF16).
 size_t lp_size(int precision);

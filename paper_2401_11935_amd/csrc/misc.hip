@@ -6,9 +6,6 @@
 namespace dcsd {
 
 namespace {
-__device__ inline int occ_sp(int spin, int i, int nc) { return i < nc ? i : nc + spin; }
-__device__ inline int vir_sp(int spin, int a, int nc) { return a > 0 ? nc + 1 + a : nc + 1 - spin; }
-
 inline unsigned nblocks(int64_t total, int threads, int64_t cap = 1 << 20) {
   int64_t b = (total + threads - 1) / threads;
   if (b > cap) b = cap;
@@ -38,19 +35,19 @@ void axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_
   DCSD_CHECK_LAUNCH();
 }
 
-// J[P] = sum_k Bt_a[P,k,k] + sum_k Bt_b[P,k,k] over the o occupied of each spin.
-__global__ void jvec_kernel(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o) {
+// J[P] = sum_k Bt_a[P,k,k] + sum_k Bt_b[P,k,k] over the occupied orbitals of each spin.
+__global__ void jvec_kernel(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int oa, int ob) {
   const int64_t P = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (P >= naux) return;
   const double* a = Ba + P * n * n;
   const double* b = Bb + P * n * n;
   double s = 0.0;
-  for (int k = 0; k < o; ++k) s += a[k * n + k];
-  for (int k = 0; k < o; ++k) s += b[k * n + k];
+  for (int k = 0; k < oa; ++k) s += a[k * n + k];
+  for (int k = 0; k < ob; ++k) s += b[k * n + k];
   J[P] = s;
 }
-void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s) {
-  hipLaunchKernelGGL(jvec_kernel, dim3(nblocks(naux, 256)), dim3(256), 0, s, J, Ba, Bb, naux, n, o);
+void jvector(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int oa, int ob, hipStream_t s) {
+  hipLaunchKernelGGL(jvec_kernel, dim3(nblocks(naux, 256)), dim3(256), 0, s, J, Ba, Bb, naux, n, oa, ob);
   DCSD_CHECK_LAUNCH();
 }
 
@@ -76,47 +73,54 @@ void batch_reduce(double* dst, const double* src, int64_t nb, int64_t bstride, i
 // ---------------------------------------------------------------------------
 // Ladder: amplitude stack.  Row r of the stack is a Vu x Vu matrix over the
 // union virtual space [t, u, virt] (spatial orbitals nc..n-1).  Row order:
-// [ab (o*o) | aa pairs i<j | bb pairs i<j | ab transposed (o*o)].
-__device__ inline int inv_alpha(int u) { return u >= 1 ? u - 1 : -1; }             // union pos -> alpha vir
-__device__ inline int inv_beta(int u) { return u == 0 ? 0 : (u == 1 ? -1 : u - 1); }  // union pos -> beta vir
+// [ab (o0*o1) | aa pairs i<j | bb pairs i<j | ab transposed (o0*o1)].
+// Virtual index of spin s at union position u, or -1 if u is not virtual for s.
+__device__ inline int union_to_vir(const SpinLayout& L, int s, int u) {
+  const int sp = L.nc + u;
+  if (L.swap_tu) {
+    if (sp == L.nc + s) return -1;  // t for alpha, u for beta: occupied
+    return u >= 2 ? u - 1 : 0;
+  }
+  const int a = sp - L.o[s];
+  return a >= 0 ? a : -1;
+}
 
 __global__ void ladder_stack_kernel(double* S, const double* t2aa, const double* t2bb, const double* t2ab,
-                                    const int* pair_i, const int* pair_j, int o, int v, int vu, int npair,
-                                    int64_t rows) {
+                                    const int* pair_i, const int* pair_j, SpinLayout L, int vu, int64_t rows) {
   const int64_t vu2 = (int64_t)vu * vu;
   const int64_t total = rows * vu2;
-  const int64_t s2 = (int64_t)o * o * v * v;
-  (void)s2;
+  const int o0 = L.o[0], o1 = L.o[1], v0 = L.v[0], v1 = L.v[1];
+  const int64_t oab = (int64_t)o0 * o1;
+  const int64_t np0 = (int64_t)o0 * (o0 - 1) / 2, np1 = (int64_t)o1 * (o1 - 1) / 2;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = idx / vu2;
     const int cu = (int)((idx % vu2) / vu), du = (int)(idx % vu);
     double val = 0.0;
-    const int64_t o2 = (int64_t)o * o;
-    if (r < o2) {  // ab: tau[c,d] = t2ab[i,J,c(alpha), D(beta)]
-      const int c = inv_alpha(cu), d = inv_beta(du);
-      if (c >= 0 && d >= 0) val = t2ab[(r * v + c) * v + d];
-    } else if (r < o2 + npair) {
-      const int64_t q = r - o2;
-      const int c = inv_alpha(cu), d = inv_alpha(du);
-      if (c >= 0 && d >= 0) val = t2aa[(((int64_t)pair_i[q] * o + pair_j[q]) * v + c) * v + d];
-    } else if (r < o2 + 2 * npair) {
-      const int64_t q = r - o2 - npair;
-      const int c = inv_beta(cu), d = inv_beta(du);
-      if (c >= 0 && d >= 0) val = t2bb[(((int64_t)pair_i[q] * o + pair_j[q]) * v + c) * v + d];
+    if (r < oab) {  // ab: tau[c,d] = t2ab[i,J,c(alpha), D(beta)]
+      const int c = union_to_vir(L, 0, cu), d = union_to_vir(L, 1, du);
+      if (c >= 0 && d >= 0) val = t2ab[(r * v0 + c) * v1 + d];
+    } else if (r < oab + np0) {
+      const int64_t q = r - oab;
+      const int c = union_to_vir(L, 0, cu), d = union_to_vir(L, 0, du);
+      if (c >= 0 && d >= 0) val = t2aa[(((int64_t)pair_i[q] * o0 + pair_j[q]) * v0 + c) * v0 + d];
+    } else if (r < oab + np0 + np1) {
+      const int64_t q = r - oab - np0;
+      const int c = union_to_vir(L, 1, cu), d = union_to_vir(L, 1, du);
+      if (c >= 0 && d >= 0) val = t2bb[(((int64_t)pair_i[np0 + q] * o1 + pair_j[np0 + q]) * v1 + c) * v1 + d];
     } else {  // ab transposed: tau^T[c,d] = tau[d,c]
-      const int64_t q = r - o2 - 2 * npair;
-      const int c = inv_alpha(du), d = inv_beta(cu);
-      if (c >= 0 && d >= 0) val = t2ab[(q * v + c) * v + d];
+      const int64_t q = r - oab - np0 - np1;
+      const int c = union_to_vir(L, 0, du), d = union_to_vir(L, 1, cu);
+      if (c >= 0 && d >= 0) val = t2ab[(q * v0 + c) * v1 + d];
     }
     S[idx] = val;
   }
 }
 void ladder_stack(double* S, const double* t2aa, const double* t2bb, const double* t2ab, const int* pair_i,
-                  const int* pair_j, int o, int v, int vu, int npair, int64_t rows, hipStream_t s) {
+                  const int* pair_j, const SpinLayout& L, int vu, int64_t rows, hipStream_t s) {
   const int64_t total = rows * (int64_t)vu * vu;
   hipLaunchKernelGGL(ladder_stack_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, S, t2aa, t2bb, t2ab, pair_i,
-                     pair_j, o, v, vu, npair, rows);
+                     pair_j, L, vu, rows);
   DCSD_CHECK_LAUNCH();
 }
 
@@ -152,69 +156,84 @@ void ladder_scatter(double* Rp, const double* Rb, int64_t rows_used, int64_t nro
 // B_vv - t1^T B_ov, so (ac|bd)~ = sum_pq M_ap M_bq (pc|qd)):
 //   step 1: S[row][p][b] = Rp[row][p][vir(b)] - sum_l t1[l,b] Rp[row][p][occ(l)]   (second-index spin)
 //   step 2: out[row][a][b] = S[row][vir(a)][b] - sum_k t1[k,a] S[row][occ(k)][b]   (first-index spin)
-__device__ inline void row_spins(int64_t r, int64_t o2, int64_t npair, int& s1, int& s2) {
-  if (r < o2) { s1 = 0; s2 = 1; }
-  else if (r < o2 + npair) { s1 = 0; s2 = 0; }
+// S rows hold n x vm entries, vm = max(v0, v1).
+__device__ inline void row_spins(int64_t r, int64_t oab, int64_t np0, int& s1, int& s2) {
+  if (r < oab) { s1 = 0; s2 = 1; }
+  else if (r < oab + np0) { s1 = 0; s2 = 0; }
   else { s1 = 1; s2 = 1; }
 }
 __global__ void ladder_mt1_kernel(double* S, const double* Rp, const double* t1a, const double* t1b, int64_t rows,
-                                  int64_t o2, int64_t npair, int n, int nc, int o, int v) {
-  const int64_t total = rows * n * v;
+                                  SpinLayout L) {
+  const int n = L.n, vm = L.v[0] > L.v[1] ? L.v[0] : L.v[1];
+  const int64_t total = rows * n * vm;
   const int64_t n2 = (int64_t)n * n;
+  const int64_t oab = (int64_t)L.o[0] * L.o[1], np0 = (int64_t)L.o[0] * (L.o[0] - 1) / 2;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = idx / ((int64_t)n * v);
-    const int p = (int)((idx / v) % n), b = (int)(idx % v);
+    const int64_t r = idx / ((int64_t)n * vm);
+    const int p = (int)((idx / vm) % n), b = (int)(idx % vm);
     int s1, s2;
-    row_spins(r, o2, npair, s1, s2);
+    row_spins(r, oab, np0, s1, s2);
+    const int v = L.v[s2], o = L.o[s2];
+    if (b >= v) continue;
     const double* t1 = s2 == 0 ? t1a : t1b;
     const double* row = Rp + r * n2 + (int64_t)p * n;
-    double val = row[vir_sp(s2, b, nc)];
-    for (int l = 0; l < o; ++l) val -= t1[l * v + b] * row[occ_sp(s2, l, nc)];
+    double val = row[L.vir(s2, b)];
+    for (int l = 0; l < o; ++l) val -= t1[l * v + b] * row[L.occ(s2, l)];
     S[idx] = val;
   }
 }
 __global__ void ladder_mt2_kernel(double* R2aa, double* R2bb, double* R2ab, const double* S, const double* t1a,
-                                  const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
-                                  int64_t npair, int n, int nc, int o, int v) {
-  const int64_t total = rows * v * v;
+                                  const double* t1b, const int* pair_i, const int* pair_j, int64_t rows,
+                                  SpinLayout L) {
+  const int n = L.n, vm = L.v[0] > L.v[1] ? L.v[0] : L.v[1];
+  const int64_t total = rows * vm * vm;
+  const int64_t oab = (int64_t)L.o[0] * L.o[1], np0 = (int64_t)L.o[0] * (L.o[0] - 1) / 2;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = idx / ((int64_t)v * v);
-    const int a = (int)((idx / v) % v), b = (int)(idx % v);
+    const int64_t r = idx / ((int64_t)vm * vm);
+    const int a = (int)((idx / vm) % vm), b = (int)(idx % vm);
     int s1, s2;
-    row_spins(r, o2, npair, s1, s2);
+    row_spins(r, oab, np0, s1, s2);
+    const int va = L.v[s1], vb = L.v[s2], o = L.o[s1];
+    if (a >= va || b >= vb) continue;
     const double* t1 = s1 == 0 ? t1a : t1b;
-    const double* Sr = S + r * (int64_t)n * v;
-    double val = Sr[(int64_t)vir_sp(s1, a, nc) * v + b];
-    for (int k = 0; k < o; ++k) val -= t1[k * v + a] * Sr[(int64_t)occ_sp(s1, k, nc) * v + b];
-    if (r < o2) {
-      R2ab[(r * v + a) * v + b] += val;
+    const double* Sr = S + r * (int64_t)n * vm;
+    double val = Sr[(int64_t)L.vir(s1, a) * vm + b];
+    for (int k = 0; k < o; ++k) val -= t1[k * va + a] * Sr[(int64_t)L.occ(s1, k) * vm + b];
+    if (r < oab) {
+      R2ab[(r * va + a) * vb + b] += val;
     } else {
-      const int64_t q = r < o2 + npair ? r - o2 : r - o2 - npair;
-      double* R2 = r < o2 + npair ? R2aa : R2bb;
+      const int64_t q = r - oab;  // pair index in the combined alpha-then-beta list
+      double* R2 = r < oab + np0 ? R2aa : R2bb;
       const int i = pair_i[q], j = pair_j[q];
-      R2[((((int64_t)i * o + j) * v) + a) * v + b] += val;
-      R2[((((int64_t)j * o + i) * v) + a) * v + b] -= val;
+      R2[((((int64_t)i * o + j) * va) + a) * va + b] += val;
+      R2[((((int64_t)j * o + i) * va) + a) * va + b] -= val;
     }
   }
 }
 void ladder_mt1(double* S, const double* Rp, const double* t1a, const double* t1b, int64_t rows, int64_t o2,
                 int64_t npair, int n, int nc, int o, int v, hipStream_t s) {
-  hipLaunchKernelGGL(ladder_mt1_kernel, dim3(nblocks(rows * n * v, 256)), dim3(256), 0, s, S, Rp, t1a, t1b, rows, o2,
-                     npair, n, nc, o, v);
+  (void)o2;
+  (void)npair;
+  SpinLayout L;
+  L.nc = nc;
+  L.n = n;
+  L.o[0] = L.o[1] = o;
+  L.v[0] = L.v[1] = v;
+  hipLaunchKernelGGL(ladder_mt1_kernel, dim3(nblocks(rows * n * v, 256)), dim3(256), 0, s, S, Rp, t1a, t1b, rows, L);
   DCSD_CHECK_LAUNCH();
 }
 void ladder_mtransform(double* R2aa, double* R2bb, double* R2ab, double* S, const double* Rp, const double* t1a,
-                       const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, int64_t o2,
-                       int64_t npair, int n, int nc, int o, int v, hipStream_t s) {
-  const int64_t t1tot = rows * n * v;
-  hipLaunchKernelGGL(ladder_mt1_kernel, dim3(nblocks(t1tot, 256)), dim3(256), 0, s, S, Rp, t1a, t1b, rows, o2, npair,
-                     n, nc, o, v);
+                       const double* t1b, const int* pair_i, const int* pair_j, int64_t rows, const SpinLayout& L,
+                       hipStream_t s) {
+  const int vm = L.v[0] > L.v[1] ? L.v[0] : L.v[1];
+  const int64_t t1tot = rows * L.n * vm;
+  hipLaunchKernelGGL(ladder_mt1_kernel, dim3(nblocks(t1tot, 256)), dim3(256), 0, s, S, Rp, t1a, t1b, rows, L);
   DCSD_CHECK_LAUNCH();
-  const int64_t t2tot = rows * v * v;
+  const int64_t t2tot = rows * (int64_t)vm * vm;
   hipLaunchKernelGGL(ladder_mt2_kernel, dim3(nblocks(t2tot, 256)), dim3(256), 0, s, R2aa, R2bb, R2ab, S, t1a, t1b,
-                     pair_i, pair_j, rows, o2, npair, n, nc, o, v);
+                     pair_i, pair_j, rows, L);
   DCSD_CHECK_LAUNCH();
 }
 
@@ -226,36 +245,35 @@ __device__ inline double pq_pq(const double* J, const double* K, int n, int sp, 
 }
 
 __global__ void jacobi_kernel(double* Tn, double* E, const double* T, const double* R, const double* fa,
-                              const double* fb, const double* J, const double* K, int nc, int o, int v, int n,
-                              double shift) {
-  const int64_t ov = (int64_t)o * v, s2 = ov * ov;
-  const int64_t total = 2 * ov + 3 * s2;
+                              const double* fb, const double* J, const double* K, SpinLayout L, double shift) {
+  const int n = L.n;
+  const int64_t t1end = L.t2_off(0), total = L.total();
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
        x += (int64_t)gridDim.x * blockDim.x) {
     double D;
-    if (x < 2 * ov) {
-      const double* f = x < ov ? fa : fb;
-      const int i = (int)((x % ov) / v), a = (int)(x % v);
+    if (x < t1end) {
+      const int sp = x < L.ov(0) ? 0 : 1;
+      const int64_t y = x - L.t1_off(sp);
+      const int v = L.v[sp], o = L.o[sp];
+      const double* f = sp ? fb : fa;
+      const int i = (int)(y / v), a = (int)(y % v);
       D = f[(int64_t)i * n + i] - f[(int64_t)(o + a) * n + o + a];
-      if (J) {
-        const int sp = x < ov ? 0 : 1;
-        D += pq_pq(J, K, n, sp, occ_sp(sp, i, nc), sp, vir_sp(sp, a, nc));  // D - s, s = -<ia||ia>
-      }
+      if (J) D += pq_pq(J, K, n, sp, L.occ(sp, i), sp, L.vir(sp, a));  // D - s, s = -<ia||ia>
     } else {
-      const int64_t y = x - 2 * ov;
-      const int blk = (int)(y / s2);
-      int64_t r = y % s2;
-      const int b = (int)(r % v); r /= v;
-      const int a = (int)(r % v); r /= v;
-      const int j = (int)(r % o);
-      const int i = (int)(r / o);
-      const double* fi = blk == 1 ? fb : fa;
-      const double* fj = blk == 0 ? fa : fb;
-      D = fi[(int64_t)i * n + i] + fj[(int64_t)j * n + j] - fi[(int64_t)(o + a) * n + o + a] -
-          fj[(int64_t)(o + b) * n + o + b];
+      const int blk = x < L.t2_off(1) ? 0 : (x < L.t2_off(2) ? 1 : 2);
+      const int si = blk == 1 ? 1 : 0, sj = blk == 0 ? 0 : 1;
+      int64_t r = x - L.t2_off(blk);
+      const int vi = L.v[si], vj = L.v[sj], oi = L.o[si], oj = L.o[sj];
+      const int b = (int)(r % vj); r /= vj;
+      const int a = (int)(r % vi); r /= vi;
+      const int j = (int)(r % oj);
+      const int i = (int)(r / oj);
+      const double* fi = si ? fb : fa;
+      const double* fj = sj ? fb : fa;
+      D = fi[(int64_t)i * n + i] + fj[(int64_t)j * n + j] - fi[(int64_t)(oi + a) * n + oi + a] -
+          fj[(int64_t)(oj + b) * n + oj + b];
       if (J) {
-        const int si = blk == 1 ? 1 : 0, sj = blk == 0 ? 0 : 1;
-        const int pi = occ_sp(si, i, nc), pj = occ_sp(sj, j, nc), pa = vir_sp(si, a, nc), pb = vir_sp(sj, b, nc);
+        const int pi = L.occ(si, i), pj = L.occ(sj, j), pa = L.vir(si, a), pb = L.vir(sj, b);
         const double sEN = pq_pq(J, K, n, si, pa, sj, pb) + pq_pq(J, K, n, si, pi, sj, pj) -
                            pq_pq(J, K, n, si, pi, si, pa) - pq_pq(J, K, n, si, pi, sj, pb) -
                            pq_pq(J, K, n, sj, pj, si, pa) - pq_pq(J, K, n, sj, pj, sj, pb);
@@ -270,10 +288,9 @@ __global__ void jacobi_kernel(double* Tn, double* E, const double* T, const doub
   }
 }
 void jacobi(double* Tn, double* E, const double* T, const double* R, const double* fa, const double* fb,
-            const double* J, const double* K, int nc, int o, int v, int n, double shift, int64_t total,
-            hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_kernel, dim3(nblocks(total, 256)), dim3(256), 0, s, Tn, E, T, R, fa, fb, J, K, nc, o, v,
-                     n, shift);
+            const double* J, const double* K, const SpinLayout& L, double shift, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_kernel, dim3(nblocks(L.total(), 256)), dim3(256), 0, s, Tn, E, T, R, fa, fb, J, K, L,
+                     shift);
   DCSD_CHECK_LAUNCH();
 }
 

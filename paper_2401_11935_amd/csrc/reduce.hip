@@ -70,48 +70,50 @@ void maxabs(const double* x, int64_t n, double* out_dev, int* nonfinite_dev, dou
   DCSD_CHECK_LAUNCH();
 }
 
-// Energy of Phi_A's amplitudes (undressed integrals):
-//   dE_A = sum_s f^s_ia t1^s_ia + 1/2 sum (ia|jb)_ss tau^ss + 1/2 sum (IA|JB) tau^bb
+// Energy of the reference's amplitudes (undressed integrals):
+//   dE = sum_s f^s_ia t1^s_ia + 1/2 sum (ia|jb)_ss tau^ss + 1/2 sum (IA|JB) tau^bb
 //        + sum (ia|JB) tau^ab,   tau = t2 + t1 t1 (antisymmetrised for equal spins).
-__global__ void energy_partial(const double* T, const double* Isc, const double* fa, const double* fb, int nc, int o,
-                               int v, int n, double* part) {
-  const int64_t ov = (int64_t)o * v, s2 = ov * ov, tov = 2 * ov;
-  const int64_t total = 2 * ov + 3 * s2;
+__global__ void energy_partial(const double* T, const double* Isc, const double* fa, const double* fb, SpinLayout L,
+                               double* part) {
+  const int n = L.n;
+  const int64_t tov = L.ov(0) + L.ov(1), total = L.total(), t1end = L.t2_off(0);
   double acc = 0.0;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total;
        x += (int64_t)gridDim.x * blockDim.x) {
-    if (x < 2 * ov) {
-      const int spin = (int)(x / ov);
-      const int i = (int)((x % ov) / v), a = (int)(x % v);
+    if (x < t1end) {
+      const int spin = x < L.ov(0) ? 0 : 1;
+      const int64_t y = x - L.t1_off(spin);
+      const int v = L.v[spin], o = L.o[spin];
+      const int i = (int)(y / v), a = (int)(y % v);
       const double* f = spin ? fb : fa;
       acc += f[(int64_t)i * n + o + a] * T[x];
       continue;
     }
-    const int64_t y = x - 2 * ov;
-    const int blk = (int)(y / s2);
-    int64_t r = y % s2;
-    const int b = (int)(r % v); r /= v;
-    const int a = (int)(r % v); r /= v;
-    const int j = (int)(r % o);
-    const int i = (int)(r / o);
+    const int blk = x < L.t2_off(1) ? 0 : (x < L.t2_off(2) ? 1 : 2);
     const int si = blk == 1 ? 1 : 0, sj = blk == 0 ? 0 : 1;
-    const double* t1i = T + si * ov;
-    const double* t1j = T + sj * ov;
-    double tau = T[x] + t1i[i * v + a] * t1j[j * v + b];
+    int64_t r = x - L.t2_off(blk);
+    const int vi = L.v[si], vj = L.v[sj], oj = L.o[sj];
+    const int b = (int)(r % vj); r /= vj;
+    const int a = (int)(r % vi); r /= vi;
+    const int j = (int)(r % oj);
+    const int i = (int)(r / oj);
+    const double* t1i = T + L.t1_off(si);
+    const double* t1j = T + L.t1_off(sj);
+    double tau = T[x] + t1i[i * vi + a] * t1j[j * vj + b];
     double fac = 1.0;
     if (blk < 2) {
-      tau -= t1i[i * v + b] * t1j[j * v + a];
+      tau -= t1i[i * vi + b] * t1j[j * vj + a];
       fac = 0.5;
     }
-    const double I = Isc[(si * ov + (int64_t)i * v + a) * tov + sj * ov + (int64_t)j * v + b];
+    const double I = Isc[(L.t1_off(si) + (int64_t)i * vi + a) * tov + L.t1_off(sj) + (int64_t)j * vj + b];
     acc += fac * I * tau;
   }
   acc = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
-void energy(const double* T, const double* Isc, const double* fa, const double* fb, int nc, int o, int v, int n,
+void energy(const double* T, const double* Isc, const double* fa, const double* fb, const SpinLayout& L,
             double* out_dev, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(energy_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, T, Isc, fa, fb, nc, o, v, n, part);
+  hipLaunchKernelGGL(energy_partial, dim3(RED_BLOCKS), dim3(RED_THREADS), 0, s, T, Isc, fa, fb, L, part);
   DCSD_CHECK_LAUNCH();
   hipLaunchKernelGGL(final_sum, dim3(1), dim3(RED_THREADS), 0, s, (const double*)part, RED_BLOCKS, out_dev, 0);
   DCSD_CHECK_LAUNCH();

@@ -124,8 +124,8 @@ void rswap(double* dst, const double* src, int64_t batch, int n, int nc, hipStre
   }
   swap_tu(dst, src, batch, n, nc, s);
 }
-void rjvec(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int o, hipStream_t s) {
-  if (t_tape) {
+void rjvec(double* J, const double* Ba, const double* Bb, int64_t naux, int n, int oa, int ob, hipStream_t s) {
+  if (t_tape) {  // (the adjoint runs for Phi_A, oa == ob)
     TapeOp op;
     op.kind = OP_JVEC;
     op.dst = J;
@@ -133,10 +133,10 @@ void rjvec(double* J, const double* Ba, const double* Bb, int64_t naux, int n, i
     op.src2 = Bb;
     op.n = naux;
     op.ints[0] = n;
-    op.ints[1] = o;
+    op.ints[1] = oa;
     tape_op(op);
   }
-  jvector(J, Ba, Bb, naux, n, o, s);
+  jvector(J, Ba, Bb, naux, n, oa, ob, s);
 }
 void rbreduce(double* dst, const double* src, int64_t nbat, int64_t bstride, int rows, int cols, int64_t ld,
               int64_t ldd, bool transpose, double alpha, hipStream_t s) {
@@ -211,22 +211,25 @@ void Ctx::release() {
 //   f^s += sum_P J_P B^s[P] - sum_P sum_{k<o} B^s[P,:,k] B^s[P,k,:],
 //   J_P = sum_{s'} sum_{k<o} B^{s'}[P,k,k].   fout must already hold h^s.
 static void add_two_electron_fock(Ctx& c, double* const fout[2], double* const Bsrc[2]) {
-  const int n = c.n, o = c.o;
+  const int n = c.n;
   const int64_t naux = c.naux, n2 = c.n2;
-  rjvec(c.Jv, Bsrc[0], Bsrc[1], naux, n, o, c.s);
+  rjvec(c.Jv, Bsrc[0], Bsrc[1], naux, n, c.os[0], c.os[1], c.s);
   for (int sp = 0; sp < 2; ++sp) {
+    const int o = c.os[sp];
     G(1, n2, naux).A(c.Jv, naux, false).B(Bsrc[sp], n2, true).C(fout[sp], n2).ab(1.0, 1.0).run(c);
+    if (o == 0) continue;
     copyN(c.Xk, Bsrc[sp], {n, naux, o}, {naux * o, o, 1}, {n, n2, 1}, 1.0, 0.0, c.s);
     copyN(c.Yk, Bsrc[sp], {naux, o, n}, {(int64_t)o * n, n, 1}, {n2, n, 1}, 1.0, 0.0, c.s);
     G(n, n, naux * o).A(c.Xk, naux * o, false).B(c.Yk, n, true).C(fout[sp], n).ab(-1.0, 1.0).run(c);
   }
 }
 
-// X <- (1 - t1^T) X (1 + t1) for a batch of n x n matrices in spin order
+// X <- (1 - t1^T) X (1 + t1) for a batch of n x n matrices in the order of spin sp
 // (t1 is o x v; rows/cols 0..o-1 occupied, o..n-1 virtual).
-static void dress(Ctx& c, double* X, const double* t1, int64_t batch) {
-  const int n = c.n, o = c.o, v = c.v;
+static void dress(Ctx& c, double* X, const double* t1, int64_t batch, int sp) {
+  const int n = c.n, o = c.os[sp], v = c.vs[sp];
   const int64_t n2 = c.n2;
+  if (o == 0) return;
   // X[:, 0:o] += X[:, o:n] t1^T
   G(n, o, v).A(X + o, n, false).B(t1, v, false).C(X, n).ab(1.0, 1.0).batch(batch, n2, 0, n2).run(c);
   // X[o:n, :] -= t1^T X[0:o, :]: a streaming kernel (under a tape, a recorded GEMM)
@@ -249,6 +252,9 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
   if (!(cfg.level_shift >= 0.0)) throw ArgError("level_shift must be >= 0");
   if (cfg.precond != DCSD_PRECOND_ORBITAL && cfg.precond != DCSD_PRECOND_EN) throw ArgError("unknown precond");
+  const bool hs = method_hs(cfg.method);
+  if (hs && cfg.nc < 1) throw ArgError("the high-spin methods need nc >= 1");
+  if (hs && cfg.adjoint) throw ArgError("the adjoint is not available for the high-spin methods");
   if (!Bin || !Fin) throw ArgError("B and F must be device pointers");
   B = Bin;
   F = Fin;
@@ -261,32 +267,53 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   vu = nv + 2;
   npair = o * (o - 1) / 2;
   ov = (int64_t)o * v;
-  tov = 2 * ov;
   s2 = ov * ov;
   n2 = (int64_t)n * n;
-  total = 2 * ov + 3 * s2;
+  // per-spin layout: Phi_A (t alpha, u beta) or the M_s = 1 determinant (t, u alpha)
+  L.nc = nc;
+  L.n = n;
+  L.swap_tu = hs ? 0 : 1;
+  L.o[0] = hs ? nc + 2 : o;
+  L.o[1] = hs ? nc : o;
+  L.v[0] = n - L.o[0];
+  L.v[1] = n - L.o[1];
+  for (int sp = 0; sp < 2; ++sp) {
+    os[sp] = L.o[sp];
+    vs[sp] = L.v[sp];
+    ovs[sp] = L.ov(sp);
+    oos[sp] = (int64_t)os[sp] * os[sp];
+    npairs[sp] = os[sp] * (os[sp] - 1) / 2;
+  }
+  too2 = oos[0] + oos[1];
+  tov = ovs[0] + ovs[1];
+  sfr = (int64_t)os[0] * vs[1];
+  sfc = (int64_t)os[1] * vs[0];
+  total = L.total();
+  wmax = std::max({ovs[0] * ovs[0], ovs[1] * ovs[1], ovs[0] * ovs[1], sfr * sfc, sfr * sfr, sfc * sfc});
   if ((int64_t)naux * n2 > (int64_t)1 << 40) throw ArgError("problem too large");
   DCSD_HIP(hipGetDevice(&device));
 
   const int64_t NA = naux;
   const int64_t o2 = (int64_t)o * o;
   // ---- allocations ------------------------------------------------------------
+  (void)o2;
   Bs[0] = const_cast<double*>(B);
-  Bs[1] = alloc(NA * n2);
+  // beta-order factors: Phi_A exchanges t and u; the high-spin determinant keeps the order
+  Bs[1] = hs ? const_cast<double*>(B) : alloc(NA * n2);
   for (int sp = 0; sp < 2; ++sp) {
     h[sp] = alloc(n2);
     f[sp] = alloc(n2);
     Bt[sp] = alloc(NA * n2);
     ft[sp] = alloc(n2);
-    Xv[sp] = alloc((int64_t)v * v);
-    Fvv[sp] = alloc((int64_t)v * v);
-    Yo[sp] = alloc(o2);
-    Foo[sp] = alloc(o2);
-    QX1[sp] = alloc(s2);
-    QX2[sp] = alloc(s2);
-    QY1[sp] = alloc(s2);
-    QY2[sp] = alloc(s2);
-    KJPQ[sp] = alloc(2 * o2 * n2);
+    Xv[sp] = alloc((int64_t)vs[sp] * vs[sp]);
+    Fvv[sp] = alloc((int64_t)vs[sp] * vs[sp]);
+    Yo[sp] = alloc(oos[sp]);
+    Foo[sp] = alloc(oos[sp]);
+    QX1[sp] = alloc(wmax);
+    QX2[sp] = alloc(wmax);
+    QY1[sp] = alloc(wmax);
+    QY2[sp] = alloc(wmax);
+    KJPQ[sp] = alloc(too2 * n2);
   }
   Bl = alloc(NA * n * vu);
   Jpq = alloc(n2);
@@ -294,43 +321,47 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   Isc = alloc(tov * tov);
   if (method_cc(cfg.method)) {
     Icc = alloc(tov * tov);
-    Isf1 = alloc(s2);
-    Isf2 = alloc(s2);
+    Isf1 = alloc(sfr * sfc);
+    Isf2 = alloc(sfr * sfc);
   }
-  for (int k = 0; k < 3; ++k) Ikl[k] = alloc(s2);
+  for (int k = 0; k < 3; ++k) Ikl[k] = alloc(wmax);
   Tw = alloc(total);
   Jv = alloc(NA);
   Xk = alloc((int64_t)n * NA * std::max(o, nc + 2));
   Yk = alloc((int64_t)n * NA * std::max(o, nc + 2));
   Bov = alloc(NA * tov);
   Bvo = alloc(NA * tov);
-  Boo = alloc(NA * 2 * o2);
+  Boo = alloc(NA * too2);
   Tsc = alloc(tov * tov);
-  Tsf1 = alloc(s2);
+  Tsf1 = alloc(sfr * sfc);
   Z = alloc(NA * tov);
-  out1 = alloc(NA * ov);
-  out2 = alloc(NA * ov);
+  out1 = alloc(NA * std::max(ovs[0], ovs[1]));
+  out2 = alloc(NA * std::max(ovs[0], ovs[1]));
   fvec = alloc(tov);
   KCBJ = alloc(tov * tov);
   Dvo = alloc(tov * tov);
-  OOOO = alloc(4 * o2 * o2);
+  OOOO = alloc(too2 * too2);
   Ring = alloc(tov * tov);
-  Wsf1 = alloc(s2);
-  Wsf2 = alloc(s2);
-  Rsf1 = alloc(s2);
-  Rsf2 = alloc(s2);
-  P1 = alloc(s2);
-  P2 = alloc(s2);
-  Whh = alloc(o2 * o2);
+  Wsf1 = alloc(sfc * sfc);
+  Wsf2 = alloc(sfr * sfr);
+  Rsf1 = alloc(sfr * sfc);
+  Rsf2 = alloc(sfr * sfc);
+  P1 = alloc(wmax);
+  P2 = alloc(wmax);
+  {
+    const int64_t hh = std::max({oos[0], oos[1], (int64_t)os[0] * os[1]});
+    Whh = alloc(hh * hh);
+  }
   lb = cfg.ladder_block > 0 ? std::min(cfg.ladder_block, n) : std::min(32, n);
-  rows_main = o2 + 2 * (int64_t)npair;
-  rows_all = rows_main + o2;
+  const int64_t oab = (int64_t)os[0] * os[1];
+  rows_main = oab + npairs[0] + npairs[1];
+  rows_all = rows_main + oab;
   const int64_t vu2 = (int64_t)vu * vu;
   Tstack = alloc(rows_all * vu2);
   V2 = alloc((int64_t)lb * lb * vu2);
   Rb = alloc(rows_all * (int64_t)lb * lb);
   Rp = alloc(rows_main * n2);
-  Smt = alloc(rows_main * (int64_t)n * v);
+  Smt = alloc(rows_main * (int64_t)n * std::max(vs[0], vs[1]));
   split_cap = 32;
   split = alloc(split_cap * rows_all * (int64_t)lb * lb);
   if (cfg.precision != DCSD_PREC_FP64) {
@@ -345,7 +376,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     // padding of both operands is zeroed once here and nothing writes it afterwards
     fill((double*)TstackL, 0.0, (rows_all * kp * es + 7) / 8, s);
     fill((double*)V2L, 0.0, ((int64_t)lb * lb * kp * es + 7) / 8, s);
-    lp_cap = tov * lp_ld(tov);
+    const int64_t lpm = std::max({tov, sfr, sfc});
+    lp_cap = lpm * lp_ld(lpm);
     lpA = lp_alloc(lp_cap);
     lpB = lp_alloc(lp_cap);
     lwork_cap = std::max<int64_t>(split_cap * rows_all * (int64_t)lb * lb, (int64_t)1 << 22);
@@ -353,7 +385,8 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     TstackR = alloc(rows_all * vu2);
     RpR = alloc(rows_main * n2);
     // ring sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 = spin-flip I T (CCSD); 4, 5 = spin-flip rings
-    const int64_t sz[Ctx::kSites] = {tov * tov, tov * tov, s2, s2, s2, s2};
+    const int64_t sf2 = std::max(sfr, sfc) * std::max(sfr, sfc);
+    const int64_t sz[Ctx::kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2};
     const bool av[Ctx::kSites] = {false, true, false, false, true, true};
     for (int k = 0; k < Ctx::kSites; ++k) {
       if ((k == 2 || k == 3) && !method_cc(cfg.method)) continue;
@@ -377,23 +410,26 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   Ev = alloc(total);
   Tbest = alloc(total);
   {
+    // occupied pairs i < j: the alpha pairs, then the beta pairs
     std::vector<int> pi, pj;
-    for (int i = 0; i < o; ++i)
-      for (int j = i + 1; j < o; ++j) {
-        pi.push_back(i);
-        pj.push_back(j);
-      }
-    pair_i = alloc_int(std::max(npair, 1));
-    pair_j = alloc_int(std::max(npair, 1));
-    if (npair > 0) {
-      DCSD_HIP(hipMemcpyAsync(pair_i, pi.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
-      DCSD_HIP(hipMemcpyAsync(pair_j, pj.data(), npair * sizeof(int), hipMemcpyHostToDevice, s));
+    for (int sp = 0; sp < 2; ++sp)
+      for (int i = 0; i < os[sp]; ++i)
+        for (int j = i + 1; j < os[sp]; ++j) {
+          pi.push_back(i);
+          pj.push_back(j);
+        }
+    const int np = (int)pi.size();
+    pair_i = alloc_int(std::max(np, 1));
+    pair_j = alloc_int(std::max(np, 1));
+    if (np > 0) {
+      DCSD_HIP(hipMemcpyAsync(pair_i, pi.data(), np * sizeof(int), hipMemcpyHostToDevice, s));
+      DCSD_HIP(hipMemcpyAsync(pair_j, pj.data(), np * sizeof(int), hipMemcpyHostToDevice, s));
       DCSD_HIP(hipStreamSynchronize(s));  // host sources go out of scope
     }
   }
 
   // ---- coupling patterns (checked against their compile-time tables) -----------
-  coupling_prepare(nc, nv, coup_launch);
+  if (!hs) coupling_prepare(nc, nv, coup_launch);
   // external inputs take part in the adjoint's buffer registry (not owned)
   reg(const_cast<double*>(B), NA * n2, false);
   reg(const_cast<double*>(F), n2, false);
@@ -407,8 +443,9 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
 // carry no derivative).
 void Ctx::build_constants(bool full) {
   const int64_t NA = naux;
-  // ---- beta-order factors: exchange t and u in both orbital indices ---------------
-  rswap(Bs[1], Bs[0], NA, n, nc, s);
+  const bool hs = method_hs(cfg.method);
+  // ---- beta-order factors: exchange t and u in both orbital indices (Phi_A) ---------
+  if (!hs) rswap(Bs[1], Bs[0], NA, n, nc, s);
 
   // ---- one-electron Hamiltonian h = F - G_avg ---------------------------------------
   // G_avg = sum_core [2 J_k - K_k] + sum_{t,u} [J_x - K_x / 2]
@@ -427,7 +464,10 @@ void Ctx::build_constants(bool full) {
     copyN(Xk + nc, B + nc, {n, NA, 2}, {NA * K2, K2, 1}, {n, n2, 1}, 0.5, 0.0, s);
     copyN(Yk, B, {NA, K2, n}, {(int64_t)K2 * n, n, 1}, {n2, n, 1}, 1.0, 0.0, s);
     G(n, n, NA * K2).A(Xk, NA * K2, false).B(Yk, n, true).C(h[0], n).ab(1.0, 1.0).run(*this);
-    rswap(h[1], h[0], 1, n, nc, s);
+    if (hs)
+      rcopy(h[1], h[0], n2, s);
+    else
+      rswap(h[1], h[0], 1, n, nc, s);
   }
   // ---- Fock matrices of Phi_A (undressed) ------------------------------------------
   for (int sp = 0; sp < 2; ++sp)
@@ -435,39 +475,54 @@ void Ctx::build_constants(bool full) {
   add_two_electron_fock(*this, f, Bs);
 
   // ---- (kc|ld) in the spin-conserving particle-hole layout --------------------------
+  // Isc[(s,k,c),(s',l,d)], rows and columns [alpha (o0 v0) | beta (o1 v1)]
   for (int sp = 0; sp < 2; ++sp)
-    copyN(Bov + sp * ov, Bs[sp] + o, {NA, o, v}, {tov, v, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    copyN(Bov + L.t1_off(sp), Bs[sp] + os[sp], {NA, os[sp], vs[sp]}, {tov, vs[sp], 1}, {n2, n, 1}, 1.0, 0.0, s);
   G(tov, tov, NA).A(Bov, tov, true).B(Bov, tov, true).C(Isc, tov).run(*this);
 
   // Permuted copies used by the X, Y and hole-hole intermediates.
-  const int64_t vt = (int64_t)v * tov;
+  const int oa = os[0], ob = os[1], va = vs[0], vb = vs[1];
+  const int64_t ab_blk = ovs[0];  // Isc + ab_blk: the alpha-row, beta-column block
   for (int sp = 0; sp < 2; ++sp) {
-    const int64_t base = sp * ov * (tov + 1);
+    const int o_ = os[sp], v_ = vs[sp];
+    const int64_t base = L.t1_off(sp) * (tov + 1), vt = (int64_t)v_ * tov;
+    const std::initializer_list<int64_t> d4 = {o_ * (int64_t)v_ * v_, (int64_t)v_ * v_, v_, 1};
     // QX1[(k,l,c)][d] = (kc|ld)_ss
-    copyN(QX1[sp], Isc + base, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+    copyN(QX1[sp], Isc + base, {o_, o_, v_, v_}, d4, {vt, v_, tov, 1}, 1.0, 0.0, s);
     // QY1[l][(k,c,d)] = (kc|ld)_ss
-    copyN(QY1[sp], Isc + base, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {v, vt, tov, 1}, 1.0, 0.0, s);
+    copyN(QY1[sp], Isc + base, {o_, o_, v_, v_}, d4, {v_, vt, tov, 1}, 1.0, 0.0, s);
     // Ikl[(k,l),(c,d)] = (kc|ld)_ss
-    copyN(Ikl[sp], Isc + base, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+    copyN(Ikl[sp], Isc + base, {o_, o_, v_, v_}, d4, {vt, v_, tov, 1}, 1.0, 0.0, s);
   }
-  // QX2a[(k,L,C)][d] = (kd|LC);  QX2b[(l,K,c)][D] = (KD|lc)
-  copyN(QX2[0], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, 1, tov}, 1.0, 0.0, s);
-  copyN(QX2[1], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
-  // QY2a[l][(K,d,C)] = (KC|ld);  QY2b[L][(k,c,D)] = (kc|LD)
-  copyN(QY2[0], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
-  copyN(QY2[1], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {v, vt, tov, 1}, 1.0, 0.0, s);
+  const int64_t vta = (int64_t)va * tov;
+  // QX2a[(k,L,C)][d] = (kd|LC)  (k, d alpha; L, C beta)
+  copyN(QX2[0], Isc + ab_blk, {oa, ob, vb, va}, {ob * (int64_t)vb * va, (int64_t)vb * va, va, 1}, {vta, vb, 1, tov},
+        1.0, 0.0, s);
+  // QX2b[(l,K,c)][D] = (KD|lc)  (l, c alpha; K, D beta)
+  copyN(QX2[1], Isc + ab_blk, {oa, ob, va, vb}, {ob * (int64_t)va * vb, (int64_t)va * vb, vb, 1}, {vta, vb, tov, 1},
+        1.0, 0.0, s);
+  // QY2a[l][(K,d,C)] = (KC|ld)  (l, d alpha; K, C beta)
+  copyN(QY2[0], Isc + ab_blk, {oa, ob, va, vb}, {ob * (int64_t)va * vb, (int64_t)va * vb, vb, 1}, {vta, vb, tov, 1},
+        1.0, 0.0, s);
+  // QY2b[L][(k,c,D)] = (kc|LD)  (k, c alpha; L, D beta)
+  copyN(QY2[1], Isc + ab_blk, {ob, oa, va, vb}, {oa * (int64_t)va * vb, (int64_t)va * vb, vb, 1}, {vb, vta, tov, 1},
+        1.0, 0.0, s);
   // Ikl_ab[(k,L),(c,D)] = (kc|LD)
-  copyN(Ikl[2], Isc + ov, {o, o, v, v}, {o * (int64_t)v * v, (int64_t)v * v, v, 1}, {vt, v, tov, 1}, 1.0, 0.0, s);
+  copyN(Ikl[2], Isc + ab_blk, {oa, ob, va, vb}, {ob * (int64_t)va * vb, (int64_t)va * vb, vb, 1}, {vta, vb, tov, 1},
+        1.0, 0.0, s);
   if (method_cc(cfg.method)) {
     // <kl||cd> = (kc|ld) - (kd|lc): exchange part on the equal-spin blocks
     rcopy(Icc, Isc, tov * tov, s);
     for (int sp = 0; sp < 2; ++sp) {
-      const int64_t base = sp * ov * (tov + 1);
-      copyN(Icc + base, Isc + base, {o, v, o, v}, {vt, tov, v, 1}, {vt, 1, v, tov}, -1.0, 1.0, s);
+      const int o_ = os[sp], v_ = vs[sp];
+      const int64_t base = L.t1_off(sp) * (tov + 1), vt = (int64_t)v_ * tov;
+      copyN(Icc + base, Isc + base, {o_, v_, o_, v_}, {vt, tov, v_, 1}, {vt, 1, v_, tov}, -1.0, 1.0, s);
     }
-    // spin-flip blocks: Isf1[(K,c),(l,D)] = -(KD|lc), Isf2[(k,C),(L,d)] = -(kd|LC)
-    copyN(Isf1, Isc + ov * tov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
-    copyN(Isf2, Isc + ov, {o, v, o, v}, {v * ov, ov, v, 1}, {vt, 1, v, tov}, -1.0, 0.0, s);
+    // spin-flip blocks: Isf1[(K,c),(l,D)] = -(KD|lc) (rows beta occ x alpha vir, columns alpha occ x
+    // beta vir), Isf2[(k,C),(L,d)] = -(kd|LC) (rows alpha occ x beta vir, columns beta occ x alpha vir)
+    const int64_t vtb = (int64_t)vb * tov;
+    copyN(Isf1, Isc + ovs[0] * tov, {ob, va, oa, vb}, {va * sfr, sfr, vb, 1}, {vtb, 1, va, tov}, -1.0, 0.0, s);
+    copyN(Isf2, Isc + ab_blk, {oa, vb, ob, va}, {vb * sfc, sfc, va, 1}, {vta, 1, vb, tov}, -1.0, 0.0, s);
   }
   // ---- ladder factor Bl[P][p][c] = B[P][p][nc + c], c over [t, u, virt] ------------
   copyN(Bl, B + nc, {NA, n, vu}, {(int64_t)n * vu, vu, 1}, {n2, n, 1}, 1.0, 0.0, s);
@@ -487,7 +542,7 @@ void Ctx::build_constants(bool full) {
       DCSD_HIP(hipMemcpyAsync(hd.data(), h[sp], n2 * sizeof(double), hipMemcpyDeviceToHost, s));
       DCSD_HIP(hipMemcpyAsync(fd.data(), f[sp], n2 * sizeof(double), hipMemcpyDeviceToHost, s));
       DCSD_HIP(hipStreamSynchronize(s));
-      for (int k = 0; k < o; ++k) e += 0.5 * (hd[(int64_t)k * n + k] + fd[(int64_t)k * n + k]);
+      for (int k = 0; k < os[sp]; ++k) e += 0.5 * (hd[(int64_t)k * n + k] + fd[(int64_t)k * n + k]);
     }
     e_ref = e;
   }
@@ -506,71 +561,81 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
     for (auto& x : site) x.valid = false;
   }
   const uint32_t mask = cfg.term_mask;
-  const int64_t NA = naux, o2 = (int64_t)o * o, vv = (int64_t)v * v, ov2 = o * vv;
+  const int64_t NA = naux;
   const bool cc = method_cc(cfg.method);
   const double sdc = cc ? 1.0 : 0.5;  // weight of the Fock-like T2*T2 terms (Q_c, Q_d)
+  const int oa = os[0], ob = os[1], va = vs[0], vb = vs[1];
+  const int64_t oab = (int64_t)oa * ob;
   hipEvent_t ev_res;
   const int rec_res = tbegin(&ev_res);
 
   // amplitudes with the Phi_A -> Phi_B double set: zero in the two-determinant methods,
-  // +1 or -1 in the fixed-reference ones
+  // +1 or -1 in the fixed-reference ones (the high-spin methods have no such element)
   rcopy(Tw, T, total, s);
-  const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  rfill(Tw + ab_pos, ab_amplitude(cfg.method), 1, s);
-  const double* t1[2] = {Tw, Tw + ov};
-  const double* t2aa = Tw + 2 * ov;
-  const double* t2bb = t2aa + s2;
-  const double* t2ab = t2bb + s2;
+  const int64_t ab_pos = L.t2_off(2) + (((int64_t)nc * ob + nc) * va + 0) * vb + 0;
+  if (method_ab(cfg.method)) rfill(Tw + ab_pos, ab_amplitude(cfg.method), 1, s);
+  const double* t1[2] = {Tw + L.t1_off(0), Tw + L.t1_off(1)};
+  const double* t2aa = Tw + L.t2_off(0);
+  const double* t2bb = Tw + L.t2_off(1);
+  const double* t2ab = Tw + L.t2_off(2);
   const double* t2ss[2] = {t2aa, t2bb};
   double* R1 = R;
-  double* R2ss[2] = {R + 2 * ov, R + 2 * ov + s2};
-  double* R2ab = R + 2 * ov + 2 * s2;
+  double* R2ss[2] = {R + L.t2_off(0), R + L.t2_off(1)};
+  double* R2ab = R + L.t2_off(2);
   rfill(R, 0.0, total, s);
 
   // ---- T1 dressing of the DF factors and of the Fock matrix ------------------------
   for (int sp = 0; sp < 2; ++sp) {
     rcopy(Bt[sp], Bs[sp], NA * n2, s);
-    dress(*this, Bt[sp], t1[sp], NA);
+    dress(*this, Bt[sp], t1[sp], NA, sp);
     rcopy(ft[sp], h[sp], n2, s);
-    dress(*this, ft[sp], t1[sp], 1);
+    dress(*this, ft[sp], t1[sp], 1, sp);
   }
   add_two_electron_fock(*this, ft, Bt);
 
   // ---- dressed factor blocks -----------------------------------------------------
+  // Bov[P][(s,k,c)], Bvo[P][(s,k,c)] = B~[P][c][k], Boo[P][(s,k,i)] (rows [alpha | beta])
   for (int sp = 0; sp < 2; ++sp) {
-    copyN(Bov + sp * ov, Bt[sp] + o, {NA, o, v}, {tov, v, 1}, {n2, n, 1}, 1.0, 0.0, s);
-    copyN(Bvo + sp * ov, Bt[sp] + (int64_t)o * n, {NA, o, v}, {tov, v, 1}, {n2, 1, n}, 1.0, 0.0, s);
-    copyN(Boo + sp * o2, Bt[sp], {NA, o, o}, {2 * o2, o, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    const int o_ = os[sp], v_ = vs[sp];
+    copyN(Bov + L.t1_off(sp), Bt[sp] + o_, {NA, o_, v_}, {tov, v_, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    copyN(Bvo + L.t1_off(sp), Bt[sp] + (int64_t)o_ * n, {NA, o_, v_}, {tov, v_, 1}, {n2, 1, n}, 1.0, 0.0, s);
+    copyN(Boo + (sp ? oos[0] : 0), Bt[sp], {NA, o_, o_}, {too2, o_, 1}, {n2, n, 1}, 1.0, 0.0, s);
   }
 
   // ---- particle-hole amplitude matrices ------------------------------------------
   // Tsc[(s,i,a),(s',k,c)] = t_ik^ac (spin-orbital), spin-conserving excitations
-  const int64_t vt = (int64_t)v * tov;
-  copyN(Tsc, t2aa, {o, v, o, v}, {vt, tov, v, 1}, {ov2, v, vv, 1}, 1.0, 0.0, s);
-  copyN(Tsc + ov, t2ab, {o, v, o, v}, {vt, tov, v, 1}, {ov2, v, vv, 1}, 1.0, 0.0, s);
-  copyN(Tsc + ov * tov, t2ab, {o, v, o, v}, {vt, tov, v, 1}, {vv, 1, ov2, v}, 1.0, 0.0, s);
-  copyN(Tsc + ov * tov + ov, t2bb, {o, v, o, v}, {vt, tov, v, 1}, {ov2, v, vv, 1}, 1.0, 0.0, s);
-  // Tsf1[(i,A),(K,c)] = t_{i K}^{A c} = -t2ab[i,K,c,A]   (Tsf2 = Tsf1^T)
-  copyN(Tsf1, t2ab, {o, v, o, v}, {v * ov, ov, v, 1}, {ov2, 1, vv, v}, -1.0, 0.0, s);
+  const int64_t vta = (int64_t)va * tov, vtb = (int64_t)vb * tov;
+  const int64_t aa2 = (int64_t)oa * va * va, bb2 = (int64_t)ob * vb * vb, ab2 = (int64_t)ob * va * vb;
+  copyN(Tsc, t2aa, {oa, va, oa, va}, {vta, tov, va, 1}, {aa2, va, (int64_t)va * va, 1}, 1.0, 0.0, s);
+  copyN(Tsc + ovs[0], t2ab, {oa, va, ob, vb}, {vta, tov, vb, 1}, {ab2, vb, (int64_t)va * vb, 1}, 1.0, 0.0, s);
+  copyN(Tsc + ovs[0] * tov, t2ab, {ob, vb, oa, va}, {vtb, tov, va, 1}, {(int64_t)va * vb, 1, ab2, vb}, 1.0, 0.0, s);
+  copyN(Tsc + ovs[0] * tov + ovs[0], t2bb, {ob, vb, ob, vb}, {vtb, tov, vb, 1}, {bb2, vb, (int64_t)vb * vb, 1}, 1.0,
+        0.0, s);
+  // Tsf1[(i,A),(K,c)] = t_{i K}^{A c} = -t2ab[i,K,c,A]  (sfr x sfc; Tsf2 = Tsf1^T)
+  copyN(Tsf1, t2ab, {oa, vb, ob, va}, {vb * sfc, sfc, va, 1}, {ab2, 1, (int64_t)va * vb, vb}, -1.0, 0.0, s);
 
   // ---- singles residual -------------------------------------------------------------
   if (mask & DCSD_TERM_SINGLES) {
     for (int sp = 0; sp < 2; ++sp) {
-      copyN(R1 + sp * ov, ft[sp] + (int64_t)o * n, {o, v}, {v, 1}, {1, n}, 1.0, 0.0, s);   // f~_ai
-      copyN(fvec + sp * ov, ft[sp] + o, {o, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);             // f~_kc
+      const int o_ = os[sp], v_ = vs[sp];
+      copyN(R1 + L.t1_off(sp), ft[sp] + (int64_t)o_ * n, {o_, v_}, {v_, 1}, {1, n}, 1.0, 0.0, s);   // f~_ai
+      copyN(fvec + L.t1_off(sp), ft[sp] + o_, {o_, v_}, {v_, 1}, {n, 1}, 1.0, 0.0, s);             // f~_kc
     }
     // sum_kc f~_kc t_ik^ac
     G(tov, 1, tov).A(Tsc, tov, false).B(fvec, 1, true).C(R1, 1).ab(1.0, 1.0).run(*this);
     // Z[P][(s,i,c)] = sum_{(s',k,d)} B~_ov[P][(s',k,d)] t_ik^cd
     G(NA, tov, tov).A(Bov, tov, false).B(Tsc, tov, true).C(Z, tov).run(*this);
     for (int sp = 0; sp < 2; ++sp) {
+      const int o_ = os[sp], v_ = vs[sp];
+      if (o_ == 0) continue;
+      const int64_t off = L.t1_off(sp), ovx = ovs[sp];
       // + sum_P sum_c B~[P][a][c] Z[P][i][c]
-      G(v, o, v).A(Bt[sp] + (int64_t)o * n + o, n, false).B(Z + sp * ov, v, false).C(out1, o)
-          .batch(NA, n2, tov, ov).run(*this);
-      rbreduce(R1 + sp * ov, out1, NA, ov, v, o, o, v, true, 1.0, s);
+      G(v_, o_, v_).A(Bt[sp] + (int64_t)o_ * n + o_, n, false).B(Z + off, v_, false).C(out1, o_)
+          .batch(NA, n2, tov, ovx).run(*this);
+      rbreduce(R1 + off, out1, NA, ovx, v_, o_, o_, v_, true, 1.0, s);
       // - sum_P sum_k B~[P][k][i] Z[P][k][a]
-      G(o, v, o).A(Bt[sp], n, true).B(Z + sp * ov, v, true).C(out2, v).batch(NA, n2, tov, ov).run(*this);
-      rbreduce(R1 + sp * ov, out2, NA, ov, o, v, v, v, false, -1.0, s);
+      G(o_, v_, o_).A(Bt[sp], n, true).B(Z + off, v_, true).C(out2, v_).batch(NA, n2, tov, ovx).run(*this);
+      rbreduce(R1 + off, out2, NA, ovx, o_, v_, v_, v_, false, -1.0, s);
     }
   }
 
@@ -581,118 +646,132 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   if (!(mask & DCSD_TERM_DRIVER)) rfill(Dvo, 0.0, tov * tov, s);
   if (mask & (DCSD_TERM_RING | DCSD_TERM_HH)) {
     // OOOO[(s,k,i),(s',l,j)] = (ki|lj)~
-    G(2 * o2, 2 * o2, NA).A(Boo, 2 * o2, true).B(Boo, 2 * o2, true).C(OOOO, 2 * o2).run(*this);
+    G(too2, too2, NA).A(Boo, too2, true).B(Boo, too2, true).C(OOOO, too2).run(*this);
   }
   if (mask & DCSD_TERM_RING) {
-    // KCBJ[(s,k,c),(s',j,b)] = (kc|bj)~ ; KJPQ[s'][(s,k,j)][(p,q)] = (kj|pq)~
+    // KCBJ[(s,k,c),(s',j,b)] = (kc|bj)~ ; KJPQ[s'][(s,k,j)][(p,q)] = (kj|pq)~ (p, q in spin s' order)
     G(tov, tov, NA).A(Bov, tov, true).B(Bvo, tov, true).C(KCBJ, tov).run(*this);
     for (int sp = 0; sp < 2; ++sp)
-      G(2 * o2, n2, NA).A(Boo, 2 * o2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).run(*this);
+      G(too2, n2, NA).A(Boo, too2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).run(*this);
     // W_sc = <kb||cj>~ = (kc|bj)~ - (kj|bc)~ (equal spins)
     for (int sp = 0; sp < 2; ++sp) {
-      const int64_t base = sp * ov * (tov + 1);
-      copyN(KCBJ + base, KJPQ[sp] + sp * o2 * n2 + (int64_t)o * n + o, {o, v, o, v}, {vt, tov, v, 1},
-            {o * n2, 1, n2, n}, -1.0, 1.0, s);
+      const int o_ = os[sp], v_ = vs[sp];
+      const int64_t base = L.t1_off(sp) * (tov + 1), vt = (int64_t)v_ * tov;
+      copyN(KCBJ + base, KJPQ[sp] + (sp ? oos[0] : 0) * n2 + (int64_t)o_ * n + o_, {o_, v_, o_, v_},
+            {vt, tov, v_, 1}, {o_ * n2, 1, n2, n}, -1.0, 1.0, s);
     }
     // + 1/2 <kl||cd> t_jl^bd  (DCSD: direct (kc|ld) only)
     G(tov, tov, tov).A(cc ? Icc : Isc, tov, false).B(Tsc, tov, true).C(KCBJ, tov).ab(0.5, 1.0).ring(*this, 0, false, true);
     // Ring_sc = T_sc W_sc
     G(tov, tov, tov).A(Tsc, tov, false).B(KCBJ, tov, true).C(Ring, tov).ring(*this, 1, true, true);
-    // spin-flip: Wsf1[(K,c),(J,b)] = -(KJ|bc)~, Wsf2[(k,C),(j,B)] = -(kj|BC)~
-    copyN(Wsf1, KJPQ[0] + o2 * n2 + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0,
+    // spin-flip: Wsf1[(K,c),(J,b)] = -(KJ|bc)~ (sfc x sfc), Wsf2[(k,C),(j,B)] = -(kj|BC)~ (sfr x sfr)
+    copyN(Wsf1, KJPQ[0] + oos[0] * n2 + (int64_t)oa * n + oa, {ob, va, ob, va}, {va * sfc, sfc, va, 1},
+          {ob * n2, 1, n2, n}, -1.0, 0.0, s);
+    copyN(Wsf2, KJPQ[1] + (int64_t)ob * n + ob, {oa, vb, oa, vb}, {vb * sfr, sfr, vb, 1}, {oa * n2, 1, n2, n}, -1.0,
           0.0, s);
-    copyN(Wsf2, KJPQ[1] + (int64_t)o * n + o, {o, v, o, v}, {v * ov, ov, v, 1}, {o * n2, 1, n2, n}, -1.0, 0.0, s);
     if (cc) {
       // + 1/2 I_sf1 Tsf1 and + 1/2 I_sf2 Tsf1^T
-      G(ov, ov, ov).A(Isf1, ov, false).B(Tsf1, ov, true).C(Wsf1, ov).ab(0.5, 1.0).ring(*this, 2, false, true);
-      G(ov, ov, ov).A(Isf2, ov, false).B(Tsf1, ov, false).C(Wsf2, ov).ab(0.5, 1.0).ring(*this, 3, false, true);
+      G(sfc, sfc, sfr).A(Isf1, sfr, false).B(Tsf1, sfc, true).C(Wsf1, sfc).ab(0.5, 1.0).ring(*this, 2, false, true);
+      G(sfr, sfr, sfc).A(Isf2, sfc, false).B(Tsf1, sfc, false).C(Wsf2, sfr).ab(0.5, 1.0).ring(*this, 3, false, true);
     }
-    G(ov, ov, ov).A(Tsf1, ov, false).B(Wsf1, ov, true).C(Rsf1, ov).ring(*this, 4, true, true);
-    G(ov, ov, ov).A(Tsf1, ov, true).B(Wsf2, ov, true).C(Rsf2, ov).ring(*this, 5, true, true);
+    G(sfr, sfc, sfc).A(Tsf1, sfc, false).B(Wsf1, sfc, true).C(Rsf1, sfc).ring(*this, 4, true, true);
+    G(sfc, sfr, sfr).A(Tsf1, sfc, true).B(Wsf2, sfr, true).C(Rsf2, sfr).ring(*this, 5, true, true);
   } else {
     rfill(Ring, 0.0, tov * tov, s);
-    rfill(Rsf1, 0.0, s2, s);
-    rfill(Rsf2, 0.0, s2, s);
+    rfill(Rsf1, 0.0, sfr * sfc, s);
+    rfill(Rsf2, 0.0, sfr * sfc, s);
   }
   if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING)) {
     // equal spins: R2 += P(ij)P(ab) [ 1/2 Dvo + Ring ]
     for (int sp = 0; sp < 2; ++sp) {
-      const int64_t base = sp * ov * (tov + 1);
+      const int o_ = os[sp], v_ = vs[sp];
+      const int64_t base = L.t1_off(sp) * (tov + 1), vt = (int64_t)v_ * tov;
+      const int64_t vv = (int64_t)v_ * v_;
       const double* src[2] = {Dvo + base, Ring + base};
       const double fac[2] = {0.5, 1.0};
       for (int q = 0; q < 2; ++q) {
-        std::initializer_list<int64_t> dst = {ov2, vv, v, 1};
-        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {vt, v, tov, 1}, fac[q], 1.0, s);
-        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {v, vt, tov, 1}, -fac[q], 1.0, s);
-        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {vt, v, 1, tov}, -fac[q], 1.0, s);
-        copyN(R2ss[sp], src[q], {o, o, v, v}, dst, {v, vt, 1, tov}, fac[q], 1.0, s);
+        std::initializer_list<int64_t> dst = {o_ * vv, vv, v_, 1};
+        copyN(R2ss[sp], src[q], {o_, o_, v_, v_}, dst, {vt, v_, tov, 1}, fac[q], 1.0, s);
+        copyN(R2ss[sp], src[q], {o_, o_, v_, v_}, dst, {v_, vt, tov, 1}, -fac[q], 1.0, s);
+        copyN(R2ss[sp], src[q], {o_, o_, v_, v_}, dst, {vt, v_, 1, tov}, -fac[q], 1.0, s);
+        copyN(R2ss[sp], src[q], {o_, o_, v_, v_}, dst, {v_, vt, 1, tov}, fac[q], 1.0, s);
       }
     }
     // alpha-beta: D + Ring[(ia),(JB)] + Ring[(JB),(ia)] - Rsf2[(J,a),(i,B)] - Rsf1[(i,B),(J,a)]
-    std::initializer_list<int64_t> dab = {ov2, vv, v, 1};
-    copyN(R2ab, Dvo + ov, {o, o, v, v}, dab, {vt, v, tov, 1}, 1.0, 1.0, s);
-    copyN(R2ab, Ring + ov, {o, o, v, v}, dab, {vt, v, tov, 1}, 1.0, 1.0, s);
-    copyN(R2ab, Ring + ov * tov, {o, o, v, v}, dab, {v, vt, 1, tov}, 1.0, 1.0, s);
-    copyN(R2ab, Rsf2, {o, o, v, v}, dab, {v, v * ov, ov, 1}, -1.0, 1.0, s);
-    copyN(R2ab, Rsf1, {o, o, v, v}, dab, {v * ov, v, 1, ov}, -1.0, 1.0, s);
+    std::initializer_list<int64_t> dab = {ab2, (int64_t)va * vb, vb, 1};
+    copyN(R2ab, Dvo + ovs[0], {oa, ob, va, vb}, dab, {vta, vb, tov, 1}, 1.0, 1.0, s);
+    copyN(R2ab, Ring + ovs[0], {oa, ob, va, vb}, dab, {vta, vb, tov, 1}, 1.0, 1.0, s);
+    copyN(R2ab, Ring + ovs[0] * tov, {oa, ob, va, vb}, dab, {va, vtb, 1, tov}, 1.0, 1.0, s);
+    copyN(R2ab, Rsf2, {oa, ob, va, vb}, dab, {vb, va * sfr, sfr, 1}, -1.0, 1.0, s);
+    copyN(R2ab, Rsf1, {oa, ob, va, vb}, dab, {vb * sfc, va, 1, sfc}, -1.0, 1.0, s);
   }
 
   // ---- Fock-like terms with the X (vv) and Y (oo) T2*T2 intermediates --------------
   if (mask & DCSD_TERM_FOCK) {
-    const double* t2p[2] = {t2aa, t2bb};
     for (int sp = 0; sp < 2; ++sp) {
+      const int o_ = os[sp], v_ = vs[sp];
+      const int64_t vv = (int64_t)v_ * v_, ov2 = o_ * vv, oo = oos[sp];
       // X[b][d] = sum (kc|ld)_ss t2ss[k,l,b,c] - sum (kd|L C) t2ab[k,L,b,C]   (alpha)
-      copyN(P1, t2p[sp], {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {v, ov2, vv, 1}, 1.0, 0.0, s);
-      G(v, v, o2 * v).A(P1, o2 * v, false).B(QX1[sp], v, true).C(Xv[sp], v).run(*this);
-      if (sp == 0)
-        copyN(P2, t2ab, {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {v, ov2, vv, 1}, 1.0, 0.0, s);
+      copyN(P1, t2ss[sp], {v_, o_, o_, v_}, {oo * v_, o_ * (int64_t)v_, v_, 1}, {v_, ov2, vv, 1}, 1.0, 0.0, s);
+      G(v_, v_, oo * v_).A(P1, oo * v_, false).B(QX1[sp], v_, true).C(Xv[sp], v_).run(*this);
+      const int64_t kx = oab * vs[1 - sp];  // (k, L, C) for alpha, (l, K, c) for beta
+      if (sp == 0)  // t2ab[k,L,b,C] -> [b][k][L][C]
+        copyN(P2, t2ab, {va, oa, ob, vb}, {kx, (int64_t)ob * vb, vb, 1}, {vb, ab2, (int64_t)va * vb, 1}, 1.0, 0.0, s);
       else  // t2ab[l,K,c,B] -> [B][l][K][c]
-        copyN(P2, t2ab, {v, o, o, v}, {o * o * (int64_t)v, o * (int64_t)v, v, 1}, {1, ov2, vv, v}, 1.0, 0.0, s);
-      G(v, v, o2 * v).A(P2, o2 * v, false).B(QX2[sp], v, true).C(Xv[sp], v).ab(-1.0, 1.0).run(*this);
+        copyN(P2, t2ab, {vb, oa, ob, va}, {kx, (int64_t)ob * va, va, 1}, {1, ab2, (int64_t)va * vb, vb}, 1.0, 0.0, s);
+      G(v_, v_, kx).A(P2, kx, false).B(QX2[sp], v_, true).C(Xv[sp], v_).ab(-1.0, 1.0).run(*this);
       // Y[l][j] = -sum (kc|ld) t2ss[j,k,c,d] + sum (KC|ld) t2ab[j,K,d,C]   (alpha)
-      G(o, o, ov2).A(QY1[sp], ov2, false).B(t2p[sp], ov2, false).C(Yo[sp], o).ab(-1.0, 0.0).run(*this);
+      G(o_, o_, ov2).A(QY1[sp], ov2, false).B(t2ss[sp], ov2, false).C(Yo[sp], o_).ab(-1.0, 0.0).run(*this);
       if (sp == 0) {
-        G(o, o, ov2).A(QY2[0], ov2, false).B(t2ab, ov2, false).C(Yo[0], o).ab(1.0, 1.0).run(*this);
+        G(oa, oa, ab2).A(QY2[0], ab2, false).B(t2ab, ab2, false).C(Yo[0], oa).ab(1.0, 1.0).run(*this);
       } else {
-        copyN(P2, t2ab, {o, o, v, v}, {ov2, vv, v, 1}, {vv, ov2, v, 1}, 1.0, 0.0, s);  // [J][k][c][D]
-        G(o, o, ov2).A(QY2[1], ov2, false).B(P2, ov2, false).C(Yo[1], o).ab(1.0, 1.0).run(*this);
+        const int64_t ka = (int64_t)oa * va * vb;
+        copyN(P2, t2ab, {ob, oa, va, vb}, {ka, (int64_t)va * vb, vb, 1}, {(int64_t)va * vb, ab2, vb, 1}, 1.0, 0.0,
+              s);  // [J][k][c][D]
+        G(ob, ob, ka).A(QY2[1], ka, false).B(P2, ka, false).C(Yo[1], ob).ab(1.0, 1.0).run(*this);
       }
       // F~vv = f~_vv + s X,  F~oo = f~_oo + s Y
-      copyN(Fvv[sp], ft[sp] + (int64_t)o * n + o, {v, v}, {v, 1}, {n, 1}, 1.0, 0.0, s);
+      copyN(Fvv[sp], ft[sp] + (int64_t)o_ * n + o_, {v_, v_}, {v_, 1}, {n, 1}, 1.0, 0.0, s);
       raxpby(Fvv[sp], Xv[sp], sdc, 1.0, vv, s);
-      copyN(Foo[sp], ft[sp], {o, o}, {o, 1}, {n, 1}, 1.0, 0.0, s);
-      raxpby(Foo[sp], Yo[sp], sdc, 1.0, o2, s);
+      copyN(Foo[sp], ft[sp], {o_, o_}, {o_, 1}, {n, 1}, 1.0, 0.0, s);
+      raxpby(Foo[sp], Yo[sp], sdc, 1.0, oo, s);
     }
     for (int sp = 0; sp < 2; ++sp) {
+      const int o_ = os[sp], v_ = vs[sp];
+      const int64_t vv = (int64_t)v_ * v_, ov2 = o_ * vv;
+      if (o_ == 0) continue;
       // P(ab) sum_d t_ij^ad F_bd
-      G(o2 * v, v, v).A(t2ss[sp], v, false).B(Fvv[sp], v, false).C(P1, v).run(*this);
-      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, v, 1}, 1.0, 1.0, s);
-      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, 1, v}, -1.0, 1.0, s);
+      G(oos[sp] * v_, v_, v_).A(t2ss[sp], v_, false).B(Fvv[sp], v_, false).C(P1, v_).run(*this);
+      copyN(R2ss[sp], P1, {o_, o_, v_, v_}, {ov2, vv, v_, 1}, {ov2, vv, v_, 1}, 1.0, 1.0, s);
+      copyN(R2ss[sp], P1, {o_, o_, v_, v_}, {ov2, vv, v_, 1}, {ov2, vv, 1, v_}, -1.0, 1.0, s);
       // -P(ij) sum_l t_il^ab F_lj
-      G(o, vv, o).A(Foo[sp], o, true).B(t2ss[sp], vv, true).C(P1, vv).batch(o, 0, ov2, ov2).run(*this);
-      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {ov2, vv, v, 1}, -1.0, 1.0, s);
-      copyN(R2ss[sp], P1, {o, o, v, v}, {ov2, vv, v, 1}, {vv, ov2, v, 1}, 1.0, 1.0, s);
+      G(o_, vv, o_).A(Foo[sp], o_, true).B(t2ss[sp], vv, true).C(P1, vv).batch(o_, 0, ov2, ov2).run(*this);
+      copyN(R2ss[sp], P1, {o_, o_, v_, v_}, {ov2, vv, v_, 1}, {ov2, vv, v_, 1}, -1.0, 1.0, s);
+      copyN(R2ss[sp], P1, {o_, o_, v_, v_}, {ov2, vv, v_, 1}, {vv, ov2, v_, 1}, 1.0, 1.0, s);
     }
     // alpha-beta
-    G(o2 * v, v, v).A(t2ab, v, false).B(Fvv[1], v, false).C(R2ab, v).ab(1.0, 1.0).run(*this);
-    G(v, v, v).A(Fvv[0], v, false).B(t2ab, v, true).C(R2ab, v).ab(1.0, 1.0).batch(o2, 0, vv, vv).run(*this);
-    G(o, vv, o).A(Foo[1], o, true).B(t2ab, vv, true).C(R2ab, vv).ab(-1.0, 1.0).batch(o, 0, ov2, ov2).run(*this);
-    G(o, ov2, o).A(Foo[0], o, true).B(t2ab, ov2, true).C(R2ab, ov2).ab(-1.0, 1.0).run(*this);
+    const int64_t vab = (int64_t)va * vb;
+    G(oab * va, vb, vb).A(t2ab, vb, false).B(Fvv[1], vb, false).C(R2ab, vb).ab(1.0, 1.0).run(*this);
+    G(va, vb, va).A(Fvv[0], va, false).B(t2ab, vb, true).C(R2ab, vb).ab(1.0, 1.0).batch(oab, 0, vab, vab).run(*this);
+    G(ob, vab, ob).A(Foo[1], ob, true).B(t2ab, vab, true).C(R2ab, vab).ab(-1.0, 1.0).batch(oa, 0, ab2, ab2).run(*this);
+    G(oa, ab2, oa).A(Foo[0], oa, true).B(t2ab, ab2, true).C(R2ab, ab2).ab(-1.0, 1.0).run(*this);
   }
 
   // ---- hole-hole ladder -----------------------------------------------------------
   if (mask & DCSD_TERM_HH) {
-    const int64_t to2 = 2 * o2;
     for (int blk = 0; blk < 3; ++blk) {
       const int s1 = blk == 1 ? 1 : 0, s3 = blk == 0 ? 0 : 1;
-      // Whh[(k,l),(i,j)] = (ki|lj)~
-      copyN(Whh, OOOO + (s1 * o2) * to2 + s3 * o2, {o, o, o, o}, {o * o2, o2, o, 1}, {o * to2, o, to2, 1}, 1.0, 0.0,
-            s);
+      const int o1 = os[s1], o3 = os[s3];
+      const int64_t o13 = (int64_t)o1 * o3, v13 = (int64_t)vs[s1] * vs[s3];
+      if (o13 == 0) continue;
+      // Whh[(k,l),(i,j)] = (ki|lj)~  (k, i of spin s1; l, j of spin s3)
+      copyN(Whh, OOOO + (s1 ? oos[0] : 0) * too2 + (s3 ? oos[0] : 0), {o1, o3, o1, o3},
+            {o3 * o13, o13, o3, 1}, {o1 * too2, o3, too2, 1}, 1.0, 0.0, s);
       const double* t2b = blk == 0 ? t2aa : (blk == 1 ? t2bb : t2ab);
       double* Rb2 = blk == 0 ? R2ss[0] : (blk == 1 ? R2ss[1] : R2ab);
       if (cc)  // + 1/2 <kl||cd> t_ij^cd  ->  sum_cd (kc|ld) t_ij^cd (x 1/2 for equal spins)
-        G(o2, o2, vv).A(Ikl[blk], vv, false).B(t2b, vv, false).C(Whh, o2).ab(blk == 2 ? 1.0 : 0.5, 1.0).run(*this);
-      G(o2, vv, o2).A(Whh, o2, true).B(t2b, vv, true).C(Rb2, vv).ab(1.0, 1.0).run(*this);
+        G(o13, o13, v13).A(Ikl[blk], v13, false).B(t2b, v13, false).C(Whh, o13).ab(blk == 2 ? 1.0 : 0.5, 1.0).run(*this);
+      G(o13, v13, o13).A(Whh, o13, true).B(t2b, v13, true).C(Rb2, v13).ab(1.0, 1.0).run(*this);
     }
   }
 
@@ -701,7 +780,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
     const int64_t vu2 = (int64_t)vu * vu;
     const bool low = prec_now != DCSD_PREC_FP64;
     const bool delta = low && mode == DELTA && ladder_ref;  // contract lp(tau - tau_r), add L(tau_r)
-    ladder_stack(Tstack, t2aa, t2bb, t2ab, pair_i, pair_j, o, v, vu, npair, rows_all, s);
+    ladder_stack(Tstack, t2aa, t2bb, t2ab, pair_i, pair_j, L, vu, rows_all, s);
     // Under a tape the whole batch loop is one operation: its adjoint
     // recomputes each integral batch instead of storing it.
     Tape* const tape_here = t_tape;
@@ -755,7 +834,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
           G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
         }
         if (rec) tend(ev0, 2.0 * (double)M * (double)N * (double)vu2, 1);
-        ladder_scatter(Rp, Rb, M, rows_main, o2, n, p0, np, q0, nq, diag, s);
+        ladder_scatter(Rp, Rb, M, rows_main, oab, n, p0, np, q0, nq, diag, s);
       }
     }
     if (mode == RECORD) {
@@ -776,17 +855,16 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
       op.val[1] = tape_value(Tw, 2 * ov);
       tape_op(op);
     }
-    ladder_mtransform(R2ss[0], R2ss[1], R2ab, Smt, Rp, t1[0], t1[1], pair_i, pair_j, rows_main, o2, npair, n, nc, o,
-                      v, s);
+    ladder_mtransform(R2ss[0], R2ss[1], R2ab, Smt, Rp, t1[0], t1[1], pair_i, pair_j, rows_main, L, s);
   }
 
-  // ---- coupling of the two determinants (none in the fixed-reference methods) -------
-  const bool fr = method_fr(cfg.method);
-  if (fr)
-    rfill(scal, 0.0, 1, s);  // W
-  else
+  // ---- coupling of the two determinants (2D methods only) ---------------------------
+  const bool two_det = method_ab(cfg.method) && !method_fr(cfg.method);
+  if (two_det)
     rcopy(scal, R + ab_pos, 1, s);  // W
-  if (!fr && (mask & DCSD_TERM_COUPLING)) {
+  else
+    rfill(scal, 0.0, 1, s);  // W = 0: fixed-reference and high-spin methods
+  if (two_det && (mask & DCSD_TERM_COUPLING)) {
     if (t_tape) {
       TapeOp op;
       op.kind = OP_COUPLING;
@@ -801,7 +879,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   }
   // the Phi_A -> Phi_B double is not solved for (its residual is W in the two-determinant
   // methods; the fixed-reference methods hold the amplitude fixed)
-  rfill(R + ab_pos, 0.0, 1, s);
+  if (method_ab(cfg.method)) rfill(R + ab_pos, 0.0, 1, s);
   if (rec_res) tend(ev_res, 0.0, 2);
   if (W_host) {
     DCSD_HIP(hipMemcpyAsync(W_host, scal, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -831,7 +909,7 @@ void Ctx::tend(hipEvent_t a, double flops, int cls) {
 // vector (the fixed-reference methods have W = 0 and need none).
 void Ctx::energies(const double* T, dcsd_energies* out) {
   double W = 0.0;
-  if (!method_fr(cfg.method)) residual(T, Rw, &W, DCSD_PREC_FP64, PLAIN);
+  if (method_ab(cfg.method) && !method_fr(cfg.method)) residual(T, Rw, &W, DCSD_PREC_FP64, PLAIN);
   const double e = energy_A(T);
   out->dE_A = e;
   out->W = W;
@@ -841,9 +919,11 @@ void Ctx::energies(const double* T, dcsd_energies* out) {
 
 double Ctx::energy_A(const double* T) {
   rcopy(Tw, T, total, s);
-  const int64_t ab_pos = 2 * ov + 2 * s2 + (((int64_t)nc * o + nc) * v + 0) * v + 0;
-  rfill(Tw + ab_pos, ab_amplitude(cfg.method), 1, s);
-  energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
+  if (method_ab(cfg.method)) {
+    const int64_t ab_pos = L.t2_off(2) + (((int64_t)nc * os[1] + nc) * vs[0] + 0) * vs[1] + 0;
+    rfill(Tw + ab_pos, ab_amplitude(cfg.method), 1, s);
+  }
+  energy(Tw, Isc, f[0], f[1], L, scal + 2, part, s);
   double e = 0.0;
   DCSD_HIP(hipMemcpyAsync(&e, scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
   DCSD_HIP(hipStreamSynchronize(s));

@@ -48,7 +48,7 @@ void Ctx::jacobi_diis(int it, double* X, const double* R, std::vector<double>& g
                       int& count) {
   const int m = cfg.diis_dim;
   const bool en = cfg.precond == DCSD_PRECOND_EN;
-  jacobi(Tn, Ev, X, R, f[0], f[1], en ? Jpq : nullptr, en ? Kpq : nullptr, nc, o, v, n, cfg.level_shift, total, s);
+  jacobi(Tn, Ev, X, R, f[0], f[1], en ? Jpq : nullptr, en ? Kpq : nullptr, L, cfg.level_shift, s);
   if (m > 0) {
     const int slot = count % m;
     ++count;
@@ -125,7 +125,7 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
     DCSD_HIP(hipMemcpyAsync(flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
     DCSD_HIP(hipStreamSynchronize(s));
     maxabs(Rw, total, scal + 1, flag, part, s);
-    energy(Tw, Isc, f[0], f[1], nc, o, v, n, scal + 2, part, s);
+    energy(Tw, Isc, f[0], f[1], L, scal + 2, part, s);
     dot(Rw, Rw, total, scal + 3, part, s);
     DCSD_HIP(hipMemcpyAsync(host, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     DCSD_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));

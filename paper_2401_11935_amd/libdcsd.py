@@ -17,7 +17,7 @@ DEFAULT_PATH = os.path.join(HERE, "lib", "libdcsd.so")
 DCSD_OK, DCSD_ERR_ARG, DCSD_ERR_OOM, DCSD_ERR_HIP, DCSD_ERR_NOCONV, DCSD_ERR_NONFINITE, DCSD_ERR_STATE = range(7)
 STATUS_NAMES = ["OK", "ERR_ARG", "ERR_OOM", "ERR_HIP", "ERR_NOCONV", "ERR_NONFINITE", "ERR_STATE"]
 METHODS = {"dcsd": 0, "ccsd": 1, "fr-dcsd-singlet": 2, "fr-dcsd-triplet": 3, "fr-ccsd-singlet": 4,
-           "fr-ccsd-triplet": 5}
+           "fr-ccsd-triplet": 5, "hs-dcsd": 6, "hs-ccsd": 7}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 TERM = {"driver": 1, "fock": 2, "hh": 4, "pp": 8, "ring": 16, "singles": 32, "coupling": 64}
 TERM_ALL = 0x7F
@@ -89,6 +89,8 @@ def load(path: str | None = None):
     vp, dp = ctypes.c_void_p, ctypes.c_void_p
     lib.dcsd_amplitude_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.dcsd_amplitude_count.restype = ctypes.c_int64
+    lib.dcsd_method_amplitude_count.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.dcsd_method_amplitude_count.restype = ctypes.c_int64
     lib.dcsd_default_config.argtypes = [ctypes.POINTER(Config)]
     lib.dcsd_default_config.restype = None
     lib.dcsd_init.argtypes = [ctypes.POINTER(Config), dp, dp, vp, ctypes.POINTER(vp)]
@@ -129,8 +131,13 @@ def load(path: str | None = None):
     return lib
 
 
-def amplitude_count(nc: int, nv: int, lib=None) -> int:
-    return int((lib or load()).dcsd_amplitude_count(nc, nv))
+def amplitude_count(nc: int, nv: int, lib=None, method=None) -> int:
+    """Length of the packed amplitudes (of `method` if given: the high-spin methods differ)."""
+    if method is None:
+        return int((lib or load()).dcsd_amplitude_count(nc, nv))
+    if isinstance(method, str):
+        method = METHODS[method]
+    return int((lib or load()).dcsd_method_amplitude_count(nc, nv, method))
 
 
 def default_config(lib=None, **kw) -> Config:
@@ -171,7 +178,7 @@ class Context:
         if st != DCSD_OK:
             raise DcsdError(st, self.lib.dcsd_last_error(None).decode())
         self.h = h
-        self.size = amplitude_count(cfg.nc, cfg.nv, self.lib)
+        self.size = amplitude_count(cfg.nc, cfg.nv, self.lib, cfg.method)
 
     def _check(self, st: int):
         if st not in (DCSD_OK,):
