@@ -110,6 +110,8 @@ def parse():
     ap.add_argument("--precisions", default="fp32,bf16",
                     help="low precisions run beside FP64 on the weak-integral inputs ('' = skip)")
     ap.add_argument("--tol", type=float, default=1e-10, help="convergence of the weak-integral solves")
+    ap.add_argument("--weak-max-iter", type=int, default=300,
+                    help="iteration cap of the weak-integral solves (a few for profiling runs)")
     ap.add_argument("--evals", type=int, default=3, help="timed single residual evaluations per precision")
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the residual VJP")
     ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
@@ -274,7 +276,7 @@ def weak_integral_run(L, torch, args, stream, alg):
     Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
     del B
     base = dict(nc=cfgw.nc, nv=cfgw.nv, naux=cfgw.naux, method=args.method, ladder_block=args.ladder_block,
-                tol_residual=args.tol, max_iter=300)
+                tol_residual=args.tol, max_iter=args.weak_max_iter)
     out = {"config": {"workload": f"2D-{args.method.upper()} nc={cfgw.nc} open-shell=2 nv={cfgw.nv} "
                                   f"naux={cfgw.naux} seed={cfgw.seed}, DF factors N(0, sigma^2) with "
                                   f"naux sigma^2 = {synth.WEAK_EXCHANGE} Eh", "sigma": cfgw.sigma,

@@ -105,7 +105,8 @@ struct Stage {
 // without divisions in 32 bits (the host bounds the block below 4 GiB), so that
 // every store is the uniform base plus one 32-bit offset.
 template <class T, int TM, int TN>
-__device__ inline void store_pairs(const LArgs& g, const f4 (&acc)[TM][TN], int64_t mb, int64_t nbase) {
+__device__ inline void store_pairs(const LArgs& g, const f4 (&acc)[TM][TN], int64_t mb, int64_t nbase,
+                                   bool interior = false) {
   constexpr uint32_t es = sizeof(T);
   const int vu = (int)g.vu;
   uint32_t coff[TN];
@@ -131,8 +132,11 @@ __device__ inline void store_pairs(const LArgs& g, const f4 (&acc)[TM][TN], int6
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       // row mb + 16 i + r: (p, c) advanced by one row from the previous r, by 13 across i
-      if (mb + 16 * i + r < g.M) {
-        const uint32_t ro = (uint32_t)p * pstep + (uint32_t)c * cstep;
+      const uint32_t ro = (uint32_t)p * pstep + (uint32_t)c * cstep;
+      if (interior) {
+#pragma unroll
+        for (int j = 0; j < TN; ++j) *(T*)(V + (ro + coff[j])) = (T)acc[i][j][r];
+      } else if (mb + 16 * i + r < g.M) {
 #pragma unroll
         for (int j = 0; j < TN; ++j)
           if (cok[j]) *(T*)(V + (ro + coff[j])) = (T)acc[i][j][r];
@@ -322,29 +326,42 @@ __device__ inline uint32_t lds_byte_address(const void* p) {
 }
 constexpr int waitcnt_vm(int vm) { return (vm & 0xF) | ((vm >> 4) << 14) | (7 << 4) | (0xF << 8); }
 
-template <class T, int S, int CPR, int EPI>
-__global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
+// BT x BT output tile per workgroup: BT = 128 on four waves (2 x 2, 64 x 64 each) or
+// BT = 256 on eight waves (2 x 4, 128 x 64 each), which halves the operand bytes per
+// MFMA that the L2 has to supply.
+template <int BT>
+struct DlTile {
+  static constexpr int NW = BT == 256 ? 8 : 4;   // waves
+  static constexpr int WGN = NW / 2;             // waves along n
+  static constexpr int WM = BT / 2, WN = BT / WGN;
+  static constexpr int TM = WM / 16, TN = WN / 16;
+};
+
+template <class T, int S, int CPR, int EPI, int BT = 128>
+__global__ __launch_bounds__(64 * DlTile<BT>::NW) void gemm_lp_dl_kernel(LArgs g) {
   constexpr int VL = Traits<T>::VL;          // elements per 16-byte chunk
   constexpr int RB = 16 * CPR;               // bytes of K per row and stage
   constexpr int BK = CPR * VL;               // elements of K per stage
   constexpr int H = CPR / 4;                 // fragment sub-steps per stage (4 chunks each)
   constexpr int RPI = 64 / CPR;              // rows per wave instruction
-  constexpr int IPW = 128 / RPI / 4;         // instructions per operand per wave and stage
-  constexpr int WM = 64, WN = 64, TM = 4, TN = 4;
-  constexpr int STAGE = 128 * RB;            // bytes per operand per stage
+  constexpr int NW = DlTile<BT>::NW, WGN = DlTile<BT>::WGN;
+  constexpr int IPW = BT / RPI / NW;         // instructions per operand per wave and stage
+  constexpr int WM = DlTile<BT>::WM, WN = DlTile<BT>::WN, TM = DlTile<BT>::TM, TN = DlTile<BT>::TN;
+  constexpr int STAGE = BT * RB;             // bytes per operand per stage
   static_assert(CPR == 4 || CPR == 8, "4 or 8 chunks per row");
+  static_assert(TN == 4 && (TM == 4 || TM == 8), "wave tiles of 64 x 64 or 128 x 64");
   __shared__ __attribute__((aligned(16))) unsigned char sA[S][STAGE];
   __shared__ __attribute__((aligned(16))) unsigned char sB[S][STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WGN, wn = wave % WGN;
   int64_t tm, tn;
   if (EPI == EPI_PAIRS && g.skip_lower) {
-    if (!diag_tile(blockIdx.x, (g.M + 127) / 128, g.tiles_n, g.N, g.vu, 128, 128, tm, tn))
+    if (!diag_tile(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, g.N, g.vu, BT, BT, tm, tn))
       return;  // whole workgroup, before any barrier
   } else {
-    tile_of(blockIdx.x, (g.M + 127) / 128, g.tiles_n, tm, tn);
+    tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
   }
-  const int64_t m0 = tm * 128, n0 = tn * 128;
+  const int64_t m0 = tm * BT, n0 = tn * BT;
   int64_t kbeg = 0, kend = g.K;
   if (EPI == EPI_SPLIT) {
     kbeg = (int64_t)blockIdx.z * g.kchunk;
@@ -396,48 +413,99 @@ __global__ __launch_bounds__(NT) void gemm_lp_dl_kernel(LArgs g) {
     __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * IPW * (S - 2)));
     __builtin_amdgcn_s_barrier();
     const uint32_t sa = lds_byte_address(sA[slot]), sb = lds_byte_address(sB[slot]);
-    u4v af[H][TM], bf[H][TN];
+    if constexpr (TM == 4) {
+      u4v af[H][TM], bf[H][TN];
 #pragma unroll
-    for (int h = 0; h < H; ++h) {
-      const uint32_t pa = sa + ao[h], pb = sb + bo[h];
-      asm volatile(
-          "ds_read_b128 %0, %8\n"
-          "ds_read_b128 %1, %8 offset:%10\n"
-          "ds_read_b128 %2, %8 offset:%11\n"
-          "ds_read_b128 %3, %8 offset:%12\n"
-          "ds_read_b128 %4, %9\n"
-          "ds_read_b128 %5, %9 offset:%10\n"
-          "ds_read_b128 %6, %9 offset:%11\n"
-          "ds_read_b128 %7, %9 offset:%12\n"
-          "s_waitcnt lgkmcnt(0)"
-          : "=&v"(af[h][0]), "=&v"(af[h][1]), "=&v"(af[h][2]), "=&v"(af[h][3]), "=&v"(bf[h][0]), "=&v"(bf[h][1]),
-            "=&v"(bf[h][2]), "=&v"(bf[h][3])
-          : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB)
-          : "memory");
-    }
-    issue(fill, kbeg + (kt + S - 1) * BK);  // past the K range: zero rows
-    slot = slot + 1 == S ? 0 : slot + 1;
-    fill = fill + 1 == S ? 0 : fill + 1;
+      for (int h = 0; h < H; ++h) {
+        const uint32_t pa = sa + ao[h], pb = sb + bo[h];
+        asm volatile(
+            "ds_read_b128 %0, %8\n"
+            "ds_read_b128 %1, %8 offset:%10\n"
+            "ds_read_b128 %2, %8 offset:%11\n"
+            "ds_read_b128 %3, %8 offset:%12\n"
+            "ds_read_b128 %4, %9\n"
+            "ds_read_b128 %5, %9 offset:%10\n"
+            "ds_read_b128 %6, %9 offset:%11\n"
+            "ds_read_b128 %7, %9 offset:%12\n"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(af[h][0]), "=&v"(af[h][1]), "=&v"(af[h][2]), "=&v"(af[h][3]), "=&v"(bf[h][0]), "=&v"(bf[h][1]),
+              "=&v"(bf[h][2]), "=&v"(bf[h][3])
+            : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB)
+            : "memory");
+      }
+      issue(fill, kbeg + (kt + S - 1) * BK);  // past the K range: zero rows
+      slot = slot + 1 == S ? 0 : slot + 1;
+      fill = fill + 1 == S ? 0 : fill + 1;
 #pragma unroll
-    for (int h = 0; h < H; ++h)
+      for (int h = 0; h < H; ++h)
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          if constexpr (VL == 8) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af[h][i]),
-                                                                __builtin_bit_cast(bf8, bf[h][j]), acc[i][j], 0, 0, 0);
-          } else {
-            const f4 a = __builtin_bit_cast(f4, af[h][i]), b = __builtin_bit_cast(f4, bf[h][j]);
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (VL == 8) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf8, af[h][i]), __builtin_bit_cast(bf8, bf[h][j]), acc[i][j], 0, 0, 0);
+            } else {
+              const f4 a = __builtin_bit_cast(f4, af[h][i]), b = __builtin_bit_cast(f4, bf[h][j]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc[i][j], 0, 0, 0);
+              for (int e = 0; e < 4; ++e)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc[i][j], 0, 0, 0);
+            }
           }
+    } else {
+      // 128 x 64 wave tiles: each sub-step's fragments are read just before its MFMAs
+      // (12 reads of 16 bytes), which keeps the fragment registers at 48
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        u4v af[TM], bf[TN];
+        const uint32_t pa = sa + ao[h], pb = sb + bo[h];
+        asm volatile(
+            "ds_read_b128 %0, %12\n"
+            "ds_read_b128 %1, %12 offset:%14\n"
+            "ds_read_b128 %2, %12 offset:%15\n"
+            "ds_read_b128 %3, %12 offset:%16\n"
+            "ds_read_b128 %4, %12 offset:%17\n"
+            "ds_read_b128 %5, %12 offset:%18\n"
+            "ds_read_b128 %6, %12 offset:%19\n"
+            "ds_read_b128 %7, %12 offset:%20\n"
+            "ds_read_b128 %8, %13\n"
+            "ds_read_b128 %9, %13 offset:%14\n"
+            "ds_read_b128 %10, %13 offset:%15\n"
+            "ds_read_b128 %11, %13 offset:%16\n"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(af[0]), "=&v"(af[1]), "=&v"(af[2]), "=&v"(af[3]), "=&v"(af[4]), "=&v"(af[5]), "=&v"(af[6]),
+              "=&v"(af[7]), "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3])
+            : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB), "n"(64 * RB), "n"(80 * RB),
+              "n"(96 * RB), "n"(112 * RB)
+            : "memory");
+        if (h == 0) {  // every wave has read the stage's first fragments: refill the oldest stage
+          issue(fill, kbeg + (kt + S - 1) * BK);  // past the K range: zero rows
+          slot = slot + 1 == S ? 0 : slot + 1;
+          fill = fill + 1 == S ? 0 : fill + 1;
         }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            if constexpr (VL == 8) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af[i]),
+                                                                  __builtin_bit_cast(bf8, bf[j]), acc[i][j], 0, 0, 0);
+            } else {
+              const f4 a = __builtin_bit_cast(f4, af[i]), b = __builtin_bit_cast(f4, bf[j]);
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc[i][j], 0, 0, 0);
+            }
+          }
+      }
+    }
   }
   __builtin_amdgcn_s_waitcnt(0);  // the last (zero) stages have landed before the wave retires
   const int64_t mb = m0 + wm * WM + 4 * lrow, nbase = n0 + wn * WN + lcol;
   if constexpr (EPI == EPI_PAIRS) {
-    store_pairs<T, TM, TN>(g, acc, mb, nbase);
+    // interior wave tiles (every row and column in range) store without checks
+    const bool interior = m0 + wm * WM + WM <= g.M && n0 + wn * WN + WN <= g.N;
+    store_pairs<T, TM, TN>(g, acc, mb, nbase, interior);
   } else if constexpr (EPI == EPI_F64) {
     double* C = (double*)g.C;
 #pragma unroll
@@ -591,9 +659,9 @@ void launch_pairs(const void* BlT, int64_t ldk, int64_t naux, int64_t vu, int64_
   // skipped and those pairs copied from their mirrors below
   a.skip_lower = p0 == q0 && np == nq && np * (np - 1) / 2 <= 65535 && diag_skips(np, vu, BT, BT);
   const int64_t tiles = a.skip_lower ? diag_grid(tiles_m, a.tiles_n) : tiles_m * a.tiles_n;
-  if (BT == 128 && naux % Traits<T>::VL == 0)
-    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_PAIRS>), dim3((unsigned)tiles), dim3(NT),
-                       0, s, a);
+  if (naux % Traits<T>::VL == 0)
+    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_PAIRS, BT>), dim3((unsigned)tiles),
+                       dim3(64 * DlTile<BT>::NW), 0, s, a);
   else
     hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_PAIRS, false, BT>), dim3((unsigned)tiles), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();
@@ -641,7 +709,11 @@ void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t
     throw ArgError("low-precision ladder: factor too large for 32-bit offsets");
   if (np * nq * kp * (int64_t)lp_size(precision) >= ((int64_t)1 << 32))
     throw ArgError("low-precision ladder: integral block too large for 32-bit offsets");
-  if (precision == DCSD_PREC_BF16)
+  // BF16 batches of at least 512 rows take 256 x 256 tiles (eight waves): at BF16 rates the
+  // 128 x 128 tiles asked more operand bytes of the L2 per MFMA than it delivered
+  if (precision == DCSD_PREC_BF16 && np * vu >= 512 && nq * vu >= 512)
+    launch_pairs<__bf16, 256>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
+  else if (precision == DCSD_PREC_BF16)
     launch_pairs<__bf16, 128>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
   else
     launch_pairs<float, 128>(BlT, ldk, naux, vu, p0, np, q0, nq, kp, V2, s);
