@@ -116,6 +116,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the residual VJP")
     ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
     ap.add_argument("--no-weak", action="store_true", help="skip the weak-integral solves")
+    ap.add_argument("--largest", action="store_true",
+                    help="also time single residual evaluations at nc=20 nv=600 naux=1800 (FP64, FP32, BF16) and "
+                         "try the adjoint's reservation there")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     return ap.parse_args()
@@ -387,6 +390,55 @@ def adjoint_timing(L, torch, args, Bd, Fd, stream):
     return out
 
 
+def largest_config_run(L, torch, args, stream):
+    """The largest single-GPU configuration (nc=20, nv=600, naux=1800, seed 3, the
+    prescribed DF factors): single residual evaluations in FP64, FP32 and BF16 at
+    random amplitudes (the work does not depend on the values), and whether the
+    adjoint's reservation (cfg.adjoint) fits in the device memory there."""
+    import dcsd_synth as synth
+    cfg = synth.LARGEST
+    print(f"bench: largest configuration nc={cfg.nc} nv={cfg.nv} naux={cfg.naux}", file=sys.stderr, flush=True)
+    B, F = synth.make_config_inputs(cfg)
+    dev = torch.device("cuda:0")
+    Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
+    del B
+    alg = algorithmic_flops(cfg.nc, cfg.nv, cfg.naux)
+    T = torch.from_numpy(synth.random_amplitudes(cfg.nc, cfg.nv, 5, 0.01)).to(dev)
+    base = dict(nc=cfg.nc, nv=cfg.nv, naux=cfg.naux, method=args.method)
+    out = {"config": f"2D-{args.method.upper()} nc={cfg.nc} open-shell=2 nv={cfg.nv} naux={cfg.naux} seed={cfg.seed}",
+           "flops_per_eval": alg["total"], "evals_timed": 2}
+    R64 = None
+    for prec in ("fp64", "fp32", "bf16"):
+        print(f"bench: largest configuration, residual evals in {prec}", file=sys.stderr, flush=True)
+        R, W, dt, tim = residual_rate(L, torch, L.default_config(precision=prec, **base), Bd, Fd, stream, T, 2)
+        asm = tim["assembly"]
+        ach = asm["flops"] / (asm["ms"] * 1e-3) / 1e12 if asm["ms"] > 0 else 0.0
+        d = {"ms_per_eval": 1e3 * dt, "residual_evals_per_s": 1.0 / dt, "tflops_algorithmic": alg["total"] / dt / 1e12,
+             "assembly_tflops_executed": ach, "assembly_frac_of_peak": ach / PEAK_TFLOPS[prec],
+             "assembly_avg_launch_ms": asm["ms"] / max(asm["launches"], 1)}
+        if R64 is None:
+            R64, W64 = R, W
+        else:
+            d["max_abs_dR_vs_fp64"] = float((R - R64).abs().max())
+            d["abs_dW_vs_fp64"] = abs(W - W64)
+            d["speedup_vs_fp64"] = out["fp64"]["ms_per_eval"] / d["ms_per_eval"]
+        del R
+        out[prec] = d
+    ctx = L.Context(L.default_config(**base), Bd.data_ptr(), Fd.data_ptr(), stream)
+    out["device_memory_gib"] = ctx.device_memory()[0] / 2 ** 30
+    ctx.close()
+    del R64
+    torch.cuda.empty_cache()
+    try:
+        ctx = L.Context(L.default_config(adjoint=1, **base), Bd.data_ptr(), Fd.data_ptr(), stream)
+        out["adjoint"] = {"reserved": True, "device_memory_gib": ctx.device_memory()[0] / 2 ** 30}
+        ctx.close()
+    except L.DcsdError as e:
+        out["adjoint"] = {"reserved": False, "status": L.STATUS_NAMES[e.status], "message": str(e),
+                          "device_total_gib": torch.cuda.mem_get_info()[1] / 2 ** 30}
+    return out
+
+
 def main():
     args = parse()
     if args.traffic_from_pmc:
@@ -495,9 +547,12 @@ def main():
     if not args.no_adjoint:
         print("bench: residual VJP", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_timing(L, torch, args, Bd, Fd, stream)
+    if args.largest:
+        del Bd, Fd
+        torch.cuda.empty_cache()
+        out["largest"] = largest_config_run(L, torch, args, stream)
     if args.cpu_subsets:
         print("bench: timing the oracle", file=sys.stderr, flush=True)
-        del Bd, Fd
         subsets = [int(x) for x in args.cpu_subsets.split(",")]
         out["cpu_baseline"] = cpu_baseline(B, F, nc, nv, subsets)
     print(json.dumps(out), flush=True)
