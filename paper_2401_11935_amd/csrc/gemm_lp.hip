@@ -44,6 +44,7 @@ struct LArgs {
   int64_t kchunk, tiles_n, split_stride;
   int64_t vu, nq, kp;  // pair-blocked output
   int64_t skip_lower;  // pair-blocked diagonal batch: skip tiles whose pairs all have p > q
+  int64_t xcd_split;   // split product on a one-dimensional grid, chunks grouped per XCD
 };
 
 template <class T>
@@ -355,16 +356,26 @@ __global__ __launch_bounds__(64 * DlTile<BT>::NW) void gemm_lp_dl_kernel(LArgs g
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
   int64_t tm, tn;
+  int64_t zsplit = blockIdx.z;  // K chunk of a split product
   if (EPI == EPI_PAIRS && g.skip_lower) {
     if (!diag_tile(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, g.N, g.vu, BT, BT, tm, tn))
       return;  // whole workgroup, before any barrier
+  } else if (EPI == EPI_SPLIT && g.xcd_split) {
+    // one-dimensional grid of tiles x chunks (chunks a multiple of 8): the workgroups are
+    // dealt round-robin to the 8 XCDs, so workgroup L runs on XCD L % 8; give every tile of
+    // one K chunk to the same XCD, dispatched together, so that they share the chunk's
+    // operand rows in that XCD's L2
+    const int64_t tiles = ((g.M + BT - 1) / BT) * g.tiles_n;
+    const int64_t L = blockIdx.x, j = L / 8;
+    zsplit = L % 8 + 8 * (j / tiles);
+    tile_of(j % tiles, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
   } else {
     tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
   }
   const int64_t m0 = tm * BT, n0 = tn * BT;
   int64_t kbeg = 0, kend = g.K;
   if (EPI == EPI_SPLIT) {
-    kbeg = (int64_t)blockIdx.z * g.kchunk;
+    kbeg = zsplit * g.kchunk;
     kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
   }
   const T* A = (const T*)g.A;
@@ -525,7 +536,7 @@ __global__ __launch_bounds__(64 * DlTile<BT>::NW) void gemm_lp_dl_kernel(LArgs g
         }
       }
   } else {
-    float* W = (float*)g.C + (int64_t)blockIdx.z * g.split_stride;
+    float* W = (float*)g.C + zsplit * g.split_stride;
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -633,7 +644,17 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
   a.C = q.work;
   a.kchunk = chunk;
   a.split_stride = q.M * q.N;
-  if (dl)
+  if (dl && q.big_tiles && sizeof(T) == 2) {
+    a.tiles_n = (q.N + 255) / 256;
+    const int64_t t256 = ((q.M + 255) / 256) * a.tiles_n;
+    a.xcd_split = ks % 8 == 0 ? 1 : 0;
+    if (a.xcd_split)
+      hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT, 256>),
+                         dim3((unsigned)(t256 * ks)), dim3(64 * DlTile<256>::NW), 0, s, a);
+    else
+      hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT, 256>),
+                         dim3((unsigned)t256, 1, (unsigned)ks), dim3(64 * DlTile<256>::NW), 0, s, a);
+  } else if (dl)
     hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT>),
                        dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
   else

@@ -130,6 +130,7 @@ struct LpGemm {
   int ks = 1;
   float* work = nullptr;
   bool k_padded = false;  // every row of A and B holds zeros from K up to a multiple of 8 elements
+  bool big_tiles = false; // BF16 split-K: 256 x 256 tiles on eight waves
 };
 void lp_gemm(const LpGemm& g, hipStream_t s);
 // C = alpha A B^T + beta C for M, N <= 16, one batch, A [M][K] and B [N][K] K-contiguous and

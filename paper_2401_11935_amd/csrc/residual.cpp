@@ -829,6 +829,13 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
           q.C = Rb; q.ldc = N;
           q.ks = ks; q.work = lwork;
           q.k_padded = true;
+          // BF16: 256 x 256 tiles, split about 256 ways (one workgroup per compute unit)
+          if (prec_now == DCSD_PREC_BF16 && M >= 256 && N >= 256) {
+            const int64_t t256 = ((M + 255) / 256) * ((N + 255) / 256);
+            q.ks = (int)std::min<int64_t>(split_cap, std::max<int64_t>(1, 256 / t256));
+            q.ks = (int)std::min<int64_t>(q.ks, std::max<int64_t>(1, vu2 / 1024));
+            q.big_tiles = true;
+          }
           lp_gemm(q, s);
         } else {
           G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
