@@ -135,7 +135,7 @@ struct Ctx {
     double *Ar = nullptr, *Br = nullptr, *Pr = nullptr;
     bool valid = false;
   };
-  static constexpr int kSites = 6;
+  static constexpr int kSites = 11;
   Site site[kSites];
   // scalars and reductions
   double* part = nullptr;

@@ -66,7 +66,9 @@ struct G {
     if (t_tape) tape_gemm(a);
     gemm_f64(a, c.s);
   }
-  void ring(Ctx& c, int site, bool a_var, bool b_var);
+  // fp64_plain: FP64 outside the delta form (low precision only for the changes since a
+  // refresh point)
+  void ring(Ctx& c, int site, bool a_var, bool b_var, bool fp64_plain = false);
   void lp_product(Ctx& c, const double* A, const double* Asub, const double* B, const double* Bsub,
                   double beta = 1.0);
 };

@@ -32,10 +32,12 @@ namespace dcsd {
 // precision: operands rounded into K-contiguous FP32/BF16 copies and
 // multiplied on the low-precision MFMA with FP32 accumulation; DELTA uses
 // A B = P_r + (A - A_r) B + A_r (B - B_r), rounding only the differences.
-// C must be a compact row-major M x N matrix.  Timed as class 3.
-void G::ring(Ctx& c, int site, bool a_var, bool b_var) {
+// The dressed-integral products (fp64_plain) take low precision only in that
+// delta form and stay FP64 otherwise.  C must be a compact row-major M x N
+// matrix.  Ring sites are timed as class 3.
+void G::ring(Ctx& c, int site, bool a_var, bool b_var, bool fp64_plain) {
   hipEvent_t ev;
-  const int rec = c.tbegin(&ev);
+  const int rec = fp64_plain ? 0 : c.tbegin(&ev);  // the dressed-integral sites are not ring GEMMs
   if (a.ldc != a.N || !a.c_nc || a.batch != 1 || a.lda != (a.a_mc ? a.M : a.K) || a.ldb != (a.b_nc ? a.N : a.K))
     throw ArgError("ring GEMM site with a non-compact layout");
   Ctx::Site& st = c.site[site];
@@ -59,6 +61,8 @@ void G::ring(Ctx& c, int site, bool a_var, bool b_var) {
     axpby(a.C, st.Pr, a.alpha, a.beta, MN, c.s);
     if (a_var) lp_product(c, a.A, st.Ar, a.B, nullptr);
     if (b_var) lp_product(c, a_var ? st.Ar : a.A, nullptr, a.B, st.Br);
+  } else if (fp64_plain) {
+    run(c);  // the dressed integrals stay FP64 outside the delta form
   } else {
     lp_product(c, a.A, nullptr, a.B, nullptr, a.beta);
   }
@@ -377,22 +381,29 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     fill((double*)TstackL, 0.0, (rows_all * kp * es + 7) / 8, s);
     fill((double*)V2L, 0.0, ((int64_t)lb * lb * kp * es + 7) / 8, s);
     const int64_t lpm = std::max({tov, sfr, sfc});
-    lp_cap = lpm * lp_ld(lpm);
+    // the ring operands, and the dressed-integral operands of the delta form (rows of
+    // length naux, or tov for the singles intermediate)
+    lp_cap = std::max({lpm * lp_ld(lpm), tov * lp_ld(NA), n2 * lp_ld(NA), NA * lp_ld(tov), too2 * lp_ld(NA)});
     lpA = lp_alloc(lp_cap);
     lpB = lp_alloc(lp_cap);
     lwork_cap = std::max<int64_t>(split_cap * rows_all * (int64_t)lb * lb, (int64_t)1 << 22);
     lwork = (float*)alloc((lwork_cap + 1) / 2);
     TstackR = alloc(rows_all * vu2);
     RpR = alloc(rows_main * n2);
-    // ring sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 = spin-flip I T (CCSD); 4, 5 = spin-flip rings
+    // ring sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 = spin-flip I T (CCSD); 4, 5 = spin-flip rings;
+    // dressed-integral sites (delta form only): 6 = (ai|bj)~, 7 = (kc|bj)~, 8, 9 = (kj|pq)~ per spin,
+    // 10 = the singles intermediate Z
     const int64_t sf2 = std::max(sfr, sfc) * std::max(sfr, sfc);
-    const int64_t sz[Ctx::kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2};
-    const bool av[Ctx::kSites] = {false, true, false, false, true, true};
+    const int64_t szA[Ctx::kSites] = {0, tov * tov, 0, 0, sf2, sf2, NA * tov, NA * tov, NA * too2, NA * too2, NA * tov};
+    const int64_t szB[Ctx::kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2, NA * tov, NA * tov, NA * n2, NA * n2,
+                                      tov * tov};
+    const int64_t szP[Ctx::kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2, tov * tov, tov * tov, too2 * n2,
+                                      too2 * n2, NA * tov};
     for (int k = 0; k < Ctx::kSites; ++k) {
       if ((k == 2 || k == 3) && !method_cc(cfg.method)) continue;
-      if (av[k]) site[k].Ar = alloc(sz[k]);
-      site[k].Br = alloc(sz[k]);
-      site[k].Pr = alloc(sz[k]);
+      if (szA[k]) site[k].Ar = alloc(szA[k]);
+      site[k].Br = alloc(szB[k]);
+      site[k].Pr = alloc(szP[k]);
     }
   }
   gws_cap = std::max<int64_t>(1 << 22, 64 * (int64_t)v * v);
@@ -624,7 +635,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
     // sum_kc f~_kc t_ik^ac
     G(tov, 1, tov).A(Tsc, tov, false).B(fvec, 1, true).C(R1, 1).ab(1.0, 1.0).run(*this);
     // Z[P][(s,i,c)] = sum_{(s',k,d)} B~_ov[P][(s',k,d)] t_ik^cd
-    G(NA, tov, tov).A(Bov, tov, false).B(Tsc, tov, true).C(Z, tov).run(*this);
+    G(NA, tov, tov).A(Bov, tov, false).B(Tsc, tov, true).C(Z, tov).ring(*this, 10, true, true, true);
     for (int sp = 0; sp < 2; ++sp) {
       const int o_ = os[sp], v_ = vs[sp];
       if (o_ == 0) continue;
@@ -642,7 +653,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   // ---- driver and ring terms (particle-hole layout) -------------------------------
   // Dvo[(s,i,a),(s',j,b)] = (ai|bj)~
   if (mask & (DCSD_TERM_DRIVER | DCSD_TERM_RING))
-    G(tov, tov, NA).A(Bvo, tov, true).B(Bvo, tov, true).C(Dvo, tov).run(*this);
+    G(tov, tov, NA).A(Bvo, tov, true).B(Bvo, tov, true).C(Dvo, tov).ring(*this, 6, true, true, true);
   if (!(mask & DCSD_TERM_DRIVER)) rfill(Dvo, 0.0, tov * tov, s);
   if (mask & (DCSD_TERM_RING | DCSD_TERM_HH)) {
     // OOOO[(s,k,i),(s',l,j)] = (ki|lj)~
@@ -650,9 +661,9 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
   }
   if (mask & DCSD_TERM_RING) {
     // KCBJ[(s,k,c),(s',j,b)] = (kc|bj)~ ; KJPQ[s'][(s,k,j)][(p,q)] = (kj|pq)~ (p, q in spin s' order)
-    G(tov, tov, NA).A(Bov, tov, true).B(Bvo, tov, true).C(KCBJ, tov).run(*this);
+    G(tov, tov, NA).A(Bov, tov, true).B(Bvo, tov, true).C(KCBJ, tov).ring(*this, 7, true, true, true);
     for (int sp = 0; sp < 2; ++sp)
-      G(too2, n2, NA).A(Boo, too2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).run(*this);
+      G(too2, n2, NA).A(Boo, too2, true).B(Bt[sp], n2, true).C(KJPQ[sp], n2).ring(*this, 8 + sp, true, true, true);
     // W_sc = <kb||cj>~ = (kc|bj)~ - (kj|bc)~ (equal spins)
     for (int sp = 0; sp < 2; ++sp) {
       const int o_ = os[sp], v_ = vs[sp];
