@@ -126,9 +126,9 @@ typedef struct {
   int32_t ladder_block;   /* orbitals per ladder batch side (0 = automatic)    */
   uint32_t term_mask;     /* DCSD_TERM_* bits                                   */
   int32_t precond;        /* DCSD_PRECOND_ORBITAL or DCSD_PRECOND_EN            */
-  int32_t refresh_every;  /* low precision only: FP64 residual every k-th iteration of
-                             dcsd_solve (0 = only when the corrected residual
-                             reaches tol_residual)                               */
+  int32_t refresh_every;  /* low precision only: FP64 residual at least every k-th
+                             iteration of dcsd_solve (0 = only by the rules of
+                             dcsd_solve)                                         */
   int32_t adjoint;        /* 1: dcsd_init also reserves the memory of
                              dcsd_residual_vjp and dcsd_backward (tape operand
                              snapshots, cotangent arrays, sweep work space), so
@@ -234,12 +234,16 @@ dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, dcsd_energies* out);
  * FP64 product.  After the first refresh, low-precision iterations evaluate
  * L(tau) = L(tau_r) + L_low(tau - tau_r) and A B = (A B)_r + (A - A_r) B +
  * A_r (B - B_r) with only the differences rounded, so their error shrinks
- * with |T - T_r|.  A refresh happens when the low-precision residual reaches
- * tol_residual, when it has set no new minimum for 3 iterations (its noise
- * floor), and every refresh_every iterations (if > 0).  Convergence is
- * declared only on a refresh whose FP64 residual meets tol_residual, so the
- * converged amplitudes solve the FP64 equations to the same tolerance.  A
- * refresh iteration costs one low-precision plus one FP64 evaluation. */
+ * with |T - T_r|.  The iteration after a low-precision residual that
+ * reaches tol_residual or has dropped 100-fold (BF16; 10^5-fold in FP32)
+ * below the last refresh is a refresh (one FP64 evaluation), and with
+ * refresh_every = k > 0 at least every k-th iteration is one.  A
+ * low-precision residual that has set no new minimum for 3 iterations sits
+ * on its noise floor: the FP64 residual at the same amplitudes replaces it
+ * (that iteration costs one low-precision and one FP64 evaluation).
+ * Convergence is declared only on a refresh whose FP64 residual meets
+ * tol_residual, so the converged amplitudes solve the FP64 equations to the
+ * same tolerance. */
 dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user);
 
 /* Vector-Jacobian product of one residual evaluation (hand-written reverse

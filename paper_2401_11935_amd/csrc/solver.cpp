@@ -144,38 +144,47 @@ int Ctx::solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user) {
     }
     return status;
   };
+  // Refreshes.  A low-precision residual that meets the tolerance, has dropped
+  // by kDrop since the last refresh or completes refresh_every iterations still
+  // takes its step, and the next iteration is the refresh.  One that has set no
+  // new minimum for kStall iterations sits on its noise floor: it is replaced at
+  // once by the FP64 residual at the same amplitudes, which takes the step.
+  constexpr int kStall = 3;
+  const double kDrop = cfg.precision == DCSD_PREC_BF16 ? 1e-2 : 1e-5;
+  bool refresh_next = false;
   for (int it = 0; it < cfg.max_iter; ++it) {
-    residual(T, Rw, nullptr, -1, low && have_ref ? DELTA : PLAIN);
+    bool exact = !low || refresh_next;
+    if (low && refresh_next)
+      residual(T, Rw, nullptr, DCSD_PREC_FP64, RECORD);
+    else
+      residual(T, Rw, nullptr, -1, low && have_ref ? DELTA : PLAIN);
     double host[4];
     int bad = 0;
     measure(host, bad);
-    bool exact = !low;
-    // refresh when the low-precision residual meets the tolerance, has dropped
-    // by kDrop since the last refresh, has made no new minimum for kStall
-    // iterations (it sits on its noise floor), or every refresh_every iterations
-    constexpr int kStall = 3;
-    const double kDrop = cfg.precision == DCSD_PREC_BF16 ? 1e-2 : 1e-5;
-    if (low && (best_it < 0 || host[1] < best)) {
-      best = host[1];
-      best_it = it;
+    if (low && !exact) {
+      ++since;
+      if (best_it < 0 || host[1] < best) {
+        best = host[1];
+        best_it = it;
+      }
+      if (it == 0) ref_res = host[1];
+      if (!bad && it - best_it >= kStall) {
+        residual(T, Rw, nullptr, DCSD_PREC_FP64, RECORD);
+        measure(host, bad);
+        exact = true;
+      }
     }
-    const bool stalled = low && it - best_it >= kStall;
-    if (it == 0) ref_res = host[1];
-    const bool dropped = low && host[1] <= kDrop * ref_res;
-    if (low && !bad && (host[1] <= cfg.tol_residual || stalled || dropped ||
-                        (cfg.refresh_every > 0 && since + 1 >= cfg.refresh_every))) {
-      // refresh: FP64 residual at T, recorded as the new reference point
-      residual(T, Rw, nullptr, DCSD_PREC_FP64, RECORD);
-      measure(host, bad);
+    if (low && exact) {  // a refresh: the new reference point
       have_ref = true;
       since = 0;
-      exact = true;
       best = host[1];
       best_it = it;
       ref_res = host[1];
-    } else if (low) {
-      ++since;
     }
+    refresh_next = low && !bad &&
+                   (exact ? cfg.refresh_every == 1
+                          : (host[1] <= cfg.tol_residual || host[1] <= kDrop * ref_res ||
+                             (cfg.refresh_every > 0 && since + 1 >= cfg.refresh_every)));
     r.iterations = it + 1;
     r.res_max = host[1];
     r.res_rms = std::sqrt(std::max(host[3], 0.0) / (double)total);
