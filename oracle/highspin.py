@@ -115,6 +115,12 @@ class HighSpin:
         dE = self.energy(vec)
         return {"dE_A": dE, "W": 0.0, "E_S": float("nan"), "E_T": dE, "E_ref_A": self.ham.e_ref()}
 
+    def triples(self, vec: np.ndarray) -> dict:
+        """(T) correction at the amplitudes vec (triples.py), with its parts."""
+        from .triples import triples_energy
+        t1, t2 = self.ham.to_so(vec)
+        return triples_energy(self.ham, t1, t2)
+
     def denominators(self) -> np.ndarray:
         """D_x = sum f_ii - sum f_aa from the spin-orbital Fock diagonal (packed)."""
         fo = np.diag(self.ints["foo"])
