@@ -214,6 +214,38 @@ dcsd_status dcsd_residual(dcsd_ctx* ctx, const double* T_dev, double* R_dev, dou
  * arguments. */
 dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, dcsd_energies* out);
 
+typedef struct {
+  double e_t4;     /* E[4]_T: sum of N^c N^c / D                               */
+  double e_st5;    /* E[5]_ST: N^c times the t1 <jk||bc> disconnected term / D */
+  double e_dt;     /* N^c times the f_ia t_jk^bc disconnected term / D         */
+  double e_t;      /* E_(T) = e_t4 + e_st5 + e_dt                              */
+  int64_t triples; /* occupied spin-orbital triples i < j < k summed           */
+} dcsd_triples_energy;
+
+/* Perturbative triples correction E_(T) of the M_s = 1 high-spin methods
+ * (DCSD_METHOD_HS_DCSD / HS_CCSD) at amplitudes T, normally the converged
+ * ones.  The paper names perturbative-triples extensions of 2D-CCSD only as
+ * other work (Introduction) and defines none; this is the standard
+ * single-reference (T) expression applied to the single determinant Phi_T:
+ * in spin orbitals
+ *   N^c_ijk^abc = P(i/jk) P(a/bc) [sum_e t_jk^ae <ei||bc> - sum_m t_im^bc <ma||jk>],
+ *   N^d_ijk^abc = P(i/jk) P(a/bc) [t_i^a <jk||bc> + f_ia t_jk^bc],
+ *   D = f_ii + f_jj + f_kk - f_aa - f_bb - f_cc (Fock diagonal of Phi_T),
+ *   E_(T) = 1/36 sum N^c (N^c + N^d) / D,
+ * with P(i/jk) g = g(ijk) - g(jik) - g(kji) and P(a/bc) alike; DCSD(T) takes
+ * the same expression with DCSD amplitudes.  Spin orbitals: occupied [alpha
+ * core, t, u | beta core], virtual [alpha virt | beta t, u, virt].  FP64.
+ * If contrib_dev is not NULL it receives, on the device, the contribution of
+ * each occupied triple i < j < k (summed over all a, b, c), in lexicographic
+ * order of (i, j, k): C(2 nc + 2, 3) doubles.  The first call allocates the
+ * device memory of the correction and keeps it until dcsd_destroy: the
+ * integrals <ei||bc> of every occupied spin orbital (n_occ n_vir^3 doubles,
+ * n_occ = 2 nc + 2, n_vir = 2 nv + 2), <jk||bc>, the spin-orbital amplitudes
+ * and two n_vir^3 work arrays.  Synchronises.  DCSD_ERR_ARG on NULL out or T
+ * and for the two-determinant and fixed-reference methods, whose triples
+ * correction is not defined here. */
+dcsd_status dcsd_triples(dcsd_ctx* ctx, const double* T_dev, dcsd_triples_energy* out, double* contrib_dev);
+
 /* Solves the amplitude equations starting from T_inout (zeros = the usual
  * start): Jacobi steps with orbital-energy denominators plus Pulay DIIS, all
  * vectors in FP64 on the device, until max |R| <= tol_residual.  T_inout

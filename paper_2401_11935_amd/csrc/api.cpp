@@ -132,6 +132,14 @@ dcsd_status dcsd_energy(dcsd_ctx* ctx, const double* T_dev, dcsd_energies* out) 
   });
 }
 
+dcsd_status dcsd_triples(dcsd_ctx* ctx, const double* T_dev, dcsd_triples_energy* out, double* contrib_dev) {
+  return guarded(ctx, [&] {
+    if (!T_dev || !out) throw dcsd::ArgError("T and out are required");
+    ctx->c.triples(T_dev, out, contrib_dev);
+    return DCSD_OK;
+  });
+}
+
 dcsd_status dcsd_solve(dcsd_ctx* ctx, double* T_inout, dcsd_report* out, dcsd_iter_cb cb, void* user) {
   return guarded(ctx, [&] {
     if (!T_inout) throw dcsd::ArgError("T_inout is required");

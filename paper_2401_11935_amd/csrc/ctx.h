@@ -206,6 +206,14 @@ struct Ctx {
   double energy_A(const double* T);
   int solve(double* T, dcsd_report* rep, dcsd_iter_cb cb, void* user);
   void energies(const double* T, dcsd_energies* out);
+  // perturbative triples of the M_s = 1 determinant (device memory allocated on first use)
+  struct TriBuf {
+    bool ready = false;
+    double *t1so = nullptr, *t2so = nullptr, *fo = nullptr, *fv = nullptr, *fov = nullptr;
+    double *I = nullptr, *oovv = nullptr, *Q = nullptr, *Zt = nullptr, *ZtT = nullptr;
+    double *part = nullptr, *out = nullptr;
+  } tri;
+  void triples(const double* T, dcsd_triples_energy* out, double* contrib);
   void jacobi_diis(int it, double* X, const double* R, std::vector<double>& gram, std::vector<int>& order,
                    int& count);
 };

@@ -1,6 +1,7 @@
 // Launchers of the libdcsd device kernels (internal).
 #pragma once
 
+#include <algorithm>
 #include <vector>
 
 #include "common.h"
@@ -145,5 +146,31 @@ void lp_pairs(int precision, const void* BlT, int64_t ldk, int64_t naux, int64_t
 
 void sumsq_batch(double* K, const double* B, int64_t nb, int64_t n2, hipStream_t s);
 void combine(double* T, const double* V, int64_t stride, const double* c, int m, int64_t n, hipStream_t s);
+
+// ---- perturbative triples of the M_s = 1 determinant (triples.hip) ----------------
+// Spin-orbital dimensions: occupied [alpha oa | beta ob], virtual [alpha va | beta vb];
+// n spatial orbitals; nU = n - ob, the union of the virtual spaces (spatial [ob, n)).
+struct TriDims {
+  int oa = 0, ob = 0, va = 0, vb = 0, n = 0, nU = 0;
+  __host__ __device__ int nO() const { return oa + ob; }
+  __host__ __device__ int nV() const { return va + vb; }
+};
+constexpr int TRI_PART_BLOCKS = 1024;  // partial sums per triple in tri_energy
+// t1so[nO][nV], t2so[nO][nO][nV][nV] (antisymmetric), Fock diagonals fo[nO], fv[nV] and f_ov[nO][nV]
+void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov, const double* T, const double* fa,
+                const double* fb, const SpinLayout& L, const TriDims& d, hipStream_t s);
+// I[X][E][B][C] = <EX||BC> from S[(eU,bU)][(x,cU)] = (eb|xc) (x spatial occupied, row length oa*nU)
+void tri_assemble_vovv(double* I, const double* S, const TriDims& d, hipStream_t s);
+// O[J][K][B][C] = <JK||BC> from S2[(j,bU)][(k,cU)] = (jb|kc)
+void tri_assemble_oovv(double* O, const double* S2, const TriDims& d, hipStream_t s);
+// Q[Y][Z][A][M] = <MA||YZ> from S3[(m,y)][(aU,z)] = (my|az)
+void tri_assemble_ovoo(double* Q, const double* S3, const TriDims& d, hipStream_t s);
+// dst[a][b][c] = src[c][b][a], n x n x n
+void tri_transpose(double* dst, const double* src, int n, hipStream_t s);
+// out4 = {E4, E5, EDT, total} of the occupied triple i < j < k (device, 4 doubles); part:
+// 3 * TRI_PART_BLOCKS doubles of work space
+void tri_energy(double* out4, double* part, const double* Zt, const double* ZtT, const double* t1so,
+                const double* t2so, const double* oovv, const double* fo, const double* fv, const double* fov, int i,
+                int j, int k, const TriDims& d, hipStream_t s);
 
 }  // namespace dcsd

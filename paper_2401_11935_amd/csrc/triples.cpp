@@ -1,0 +1,148 @@
+// Perturbative triples correction E_(T) of the M_s = 1 high-spin determinant
+// (standard single-reference (T) expression in spin orbitals; the paper names
+// triples extensions only as other work).
+//
+// Layout and flow:
+//  * once per context: the integrals <ei||bc> of every occupied spin orbital
+//    (I[i][e][b][c], n_occ n_vir^3 doubles), <jk||bc> and <ma||jk>, assembled
+//    from spatial DF products (FP64 MFMA GEMMs over the auxiliary index) with
+//    the spin selection rules applied elementwise;
+//  * per call: the packed amplitudes unpacked to spin orbitals, then for each
+//    occupied triple i < j < k
+//      Zt[a][bc] = P(i/jk) [sum_e t_jk^ae <ei||bc> - sum_m t_im^bc <ma||jk>]
+//    as FP64 GEMMs accumulated into one n_vir x n_vir^2 array (only the
+//    spin blocks of (a, e) and (a, m) allowed by spin conservation are
+//    multiplied), its 0 <-> 2 transpose, and one pass over (a, b, c) that
+//    forms N^c = P(a/bc) Zt, the disconnected numerator and the denominator
+//    and reduces the three energy parts in a fixed order.
+#include <vector>
+
+#include "ops.h"
+
+namespace dcsd {
+
+namespace {
+// Device array for the set-up only, freed when it leaves scope.
+struct Tmp {
+  double* p = nullptr;
+  explicit Tmp(int64_t n) {
+    if (hipMalloc(&p, (size_t)std::max<int64_t>(n, 1) * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw std::bad_alloc();
+    }
+  }
+  ~Tmp() {
+    if (p) (void)hipFree(p);
+  }
+  Tmp(const Tmp&) = delete;
+  Tmp& operator=(const Tmp&) = delete;
+};
+}  // namespace
+
+void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
+  if (!method_hs(cfg.method))
+    throw ArgError("the triples correction is defined for the high-spin methods (DCSD_METHOD_HS_*) only");
+  TriDims d;
+  d.oa = os[0];
+  d.ob = os[1];
+  d.va = vs[0];
+  d.vb = vs[1];
+  d.n = n;
+  d.nU = n - os[1];
+  const int64_t nO = d.nO(), nV = d.nV(), nU = d.nU, NA = naux, oa = d.oa;
+  const int64_t nV2 = nV * nV, nV3 = nV2 * nV;
+  const int64_t ntrip = nO * (nO - 1) * (nO - 2) / 6;
+  if (!tri.ready) {
+    tri.t1so = alloc(nO * nV);
+    tri.fov = alloc(nO * nV);
+    tri.fo = alloc(nO);
+    tri.fv = alloc(nV);
+    tri.t2so = alloc(nO * nO * nV2);
+    tri.oovv = alloc(nO * nO * nV2);
+    tri.Q = alloc(nO * nO * nV * nO);
+    tri.I = alloc(nO * nV3);
+    tri.Zt = alloc(nV3);
+    tri.ZtT = alloc(nV3);
+    tri.part = alloc(3 * TRI_PART_BLOCKS);
+    tri.out = alloc(std::max<int64_t>(4 * ntrip, 4));
+    // spatial factor blocks: U x U, occupied x U, occupied x occupied, U x occupied
+    const double* Bsp = Bs[0];
+    const int64_t ob = d.ob;
+    Tmp BU(NA * nU * nU), BO(NA * oa * nU), BOO(NA * oa * oa), BVO(NA * nU * oa);
+    copyN(BU.p, Bsp + ob * n + ob, {NA, nU, nU}, {nU * nU, nU, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    copyN(BO.p, Bsp + ob, {NA, oa, nU}, {oa * nU, nU, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    copyN(BOO.p, Bsp, {NA, oa, oa}, {oa * oa, oa, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    copyN(BVO.p, Bsp + ob * n, {NA, nU, oa}, {nU * oa, oa, 1}, {n2, n, 1}, 1.0, 0.0, s);
+    {
+      // S[(e,b)][(x,c)] = (eb|xc) -> <ex||bc>
+      Tmp S(nU * nU * oa * nU);
+      G(nU * nU, oa * nU, NA).A(BU.p, nU * nU, true).B(BO.p, oa * nU, true).C(S.p, oa * nU).run(*this);
+      tri_assemble_vovv(tri.I, S.p, d, s);
+      DCSD_HIP(hipStreamSynchronize(s));
+    }
+    {
+      // S2[(j,b)][(k,c)] = (jb|kc) -> <jk||bc>;  S3[(m,y)][(a,z)] = (my|az) -> <ma||yz>
+      Tmp S2(oa * nU * oa * nU), S3(oa * oa * nU * oa);
+      G(oa * nU, oa * nU, NA).A(BO.p, oa * nU, true).B(BO.p, oa * nU, true).C(S2.p, oa * nU).run(*this);
+      tri_assemble_oovv(tri.oovv, S2.p, d, s);
+      G(oa * oa, nU * oa, NA).A(BOO.p, oa * oa, true).B(BVO.p, nU * oa, true).C(S3.p, nU * oa).run(*this);
+      tri_assemble_ovoo(tri.Q, S3.p, d, s);
+      DCSD_HIP(hipStreamSynchronize(s));
+    }
+    tri.ready = true;
+  }
+  tri_unpack(tri.t1so, tri.t2so, tri.fo, tri.fv, tri.fov, T, f[0], f[1], L, d, s);
+
+  const int64_t off_v[2] = {0, d.va}, nvs[2] = {d.va, d.vb}, off_o[2] = {0, d.oa}, nos[2] = {d.oa, d.ob};
+  int64_t t = 0;
+  for (int i = 0; i < nO; ++i)
+    for (int j = i + 1; j < nO; ++j)
+      for (int k = j + 1; k < nO; ++k, ++t) {
+        fill(tri.Zt, 0.0, nV3, s);
+        // P(i/jk): (x; y z) = (i; j k), (j; i k), (k; j i) with signs +, -, -
+        const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
+        const double sg[3] = {1.0, -1.0, -1.0};
+        for (int p = 0; p < 3; ++p) {
+          const int64_t x = xs[p], y = ys[p], z = zs[p];
+          const int sy = y >= d.oa, sz = z >= d.oa;
+          for (int sa = 0; sa < 2; ++sa) {
+            // spin conservation: t_yz^{ae} and <ma||yz> need s(e) = s(m) = s(y) + s(z) - s(a)
+            const int se = sy + sz - sa;
+            if (se < 0 || se > 1 || nvs[sa] == 0) continue;
+            if (nvs[se] > 0)
+              G(nvs[sa], nV2, nvs[se])
+                  .A(tri.t2so + ((y * nO + z) * nV + off_v[sa]) * nV + off_v[se], nV, false)
+                  .B(tri.I + (x * nV + off_v[se]) * nV2, nV2, true)
+                  .C(tri.Zt + off_v[sa] * nV2, nV2)
+                  .ab(sg[p], 1.0)
+                  .run(*this);
+            if (nos[se] > 0)
+              G(nvs[sa], nV2, nos[se])
+                  .A(tri.Q + ((y * nO + z) * nV + off_v[sa]) * nO + off_o[se], nO, false)
+                  .B(tri.t2so + (x * nO + off_o[se]) * nV2, nV2, true)
+                  .C(tri.Zt + off_v[sa] * nV2, nV2)
+                  .ab(-sg[p], 1.0)
+                  .run(*this);
+          }
+        }
+        tri_transpose(tri.ZtT, tri.Zt, (int)nV, s);
+        tri_energy(tri.out + 4 * t, tri.part, tri.Zt, tri.ZtT, tri.t1so, tri.t2so, tri.oovv, tri.fo, tri.fv, tri.fov, i,
+                   j, k, d, s);
+      }
+  std::vector<double> h((size_t)std::max<int64_t>(4 * ntrip, 4), 0.0);
+  if (ntrip > 0)
+    DCSD_HIP(hipMemcpyAsync(h.data(), tri.out, 4 * ntrip * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (contrib && ntrip > 0) copyN(contrib, tri.out + 3, {ntrip}, {1}, {4}, 1.0, 0.0, s);
+  DCSD_HIP(hipStreamSynchronize(s));
+  dcsd_triples_energy e{};
+  for (int64_t q = 0; q < ntrip; ++q) {
+    e.e_t4 += h[4 * q + 0];
+    e.e_st5 += h[4 * q + 1];
+    e.e_dt += h[4 * q + 2];
+  }
+  e.e_t = e.e_t4 + e.e_st5 + e.e_dt;
+  e.triples = ntrip;
+  *out = e;
+}
+
+}  // namespace dcsd

@@ -1,0 +1,279 @@
+// Device kernels of the perturbative triples correction of the M_s = 1
+// determinant: spin-orbital unpacking of the amplitudes, integral assembly from
+// spatial DF products, the 0 <-> 2 axis transpose and the per-triple energy
+// reduction.  The contractions themselves are FP64 MFMA GEMMs (triples.cpp).
+//
+// Spin-orbital order: occupied [alpha occupied (oa) | beta occupied (ob)],
+// virtual [alpha virtual (va) | beta virtual (vb)].  For the M_s = 1
+// determinant both spins keep the spatial order, so the occupied spatial index
+// of I is I (alpha) or I - oa (beta), and the virtual A sits at spatial
+// oa + A (alpha) or ob + A - va (beta).  The integral products run over the
+// union of the virtual spaces, U = spatial [ob, n), with alpha virtuals at
+// U index (oa - ob) + A and beta virtuals at A - va.
+#include "kernels.h"
+
+namespace dcsd {
+
+namespace {
+
+constexpr int TRI_THREADS = 256;
+
+inline unsigned tri_blocks(int64_t total, int threads, int64_t cap = 1 << 20) {
+  int64_t b = (total + threads - 1) / threads;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, cap));
+}
+
+__device__ inline int vspin(const TriDims& d, int A) { return A >= d.va; }
+__device__ inline int vU(const TriDims& d, int A) { return A < d.va ? (d.oa - d.ob) + A : A - d.va; }
+__device__ inline int ospin(const TriDims& d, int I) { return I >= d.oa; }
+__device__ inline int osp(const TriDims& d, int I) { return I < d.oa ? I : I - d.oa; }
+
+// t2so[I][J][A][B] from the packed blocks (t2aa, t2bb: full squares; t2ab: [i][j][a][b])
+__global__ void tri_unpack_t2(double* t2so, const double* T, SpinLayout L, TriDims d) {
+  const int64_t nO = d.nO(), nV = d.nV();
+  const int64_t total = nO * nO * nV * nV;
+  const double* aa = T + L.t2_off(0);
+  const double* bb = T + L.t2_off(1);
+  const double* ab = T + L.t2_off(2);
+  const int64_t oa = d.oa, ob = d.ob, va = d.va, vb = d.vb;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t B = x % nV, A = (x / nV) % nV, J = (x / (nV * nV)) % nO, I = x / (nV * nV * nO);
+    const int si = I >= oa, sj = J >= oa, sa = A >= va, sb = B >= va;
+    const int64_t i = si ? I - oa : I, j = sj ? J - oa : J, a = sa ? A - va : A, b = sb ? B - va : B;
+    double v = 0.0;
+    if (si == sj) {
+      if (sa == si && sb == si)
+        v = si ? bb[((i * ob + j) * vb + a) * vb + b] : aa[((i * oa + j) * va + a) * va + b];
+    } else if (sa != sb) {
+      // alpha-beta block t_{i alpha, j beta}^{a alpha, b beta} and its antisymmetric images
+      const int64_t ia = si ? j : i, jb = si ? i : j, aa_ = sa ? b : a, bb_ = sa ? a : b;
+      const double sgn = (si == sa) ? 1.0 : -1.0;
+      v = sgn * ab[((ia * ob + jb) * va + aa_) * vb + bb_];
+    }
+    t2so[x] = v;
+  }
+}
+
+// t1so[I][A]; Fock diagonals fo[I], fv[A] and f_ov[I][A] from the per-spin Fock matrices
+__global__ void tri_unpack_small(double* t1so, double* fo, double* fv, double* fov, const double* T,
+                                 const double* fa, const double* fb, SpinLayout L, TriDims d) {
+  const int nO = d.nO(), nV = d.nV(), n = d.n;
+  const int64_t total = (int64_t)nO * nV;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int I = (int)(x / nV), A = (int)(x % nV);
+    const int si = ospin(d, I), sa = vspin(d, A);
+    const int i = osp(d, I), a = sa ? A - d.va : A;
+    const double* f = si ? fb : fa;
+    const int oo = si ? d.ob : d.oa;
+    double t = 0.0, g = 0.0;
+    if (si == sa) {
+      t = T[L.t1_off(si) + (int64_t)i * (si ? d.vb : d.va) + a];
+      g = f[(int64_t)i * n + oo + a];
+    }
+    t1so[x] = t;
+    fov[x] = g;
+    if (A == 0) fo[I] = f[(int64_t)i * n + i];
+    if (I == 0) {
+      const double* fs = sa ? fb : fa;
+      const int p = (sa ? d.ob : d.oa) + a;
+      fv[A] = fs[(int64_t)p * n + p];
+    }
+  }
+}
+
+// I[X][E][B][C] = <eX||bc> = (eb|Xc)[se = sb][sX = sc] - (ec|Xb)[se = sc][sX = sb]
+// from S[(eU, bU)][(x, cU)] = (eb|xc), row length oa * nU
+__global__ void tri_vovv(double* I, const double* S, TriDims d) {
+  const int64_t nO = d.nO(), nV = d.nV(), nU = d.nU;
+  const int64_t total = nO * nV * nV * nV, ldS = (int64_t)d.oa * nU;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int C = (int)(x % nV), B = (int)((x / nV) % nV), E = (int)((x / (nV * nV)) % nV);
+    const int X = (int)(x / (nV * nV * nV));
+    const int sx = ospin(d, X), se = vspin(d, E), sb = vspin(d, B), sc = vspin(d, C);
+    const int64_t xs = osp(d, X), eU = vU(d, E), bU = vU(d, B), cU = vU(d, C);
+    double v = 0.0;
+    if (se == sb && sx == sc) v += S[(eU * nU + bU) * ldS + xs * nU + cU];
+    if (se == sc && sx == sb) v -= S[(eU * nU + cU) * ldS + xs * nU + bU];
+    I[x] = v;
+  }
+}
+
+// O[J][K][B][C] = <jk||bc> = (jb|kc)[sj = sb][sk = sc] - (jc|kb)[sj = sc][sk = sb]
+// from S2[(j, bU)][(k, cU)] = (jb|kc), row length oa * nU
+__global__ void tri_oovv(double* O, const double* S2, TriDims d) {
+  const int64_t nO = d.nO(), nV = d.nV(), nU = d.nU;
+  const int64_t total = nO * nO * nV * nV, ld = (int64_t)d.oa * nU;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int C = (int)(x % nV), B = (int)((x / nV) % nV), K = (int)((x / (nV * nV)) % nO);
+    const int J = (int)(x / (nV * nV * nO));
+    const int sj = ospin(d, J), sk = ospin(d, K), sb = vspin(d, B), sc = vspin(d, C);
+    const int64_t js = osp(d, J), ks = osp(d, K), bU = vU(d, B), cU = vU(d, C);
+    double v = 0.0;
+    if (sj == sb && sk == sc) v += S2[(js * nU + bU) * ld + ks * nU + cU];
+    if (sj == sc && sk == sb) v -= S2[(js * nU + cU) * ld + ks * nU + bU];
+    O[x] = v;
+  }
+}
+
+// Q[Y][Z][A][M] = <mA||yz> = (my|Az)[sm = sy][sA = sz] - (mz|Ay)[sm = sz][sA = sy]
+// from S3[(m, y)][(aU, z)] = (my|az), row length nU * oa
+__global__ void tri_ovoo(double* Q, const double* S3, TriDims d) {
+  const int64_t nO = d.nO(), nV = d.nV(), oa = d.oa;
+  const int64_t total = nO * nO * nV * nO, ld = (int64_t)d.nU * oa;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int M = (int)(x % nO), A = (int)((x / nO) % nV), Z = (int)((x / (nO * nV)) % nO);
+    const int Y = (int)(x / (nO * nV * nO));
+    const int sm = ospin(d, M), sa = vspin(d, A), sy = ospin(d, Y), sz = ospin(d, Z);
+    const int64_t ms = osp(d, M), ys = osp(d, Y), zs = osp(d, Z), aU = vU(d, A);
+    double v = 0.0;
+    if (sm == sy && sa == sz) v += S3[(ms * oa + ys) * ld + aU * oa + zs];
+    if (sm == sz && sa == sy) v -= S3[(ms * oa + zs) * ld + aU * oa + ys];
+    Q[x] = v;
+  }
+}
+
+// dst[a][b][c] = src[c][b][a] for an n x n x n array: one (a, c) tile of 32 x 32 per
+// workgroup and b, staged through LDS so that both sides are read and written along
+// their contiguous index.
+__global__ void tri_transpose02(double* dst, const double* src, int n) {
+  __shared__ double tile[32][33];
+  const int64_t b = blockIdx.z;
+  const int a0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+  const int64_t nn = (int64_t)n * n;
+  // read src[c][b][a] for c in the c-tile (rows) and a in the a-tile (contiguous)
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int c = c0 + r, a = a0 + threadIdx.x;
+    if (c < n && a < n) tile[r][threadIdx.x] = src[(int64_t)c * nn + b * n + a];
+  }
+  __syncthreads();
+  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    const int a = a0 + r, c = c0 + threadIdx.x;
+    if (a < n && c < n) dst[(int64_t)a * nn + b * n + c] = tile[threadIdx.x][r];
+  }
+}
+
+__device__ double tri_block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = TRI_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Per-block partial sums over all (a, b, c) of one occupied triple (i, j, k):
+// w = N^c / D, parts w N^c, w N^d1, w N^d2 with
+//   N^c = Zt[a][b][c] - Zt[b][a][c] - Zt[c][b][a]           (Zt = P(i/jk) of the GEMM sums)
+//   N^d = P(i/jk) P(a/bc) [t_i^a <jk||bc> + f_ia t_jk^bc]
+__global__ void __launch_bounds__(TRI_THREADS)
+tri_energy_partial(double* part, const double* Zt, const double* ZtT, const double* t1so, const double* t2so,
+                   const double* oovv, const double* fo, const double* fv, const double* fov, int i, int j, int k,
+                   TriDims d) {
+  __shared__ double sh[TRI_THREADS];
+  const int64_t nO = d.nO(), nV = d.nV(), nV2 = nV * nV;
+  const int64_t total = nV2 * nV;
+  const double fijk = fo[i] + fo[j] + fo[k];
+  const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
+  const double sg[3] = {1.0, -1.0, -1.0};
+  double e4 = 0.0, e5 = 0.0, edt = 0.0;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = x % nV, b = (x / nV) % nV, a = x / nV2;
+    const double nc = Zt[x] - Zt[(b * nV + a) * nV + c] - ZtT[x];
+    if (nc == 0.0) continue;
+    double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+      const double* O = oovv + ((int64_t)ys[p] * nO + zs[p]) * nV2;
+      const double* T2 = t2so + ((int64_t)ys[p] * nO + zs[p]) * nV2;
+      const double* t1 = t1so + (int64_t)xs[p] * nV;
+      const double* f = fov + (int64_t)xs[p] * nV;
+      d1 += sg[p] * (t1[a] * O[b * nV + c] - t1[b] * O[a * nV + c] - t1[c] * O[b * nV + a]);
+      d2 += sg[p] * (f[a] * T2[b * nV + c] - f[b] * T2[a * nV + c] - f[c] * T2[b * nV + a]);
+    }
+    const double w = nc / (fijk - fv[a] - fv[b] - fv[c]);
+    e4 += w * nc;
+    e5 += w * d1;
+    edt += w * d2;
+  }
+  e4 = tri_block_sum(e4, sh);
+  e5 = tri_block_sum(e5, sh);
+  edt = tri_block_sum(edt, sh);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x + 0] = e4;
+    part[3 * blockIdx.x + 1] = e5;
+    part[3 * blockIdx.x + 2] = edt;
+  }
+}
+
+// out[0..3] = scale * (sum of the partials of each part, and their total); fixed order
+__global__ void __launch_bounds__(TRI_THREADS) tri_energy_reduce(double* out, const double* part, int nb,
+                                                                 double scale) {
+  __shared__ double sh[TRI_THREADS];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += TRI_THREADS)
+    for (int q = 0; q < 3; ++q) s[q] += part[3 * b + q];
+  for (int q = 0; q < 3; ++q) s[q] = tri_block_sum(s[q], sh);
+  if (threadIdx.x == 0) {
+    out[0] = scale * s[0];
+    out[1] = scale * s[1];
+    out[2] = scale * s[2];
+    out[3] = scale * (s[0] + s[1] + s[2]);
+  }
+}
+
+}  // namespace
+
+void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov, const double* T, const double* fa,
+                const double* fb, const SpinLayout& L, const TriDims& d, hipStream_t s) {
+  const int64_t n2 = (int64_t)d.nO() * d.nO() * d.nV() * d.nV();
+  hipLaunchKernelGGL(tri_unpack_t2, dim3(tri_blocks(n2, TRI_THREADS)), dim3(TRI_THREADS), 0, s, t2so, T, L, d);
+  DCSD_CHECK_LAUNCH();
+  const int64_t n1 = (int64_t)d.nO() * d.nV();
+  hipLaunchKernelGGL(tri_unpack_small, dim3(tri_blocks(n1, TRI_THREADS)), dim3(TRI_THREADS), 0, s, t1so, fo, fv, fov,
+                     T, fa, fb, L, d);
+  DCSD_CHECK_LAUNCH();
+}
+
+void tri_assemble_vovv(double* I, const double* S, const TriDims& d, hipStream_t s) {
+  const int64_t nV = d.nV(), total = (int64_t)d.nO() * nV * nV * nV;
+  hipLaunchKernelGGL(tri_vovv, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, I, S, d);
+  DCSD_CHECK_LAUNCH();
+}
+
+void tri_assemble_oovv(double* O, const double* S2, const TriDims& d, hipStream_t s) {
+  const int64_t total = (int64_t)d.nO() * d.nO() * d.nV() * d.nV();
+  hipLaunchKernelGGL(tri_oovv, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, O, S2, d);
+  DCSD_CHECK_LAUNCH();
+}
+
+void tri_assemble_ovoo(double* Q, const double* S3, const TriDims& d, hipStream_t s) {
+  const int64_t total = (int64_t)d.nO() * d.nO() * d.nV() * d.nO();
+  hipLaunchKernelGGL(tri_ovoo, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, Q, S3, d);
+  DCSD_CHECK_LAUNCH();
+}
+
+void tri_transpose(double* dst, const double* src, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (n > 65535) throw ArgError("triples: too many virtual spin orbitals for the transpose grid");
+  const dim3 grid((n + 31) / 32, (n + 31) / 32, n);
+  hipLaunchKernelGGL(tri_transpose02, grid, dim3(32, 8), 0, s, dst, src, n);
+  DCSD_CHECK_LAUNCH();
+}
+
+void tri_energy(double* out4, double* part, const double* Zt, const double* ZtT, const double* t1so,
+                const double* t2so, const double* oovv, const double* fo, const double* fv, const double* fov, int i,
+                int j, int k, const TriDims& d, hipStream_t s) {
+  const int64_t nV = d.nV();
+  const unsigned nb = tri_blocks(nV * nV * nV, TRI_THREADS, TRI_PART_BLOCKS);
+  hipLaunchKernelGGL(tri_energy_partial, dim3(nb), dim3(TRI_THREADS), 0, s, part, Zt, ZtT, t1so, t2so, oovv, fo, fv,
+                     fov, i, j, k, d);
+  DCSD_CHECK_LAUNCH();
+  // sum over all (a, b, c) of one triple i < j < k: 1/36 of the full sum times the 6 orders of (i, j, k)
+  hipLaunchKernelGGL(tri_energy_reduce, dim3(1), dim3(TRI_THREADS), 0, s, out4, part, (int)nb, 1.0 / 6.0);
+  DCSD_CHECK_LAUNCH();
+}
+
+}  // namespace dcsd

@@ -40,6 +40,14 @@ class Energies(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class TriplesEnergy(ctypes.Structure):
+    _fields_ = [("e_t4", ctypes.c_double), ("e_st5", ctypes.c_double), ("e_dt", ctypes.c_double),
+                ("e_t", ctypes.c_double), ("triples", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {"E_T4": self.e_t4, "E_ST5": self.e_st5, "E_DT": self.e_dt, "E_T": self.e_t, "triples": self.triples}
+
+
 class Report(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32), ("res_max", ctypes.c_double),
                 ("res_rms", ctypes.c_double), ("e", Energies), ("fp64", ctypes.c_int32)]
@@ -99,6 +107,8 @@ def load(path: str | None = None):
     lib.dcsd_residual.restype = ctypes.c_int
     lib.dcsd_energy.argtypes = [vp, dp, ctypes.POINTER(Energies)]
     lib.dcsd_energy.restype = ctypes.c_int
+    lib.dcsd_triples.argtypes = [vp, dp, ctypes.POINTER(TriplesEnergy), dp]
+    lib.dcsd_triples.restype = ctypes.c_int
     lib.dcsd_solve.argtypes = [vp, dp, ctypes.POINTER(Report), ITER_CB, vp]
     lib.dcsd_solve.restype = ctypes.c_int
     lib.dcsd_device_memory.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -193,6 +203,13 @@ class Context:
         """dE_A, W (from an FP64 residual at T), E_S, E_T and E_ref_A of amplitudes T."""
         e = Energies()
         self._check(self.lib.dcsd_energy(self.h, T_ptr, ctypes.byref(e)))
+        return e.as_dict()
+
+    def triples(self, T_ptr: int, contrib_ptr: int = 0) -> dict:
+        """(T) correction of a high-spin context at amplitudes T (parts, total, number of
+        occupied triples); contrib_ptr: optional device array for the per-triple sums."""
+        e = TriplesEnergy()
+        self._check(self.lib.dcsd_triples(self.h, T_ptr, ctypes.byref(e), contrib_ptr or None))
         return e.as_dict()
 
     def solve(self, T_ptr: int, callback=None) -> dict:
