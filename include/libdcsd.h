@@ -239,9 +239,10 @@ typedef struct {
  * each occupied triple i < j < k (summed over all a, b, c), in lexicographic
  * order of (i, j, k): C(2 nc + 2, 3) doubles.  The first call allocates the
  * device memory of the correction and keeps it until dcsd_destroy: the
- * integrals <ei||bc> of every occupied spin orbital (n_occ n_vir^3 doubles,
- * n_occ = 2 nc + 2, n_vir = 2 nv + 2), <jk||bc>, the spin-orbital amplitudes
- * and two n_vir^3 work arrays.  Synchronises.  DCSD_ERR_ARG on NULL out or T
+ * integrals <ei||bc> of every occupied spin orbital next to the amplitude
+ * rows t_im^bc (n_occ (n_vir + n_occ) n_vir^2 doubles, n_occ = 2 nc + 2,
+ * n_vir = 2 nv + 2), <jk||bc>, the spin-orbital amplitudes and two n_vir^3
+ * work arrays.  Synchronises.  DCSD_ERR_ARG on NULL out or T
  * and for the two-determinant and fixed-reference methods, whose triples
  * correction is not defined here. */
 dcsd_status dcsd_triples(dcsd_ctx* ctx, const double* T_dev, dcsd_triples_energy* out, double* contrib_dev);

@@ -211,7 +211,7 @@ struct Ctx {
     bool ready = false;
     double *t1so = nullptr, *t2so = nullptr, *fo = nullptr, *fv = nullptr, *fov = nullptr;
     double *I = nullptr, *oovv = nullptr, *Q = nullptr, *Zt = nullptr, *ZtT = nullptr;
-    double *part = nullptr, *out = nullptr;
+    double *part = nullptr, *out = nullptr, *Aop = nullptr;
   } tri;
   void triples(const double* T, dcsd_triples_energy* out, double* contrib);
   void jacobi_diis(int it, double* X, const double* R, std::vector<double>& gram, std::vector<int>& order,

@@ -154,13 +154,22 @@ struct TriDims {
   int oa = 0, ob = 0, va = 0, vb = 0, n = 0, nU = 0;
   __host__ __device__ int nO() const { return oa + ob; }
   __host__ __device__ int nV() const { return va + vb; }
+  // Slab of occupied X: nV + nO rows of nV^2, ordered [alpha virtual e | alpha occupied m |
+  // beta virtual e | beta occupied m]; rows e hold <eX||bc>, rows m the amplitudes t_Xm^bc.
+  __host__ __device__ int slab_rows() const { return va + vb + oa + ob; }
+  __host__ __device__ int row_e(int E) const { return E + (E >= va ? oa : 0); }
+  __host__ __device__ int row_m(int M) const { return va + M + (M >= oa ? vb : 0); }
 };
 constexpr int TRI_PART_BLOCKS = 1024;  // partial sums per triple in tri_energy
 // t1so[nO][nV], t2so[nO][nO][nV][nV] (antisymmetric), Fock diagonals fo[nO], fv[nV] and f_ov[nO][nV]
 void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov, const double* T, const double* fa,
                 const double* fb, const SpinLayout& L, const TriDims& d, hipStream_t s);
-// I[X][E][B][C] = <EX||BC> from S[(eU,bU)][(x,cU)] = (eb|xc) (x spatial occupied, row length oa*nU)
+// slab rows row_e(E) of every X: <EX||BC> from S[(eU,bU)][(x,cU)] = (eb|xc) (x spatial occupied,
+// row length oa*nU)
 void tri_assemble_vovv(double* I, const double* S, const TriDims& d, hipStream_t s);
+// A[3][nV][n]: the combined t2 / -<ma||yz> operand of the three orders of (i, j, k)
+void tri_operand_a(double* A, const double* t2so, const double* Q, int i, int j, int k, const TriDims& d,
+                   hipStream_t s);
 // O[J][K][B][C] = <JK||BC> from S2[(j,bU)][(k,cU)] = (jb|kc)
 void tri_assemble_oovv(double* O, const double* S2, const TriDims& d, hipStream_t s);
 // Q[Y][Z][A][M] = <MA||YZ> from S3[(m,y)][(aU,z)] = (my|az)

@@ -4,17 +4,20 @@
 //
 // Layout and flow:
 //  * once per context: the integrals <ei||bc> of every occupied spin orbital
-//    (I[i][e][b][c], n_occ n_vir^3 doubles), <jk||bc> and <ma||jk>, assembled
-//    from spatial DF products (FP64 MFMA GEMMs over the auxiliary index) with
-//    the spin selection rules applied elementwise;
+//    i, <jk||bc> and <ma||jk>, assembled from spatial DF products (FP64 MFMA
+//    GEMMs over the auxiliary index) with the spin selection rules applied
+//    elementwise.  The <ei||bc> rows of i share a slab with the amplitude rows
+//    t_im^bc (written per call), ordered by spin so that for each spin s the
+//    rows [virtual e of spin s | occupied m of spin s] are contiguous: the two
+//    sums of the connected numerator become one GEMM over n = v_s + o_s;
 //  * per call: the packed amplitudes unpacked to spin orbitals, then for each
 //    occupied triple i < j < k
 //      Zt[a][bc] = P(i/jk) [sum_e t_jk^ae <ei||bc> - sum_m t_im^bc <ma||jk>]
-//    as FP64 GEMMs accumulated into one n_vir x n_vir^2 array (only the
-//    spin blocks of (a, e) and (a, m) allowed by spin conservation are
-//    multiplied), its 0 <-> 2 transpose, and one pass over (a, b, c) that
-//    forms N^c = P(a/bc) Zt, the disconnected numerator and the denominator
-//    and reduces the three energy parts in a fixed order.
+//    as at most six FP64 GEMMs (three orders of (i, j, k) times the spins of
+//    a that spin conservation allows) accumulated into one n_vir x n_vir^2
+//    array, its 0 <-> 2 transpose, and one pass over a < b < c that forms
+//    N^c = P(a/bc) Zt, the disconnected numerator and the denominator and
+//    reduces the three energy parts in a fixed order.
 #include <vector>
 
 #include "ops.h"
@@ -60,7 +63,8 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
     tri.t2so = alloc(nO * nO * nV2);
     tri.oovv = alloc(nO * nO * nV2);
     tri.Q = alloc(nO * nO * nV * nO);
-    tri.I = alloc(nO * nV3);
+    tri.I = alloc(nO * d.slab_rows() * nV2);
+    tri.Aop = alloc(3 * nV * (int64_t)n);
     tri.Zt = alloc(nV3);
     tri.ZtT = alloc(nV3);
     tri.part = alloc(3 * TRI_PART_BLOCKS);
@@ -92,39 +96,41 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
     tri.ready = true;
   }
   tri_unpack(tri.t1so, tri.t2so, tri.fo, tri.fv, tri.fov, T, f[0], f[1], L, d, s);
+  // amplitude rows t_xm^bc of every slab x (occupied m of each spin after that spin's virtuals)
+  const int64_t R = d.slab_rows();
+  copyN(tri.I + (int64_t)d.row_m(0) * nV2, tri.t2so, {nO, oa, nV2}, {R * nV2, nV2, 1}, {nO * nV2, nV2, 1}, 1.0, 0.0,
+        s);
+  copyN(tri.I + (int64_t)d.row_m(d.oa) * nV2, tri.t2so + oa * nV2, {nO, (int64_t)d.ob, nV2}, {R * nV2, nV2, 1},
+        {nO * nV2, nV2, 1}, 1.0, 0.0, s);
 
-  const int64_t off_v[2] = {0, d.va}, nvs[2] = {d.va, d.vb}, off_o[2] = {0, d.oa}, nos[2] = {d.oa, d.ob};
+  const int64_t off_v[2] = {0, d.va}, nvs[2] = {d.va, d.vb}, row_e[2] = {0, (int64_t)d.va + d.oa};
   int64_t t = 0;
   for (int i = 0; i < nO; ++i)
     for (int j = i + 1; j < nO; ++j)
       for (int k = j + 1; k < nO; ++k, ++t) {
-        fill(tri.Zt, 0.0, nV3, s);
         // P(i/jk): (x; y z) = (i; j k), (j; i k), (k; j i) with signs +, -, -
         const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
         const double sg[3] = {1.0, -1.0, -1.0};
+        tri_operand_a(tri.Aop, tri.t2so, tri.Q, i, j, k, d, s);
+        bool written[2] = {false, false};
         for (int p = 0; p < 3; ++p) {
-          const int64_t x = xs[p], y = ys[p], z = zs[p];
-          const int sy = y >= d.oa, sz = z >= d.oa;
+          const int64_t x = xs[p];
+          const int sy = ys[p] >= d.oa, sz = zs[p] >= d.oa;
           for (int sa = 0; sa < 2; ++sa) {
             // spin conservation: t_yz^{ae} and <ma||yz> need s(e) = s(m) = s(y) + s(z) - s(a)
             const int se = sy + sz - sa;
             if (se < 0 || se > 1 || nvs[sa] == 0) continue;
-            if (nvs[se] > 0)
-              G(nvs[sa], nV2, nvs[se])
-                  .A(tri.t2so + ((y * nO + z) * nV + off_v[sa]) * nV + off_v[se], nV, false)
-                  .B(tri.I + (x * nV + off_v[se]) * nV2, nV2, true)
-                  .C(tri.Zt + off_v[sa] * nV2, nV2)
-                  .ab(sg[p], 1.0)
-                  .run(*this);
-            if (nos[se] > 0)
-              G(nvs[sa], nV2, nos[se])
-                  .A(tri.Q + ((y * nO + z) * nV + off_v[sa]) * nO + off_o[se], nO, false)
-                  .B(tri.t2so + (x * nO + off_o[se]) * nV2, nV2, true)
-                  .C(tri.Zt + off_v[sa] * nV2, nV2)
-                  .ab(-sg[p], 1.0)
-                  .run(*this);
+            G(nvs[sa], nV2, n)
+                .A(tri.Aop + (p * nV + off_v[sa]) * n, n, false)
+                .B(tri.I + (x * R + row_e[se]) * nV2, nV2, true)
+                .C(tri.Zt + off_v[sa] * nV2, nV2)
+                .ab(sg[p], written[sa] ? 1.0 : 0.0)
+                .run(*this);
+            written[sa] = true;
           }
         }
+        for (int sa = 0; sa < 2; ++sa)
+          if (!written[sa]) fill(tri.Zt + off_v[sa] * nV2, 0.0, nvs[sa] * nV2, s);
         tri_transpose(tri.ZtT, tri.Zt, (int)nV, s);
         tri_energy(tri.out + 4 * t, tri.part, tri.Zt, tri.ZtT, tri.t1so, tri.t2so, tri.oovv, tri.fo, tri.fv, tri.fov, i,
                    j, k, d, s);

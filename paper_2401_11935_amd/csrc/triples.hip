@@ -81,10 +81,10 @@ __global__ void tri_unpack_small(double* t1so, double* fo, double* fv, double* f
   }
 }
 
-// I[X][E][B][C] = <eX||bc> = (eb|Xc)[se = sb][sX = sc] - (ec|Xb)[se = sc][sX = sb]
+// Slab X, row tri_row_e(E): <eX||bc> = (eb|Xc)[se = sb][sX = sc] - (ec|Xb)[se = sc][sX = sb]
 // from S[(eU, bU)][(x, cU)] = (eb|xc), row length oa * nU
 __global__ void tri_vovv(double* I, const double* S, TriDims d) {
-  const int64_t nO = d.nO(), nV = d.nV(), nU = d.nU;
+  const int64_t nO = d.nO(), nV = d.nV(), nU = d.nU, R = d.slab_rows();
   const int64_t total = nO * nV * nV * nV, ldS = (int64_t)d.oa * nU;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
     const int C = (int)(x % nV), B = (int)((x / nV) % nV), E = (int)((x / (nV * nV)) % nV);
@@ -94,7 +94,7 @@ __global__ void tri_vovv(double* I, const double* S, TriDims d) {
     double v = 0.0;
     if (se == sb && sx == sc) v += S[(eU * nU + bU) * ldS + xs * nU + cU];
     if (se == sc && sx == sb) v -= S[(eU * nU + cU) * ldS + xs * nU + bU];
-    I[x] = v;
+    I[((int64_t)X * R + d.row_e(E)) * nV * nV + (int64_t)B * nV + C] = v;
   }
 }
 
@@ -152,6 +152,30 @@ __global__ void tri_transpose02(double* dst, const double* src, int n) {
   }
 }
 
+// A[p][a][kk] (kk < n) of the three orders p of (i, j, k) -> (x; y z) = (i; j k), (j; i k),
+// (k; j i): for a of spin sa and s = s(y) + s(z) - s(a), the columns are t_yz^{a e} over the
+// virtuals e of spin s, then -<m a||y z> over the occupied m of spin s (v_s + o_s = n columns),
+// matching rows tri_row_e(e), tri_row_m(m) of slab x; zero where no spin s exists.
+__global__ void tri_build_a(double* A, const double* t2so, const double* Q, int i, int j, int k, TriDims d) {
+  const int64_t nO = d.nO(), nV = d.nV(), n = d.n;
+  const int64_t total = 3 * nV * n;
+  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t kk = x % n, a = (x / n) % nV;
+    const int p = (int)(x / (n * nV));
+    const int64_t y = p == 0 ? j : (p == 1 ? i : j), z = p == 2 ? i : k;
+    const int se = ospin(d, (int)y) + ospin(d, (int)z) - vspin(d, (int)a);
+    double v = 0.0;
+    if (se == 0 || se == 1) {
+      const int64_t nve = se ? d.vb : d.va;
+      if (kk < nve)
+        v = t2so[((y * nO + z) * nV + a) * nV + (se ? d.va : 0) + kk];
+      else
+        v = -Q[((y * nO + z) * nV + a) * nO + (se ? d.oa : 0) + (kk - nve)];
+    }
+    A[x] = v;
+  }
+}
+
 __device__ double tri_block_sum(double v, double* sh) {
   sh[threadIdx.x] = v;
   __syncthreads();
@@ -164,7 +188,7 @@ __device__ double tri_block_sum(double v, double* sh) {
   return r;
 }
 
-// Per-block partial sums over all (a, b, c) of one occupied triple (i, j, k):
+// Per-block partial sums over a < b < c of one occupied triple (i, j, k):
 // w = N^c / D, parts w N^c, w N^d1, w N^d2 with
 //   N^c = Zt[a][b][c] - Zt[b][a][c] - Zt[c][b][a]           (Zt = P(i/jk) of the GEMM sums)
 //   N^d = P(i/jk) P(a/bc) [t_i^a <jk||bc> + f_ia t_jk^bc]
@@ -174,29 +198,33 @@ tri_energy_partial(double* part, const double* Zt, const double* ZtT, const doub
                    TriDims d) {
   __shared__ double sh[TRI_THREADS];
   const int64_t nO = d.nO(), nV = d.nV(), nV2 = nV * nV;
-  const int64_t total = nV2 * nV;
   const double fijk = fo[i] + fo[j] + fo[k];
   const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
   const double sg[3] = {1.0, -1.0, -1.0};
   double e4 = 0.0, e5 = 0.0, edt = 0.0;
-  for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = x % nV, b = (x / nV) % nV, a = x / nV2;
-    const double nc = Zt[x] - Zt[(b * nV + a) * nV + c] - ZtT[x];
-    if (nc == 0.0) continue;
-    double d1 = 0.0, d2 = 0.0;
+  // one (a, b) pair with a < b per workgroup step, c > b across the threads
+  for (int64_t pr = blockIdx.x; pr < nV2; pr += gridDim.x) {
+    const int64_t a = pr / nV, b = pr % nV;
+    if (a >= b) continue;
+    for (int64_t c = b + 1 + threadIdx.x; c < nV; c += blockDim.x) {
+      const int64_t x = (a * nV + b) * nV + c;
+      const double nc = Zt[x] - Zt[(b * nV + a) * nV + c] - ZtT[x];
+      if (nc == 0.0) continue;
+      double d1 = 0.0, d2 = 0.0;
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-      const double* O = oovv + ((int64_t)ys[p] * nO + zs[p]) * nV2;
-      const double* T2 = t2so + ((int64_t)ys[p] * nO + zs[p]) * nV2;
-      const double* t1 = t1so + (int64_t)xs[p] * nV;
-      const double* f = fov + (int64_t)xs[p] * nV;
-      d1 += sg[p] * (t1[a] * O[b * nV + c] - t1[b] * O[a * nV + c] - t1[c] * O[b * nV + a]);
-      d2 += sg[p] * (f[a] * T2[b * nV + c] - f[b] * T2[a * nV + c] - f[c] * T2[b * nV + a]);
+      for (int p = 0; p < 3; ++p) {
+        const double* O = oovv + ((int64_t)ys[p] * nO + zs[p]) * nV2;
+        const double* T2 = t2so + ((int64_t)ys[p] * nO + zs[p]) * nV2;
+        const double* t1 = t1so + (int64_t)xs[p] * nV;
+        const double* f = fov + (int64_t)xs[p] * nV;
+        d1 += sg[p] * (t1[a] * O[b * nV + c] - t1[b] * O[a * nV + c] - t1[c] * O[b * nV + a]);
+        d2 += sg[p] * (f[a] * T2[b * nV + c] - f[b] * T2[a * nV + c] - f[c] * T2[b * nV + a]);
+      }
+      const double w = nc / (fijk - fv[a] - fv[b] - fv[c]);
+      e4 += w * nc;
+      e5 += w * d1;
+      edt += w * d2;
     }
-    const double w = nc / (fijk - fv[a] - fv[b] - fv[c]);
-    e4 += w * nc;
-    e5 += w * d1;
-    edt += w * d2;
   }
   e4 = tri_block_sum(e4, sh);
   e5 = tri_block_sum(e5, sh);
@@ -237,6 +265,14 @@ void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov,
   DCSD_CHECK_LAUNCH();
 }
 
+void tri_operand_a(double* A, const double* t2so, const double* Q, int i, int j, int k, const TriDims& d,
+                   hipStream_t s) {
+  const int64_t total = 3 * (int64_t)d.nV() * d.n;
+  hipLaunchKernelGGL(tri_build_a, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, A, t2so, Q, i, j, k,
+                     d);
+  DCSD_CHECK_LAUNCH();
+}
+
 void tri_assemble_vovv(double* I, const double* S, const TriDims& d, hipStream_t s) {
   const int64_t nV = d.nV(), total = (int64_t)d.nO() * nV * nV * nV;
   hipLaunchKernelGGL(tri_vovv, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, I, S, d);
@@ -267,12 +303,12 @@ void tri_energy(double* out4, double* part, const double* Zt, const double* ZtT,
                 const double* t2so, const double* oovv, const double* fo, const double* fv, const double* fov, int i,
                 int j, int k, const TriDims& d, hipStream_t s) {
   const int64_t nV = d.nV();
-  const unsigned nb = tri_blocks(nV * nV * nV, TRI_THREADS, TRI_PART_BLOCKS);
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nV * nV, TRI_PART_BLOCKS));
   hipLaunchKernelGGL(tri_energy_partial, dim3(nb), dim3(TRI_THREADS), 0, s, part, Zt, ZtT, t1so, t2so, oovv, fo, fv,
                      fov, i, j, k, d);
   DCSD_CHECK_LAUNCH();
-  // sum over all (a, b, c) of one triple i < j < k: 1/36 of the full sum times the 6 orders of (i, j, k)
-  hipLaunchKernelGGL(tri_energy_reduce, dim3(1), dim3(TRI_THREADS), 0, s, out4, part, (int)nb, 1.0 / 6.0);
+  // 1/36 of the sum over all orders of (i, j, k) and (a, b, c) = the sum over i < j < k, a < b < c
+  hipLaunchKernelGGL(tri_energy_reduce, dim3(1), dim3(TRI_THREADS), 0, s, out4, part, (int)nb, 1.0);
   DCSD_CHECK_LAUNCH();
 }
 
