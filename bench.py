@@ -18,6 +18,7 @@ run).
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -116,6 +117,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip timing the residual VJP")
     ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
     ap.add_argument("--no-weak", action="store_true", help="skip the weak-integral solves")
+    ap.add_argument("--no-highspin", action="store_true", help="skip the high-spin residual, solve and (T)")
     ap.add_argument("--largest", action="store_true",
                     help="also time single residual evaluations at nc=20 nv=600 naux=1800 (FP64, FP32, BF16) and "
                          "try the adjoint's reservation there")
@@ -355,6 +357,73 @@ def fixed_reference_timing(L, torch, args, Bd, Fd, stream, alg):
     return out
 
 
+def triples_flops(nc, nv):
+    """Executed GEMM flops of dcsd_triples: for each occupied triple and each of its three
+    orders (x; y z), one GEMM per spin of a that spin conservation allows, of size
+    v_a x n_vir^2 x n (K = the virtuals plus the occupied of the spin of e)."""
+    oa, ob, va, vb = nc + 2, nc, nv, nv + 2
+    n, nV = nc + 2 + nv, 2 * nv + 2
+    spins = [0] * oa + [1] * ob
+    flops = 0.0
+    for i, j, k in itertools.combinations(range(oa + ob), 3):
+        for x, y, z in ((i, j, k), (j, i, k), (k, j, i)):
+            for sa, nva in ((0, va), (1, vb)):
+                if 0 <= spins[y] + spins[z] - sa <= 1:
+                    flops += 2.0 * nva * nV * nV * n
+    return flops
+
+
+def high_spin_run(L, torch, args, stream):
+    """The M_s = 1 high-spin methods: FP64 HS-DCSD residual evaluations at the metric
+    shape, and on the nc=8 nv=200 naux=600 weak-integral inputs a converged HS-DCSD
+    solve followed by its (T) correction (dcsd_triples, FP64)."""
+    import dcsd_synth as synth
+    out = {}
+    B, F = synth.make_config_inputs(synth.MIXED_WEAK)
+    Bd = torch.from_numpy(B).to("cuda:0")
+    Fd = torch.from_numpy(F).to("cuda:0")
+    c = synth.MIXED_WEAK
+    n_amp = L.amplitude_count(c.nc, c.nv, method="hs-dcsd")
+    T = torch.zeros(n_amp, dtype=torch.float64, device="cuda:0")
+    print("bench: high-spin residual evals", file=sys.stderr, flush=True)
+    _, _, dt, tim = residual_rate(L, torch, L.default_config(nc=c.nc, nv=c.nv, naux=c.naux, method="hs-dcsd"), Bd,
+                                  Fd, stream, T, args.evals)
+    out["residual"] = {"workload": f"HS-DCSD nc={c.nc} nv={c.nv} naux={c.naux}, T = 0", "ms_per_eval": 1e3 * dt,
+                       "residual_evals_per_s": 1.0 / dt, "kernels": tim}
+    del Bd, Fd
+    c = synth.MEDIUM_WEAK
+    B, F = synth.make_config_inputs(c)
+    Bd = torch.from_numpy(B).to("cuda:0")
+    Fd = torch.from_numpy(F).to("cuda:0")
+    cfg = L.default_config(nc=c.nc, nv=c.nv, naux=c.naux, method="hs-dcsd", tol_residual=args.tol)
+    ctx = L.Context(cfg, Bd.data_ptr(), Fd.data_ptr(), stream)
+    T = torch.zeros(ctx.size, dtype=torch.float64, device="cuda:0")
+    print("bench: high-spin solve and (T)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rep = ctx.solve(T.data_ptr())
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ctx.triples(T.data_ptr())   # first call: integrals and slabs
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    e = ctx.triples(T.data_ptr())
+    torch.cuda.synchronize()
+    t_tri = time.perf_counter() - t0
+    mem = ctx.device_memory()[0]
+    ctx.close()
+    fl = triples_flops(c.nc, c.nv)
+    out["solve_and_triples"] = {
+        "workload": f"HS-DCSD(T) nc={c.nc} nv={c.nv} naux={c.naux} seed={c.seed}, weak integrals",
+        "status": rep["status"], "iterations": rep["iterations"], "solve_s": t_solve, "E_T": rep["E_T"],
+        "triples": e, "triples_s": t_tri, "triples_first_call_s": t_first,
+        "triples_gemm_flops": fl, "triples_gemm_tflops": fl / t_tri / 1e12,
+        "triples_frac_of_fp64_peak": fl / t_tri / 1e12 / 78.6, "device_memory_gib": mem / 2 ** 30}
+    return out
+
+
 def adjoint_timing(L, torch, args, Bd, Fd, stream):
     """One residual VJP (dcsd_residual_vjp) at random amplitudes: the amplitude-only
     sweep that each lambda iteration runs, and the full sweep through the constants
@@ -547,6 +616,8 @@ def main():
     if not args.no_adjoint:
         print("bench: residual VJP", file=sys.stderr, flush=True)
         out["adjoint"] = adjoint_timing(L, torch, args, Bd, Fd, stream)
+    if not args.no_highspin:
+        out["high_spin"] = high_spin_run(L, torch, args, stream)
     if args.largest:
         del Bd, Fd
         torch.cuda.empty_cache()

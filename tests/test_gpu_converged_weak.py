@@ -1,0 +1,90 @@
+"""GPU: converged 2D-DCSD / 2D-CCSD on the nc=8, nv=200, naux=600 shape with weak
+integrals (dcsd_synth.MEDIUM_WEAK) against the oracle's converged solve of the
+same inputs (tests/golden/medium_weak.json, written by tests/golden/make_golden.py
+from oracle/ alone).
+
+Bars: energies within 1e-8 Eh, the converged amplitudes at 4096 seeded positions
+within 1e-8, the first iterations following the oracle's (same Jacobi/DIIS
+settings) to 1e-8 relative; the FP32 and BF16 solves reach the oracle's energies
+within 1 microhartree."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import dcsd_synth as synth
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLD = os.path.join(HERE, "golden", "medium_weak.json")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2401_11935_amd import libdcsd
+    libdcsd.load()
+
+
+def _gold(method):
+    gold = json.load(open(GOLD))
+    if method not in gold:
+        pytest.skip(f"{method} not in medium_weak.json")
+    c, cfg = gold["config"], synth.MEDIUM_WEAK
+    assert (c["nc"], c["nv"], c["naux"], c["seed"]) == (cfg.nc, cfg.nv, cfg.naux, cfg.seed)
+    assert abs(c["sigma"] - cfg.sigma) <= 1e-15
+    g = gold[method]
+    assert g["converged"]
+    return g
+
+
+@pytest.mark.parametrize("method", ["dcsd", "ccsd"])
+def test_converged_energies_and_amplitudes_match_oracle(method):
+    from gpu_util import GpuProblem
+    g = _gold(method)
+    cfg = synth.MEDIUM_WEAK
+    say("medium weak converged", method)
+    B, F = synth.make_config_inputs(cfg)
+    p = GpuProblem(B, F, cfg.nc, method, tol_residual=g["tol"], max_iter=300)
+    rep, T = p.solve()
+    p.close()
+    say(f"  GPU {rep['status']} in {rep['iterations']} (oracle {g['iterations']}): "
+        f"|dE_S| {abs(rep['E_S'] - g['E_S']):.2e} |dE_T| {abs(rep['E_T'] - g['E_T']):.2e} "
+        f"|dW| {abs(rep['W'] - g['W']):.2e}")
+    assert rep["status"] == "OK" and rep["res_max"] <= g["tol"]
+    for k in ("E_S", "E_T", "W", "dE_A", "E_ref_A"):
+        assert abs(rep[k] - g[k]) <= 1e-8, (k, rep[k], g[k])
+    idx = np.asarray(g["positions"], dtype=np.int64)
+    dT = float(np.abs(T[idx] - np.asarray(g["T"])).max())
+    say(f"  sampled max|dT| {dT:.2e} (max|T| {g['T_max']:.2e})")
+    assert dT <= 1e-8
+    rel = lambda x, y: abs(x - y) / max(1.0, abs(y))  # noqa: E731
+    for a, b in zip(rep["records"][:5], g["trajectory"][:5]):
+        assert rel(a["E_S"], b["E_S"]) <= 1e-8 and rel(a["res_max"], b["res_max"]) <= 1e-8, (a, b)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_mixed_precision_solves_reach_the_oracle_energies(precision):
+    from gpu_util import GpuProblem
+    g = _gold("dcsd")
+    cfg = synth.MEDIUM_WEAK
+    say("medium weak mixed", precision)
+    B, F = synth.make_config_inputs(cfg)
+    p = GpuProblem(B, F, cfg.nc, "dcsd", tol_residual=g["tol"], max_iter=300, precision=precision)
+    rep, _ = p.solve()
+    p.close()
+    nfp = sum(r["fp64"] for r in rep["records"])
+    say(f"  {rep['status']} in {rep['iterations']} ({nfp} FP64): |dE_S| {abs(rep['E_S'] - g['E_S']):.2e} "
+        f"|dE_T| {abs(rep['E_T'] - g['E_T']):.2e}")
+    assert rep["status"] == "OK" and rep["records"][-1]["fp64"]
+    assert nfp < rep["iterations"]
+    assert abs(rep["E_S"] - g["E_S"]) <= 1e-6 and abs(rep["E_T"] - g["E_T"]) <= 1e-6
