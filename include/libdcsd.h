@@ -140,6 +140,14 @@ typedef struct {
                              the iterations restart from the best amplitudes;
                              the third such event ends the solve with
                              DCSD_ERR_NOCONV (0 = off)                           */
+  int32_t ladder_cache;   /* low precision only: 1 (default) keeps the FP32/BF16
+                             particle-particle ladder integrals (pc|qd) of every
+                             orbital-pair batch in device memory after the first
+                             low-precision evaluation, so that later ones skip
+                             their assembly (they depend on B only, not on T;
+                             metric size nc=12 nv=400: 32 GB in BF16, 65 GB in
+                             FP32).  dcsd_init leaves the cache off when that
+                             memory cannot be allocated.  0: assemble every time */
 } dcsd_config;
 
 typedef struct {
@@ -175,7 +183,8 @@ int64_t dcsd_amplitude_count(int32_t nc, int32_t nv);
 int64_t dcsd_method_amplitude_count(int32_t nc, int32_t nv, int32_t method);
 
 /* Fills *cfg with defaults (DCSD, FP64, DIIS 8 from iteration 2, max_iter 200,
- * tol 1e-10, no shift, all terms, no adjoint reservation, guard_iters 10). */
+ * tol 1e-10, no shift, all terms, no adjoint reservation, guard_iters 10,
+ * ladder_cache 1). */
 void dcsd_default_config(dcsd_config* cfg);
 
 /* Builds a context for the reference determinant Phi_A of the open-shell

@@ -80,6 +80,7 @@ void dcsd_default_config(dcsd_config* c) {
   c->refresh_every = 0;
   c->adjoint = 0;
   c->guard_iters = 10;
+  c->ladder_cache = 1;
 }
 
 dcsd_status dcsd_init(const dcsd_config* cfg, const double* B_dev, const double* F_dev, void* hip_stream,
@@ -216,6 +217,7 @@ dcsd_status dcsd_update_config(dcsd_ctx* ctx, const dcsd_config* cfg) {
         cfg->precision != c.precision || cfg->diis_dim != c.diis_dim || cfg->ladder_block != c.ladder_block)
       throw dcsd::ArgError("only solver settings may change after dcsd_init");
     if (cfg->adjoint != c.adjoint) throw dcsd::ArgError("adjoint is fixed at dcsd_init");
+    if (cfg->ladder_cache != c.ladder_cache) throw dcsd::ArgError("ladder_cache is fixed at dcsd_init");
     if (cfg->max_iter < 1 || !(cfg->tol_residual > 0.0) || !(cfg->level_shift >= 0.0) || cfg->refresh_every < 0 ||
         cfg->guard_iters < 0 ||
         (cfg->precond != DCSD_PRECOND_ORBITAL && cfg->precond != DCSD_PRECOND_EN))

@@ -125,6 +125,11 @@ struct Ctx {
   int mode = PLAIN;
   void* BlT = nullptr;                 // Bl transposed to [(p,c)][P], row stride ldk
   void *TstackL = nullptr, *V2L = nullptr;  // rows of stride kp
+  // low-precision ladder integrals of every batch (cfg.ladder_cache), filled by the first
+  // low-precision evaluation; slot = lb * lb * kp elements
+  void* lcache = nullptr;
+  int64_t lcache_slot = 0;
+  bool lcache_valid = false;
   void *lpA = nullptr, *lpB = nullptr; // rounded ring operands, lp_cap elements each
   float* lwork = nullptr;              // FP32 split-K partials, lwork_cap floats
   int64_t ldk = 0, kp = 0, lp_cap = 0, lwork_cap = 0;

@@ -251,6 +251,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   if (cfg.refresh_every < 0) throw ArgError("refresh_every must be >= 0");
   if (cfg.guard_iters < 0) throw ArgError("guard_iters must be >= 0");
   if (cfg.adjoint != 0 && cfg.adjoint != 1) throw ArgError("adjoint must be 0 or 1");
+  if (cfg.ladder_cache != 0 && cfg.ladder_cache != 1) throw ArgError("ladder_cache must be 0 or 1");
   if (cfg.diis_dim < 0 || cfg.diis_dim > 64) throw ArgError("diis_dim must be in [0, 64]");
   if (cfg.max_iter < 1) throw ArgError("max_iter must be >= 1");
   if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
@@ -380,6 +381,19 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     // padding of both operands is zeroed once here and nothing writes it afterwards
     fill((double*)TstackL, 0.0, (rows_all * kp * es + 7) / 8, s);
     fill((double*)V2L, 0.0, ((int64_t)lb * lb * kp * es + 7) / 8, s);
+    // ladder integral cache: one V2L-sized slot per orbital-pair batch (p-block <= q-block),
+    // row padding zeroed like V2L; left off when the memory is not available
+    if (cfg.ladder_cache) {
+      const int64_t nblk = (n + lb - 1) / lb;
+      lcache_slot = (int64_t)lb * lb * kp;
+      const int64_t cbytes = nblk * (nblk + 1) / 2 * lcache_slot * es;
+      try {
+        lcache = alloc_raw((size_t)cbytes);
+        fill((double*)lcache, 0.0, (cbytes + 7) / 8, s);
+      } catch (const std::bad_alloc&) {
+        lcache = nullptr;
+      }
+    }
     const int64_t lpm = std::max({tov, sfr, sfc});
     // the ring operands, and the dressed-integral operands of the delta form (rows of
     // length naux, or tov for the singles intermediate)
@@ -812,31 +826,37 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
       t_tape = nullptr;
     }
     if (low) lp_convert(prec_now, TstackL, kp, Tstack, delta ? TstackR : nullptr, rows_all, vu2, vu2, 1, s);
+    int64_t batch = 0;
     for (int p0 = 0; p0 < n; p0 += lb) {
       const int np = std::min(lb, n - p0);
-      for (int q0 = p0; q0 < n; q0 += lb) {
+      for (int q0 = p0; q0 < n; q0 += lb, ++batch) {
         const int nq = std::min(lb, n - q0);
         const bool diag = q0 == p0;
-        hipEvent_t ev0;
-        int rec = tbegin(&ev0);
-        if (low)
-          lp_pairs(prec_now, BlT, ldk, NA, vu, p0, np, q0, nq, kp, V2L, s);
-        else
-          gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
-        // algorithmic flops: a diagonal batch needs its np (np + 1) / 2 distinct pairs
-        const double pairs = diag ? 0.5 * np * (np + 1.0) : (double)np * nq;
-        if (rec) tend(ev0, 2.0 * pairs * vu * (double)vu * (double)NA, 0);
+        // low precision with the cache: the batch's slot, assembled on the first evaluation only
+        void* const V2b = low && lcache ? (char*)lcache + batch * lcache_slot * lp_size(prec_now) : V2L;
+        if (!low || !lcache_valid) {
+          hipEvent_t ev0;
+          const int rec = tbegin(&ev0);
+          if (low)
+            lp_pairs(prec_now, BlT, ldk, NA, vu, p0, np, q0, nq, kp, V2b, s);
+          else
+            gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
+          // algorithmic flops: a diagonal batch needs its np (np + 1) / 2 distinct pairs
+          const double pairs = diag ? 0.5 * np * (np + 1.0) : (double)np * nq;
+          if (rec) tend(ev0, 2.0 * pairs * vu * (double)vu * (double)NA, 0);
+        }
         const int64_t M = diag ? rows_main : rows_all;
         const int64_t N = (int64_t)np * nq;
         const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
         int ks = (int)std::min<int64_t>(split_cap, std::max<int64_t>(1, 512 / std::max<int64_t>(tiles, 1)));
         ks = (int)std::min<int64_t>(ks, std::max<int64_t>(1, vu2 / 1024));
-        rec = tbegin(&ev0);
+        hipEvent_t ev0;
+        const int rec = tbegin(&ev0);
         if (low) {
           LpGemm q;
           q.precision = prec_now;
           q.M = M; q.N = N; q.K = vu2;
-          q.A = TstackL; q.lda = kp; q.B = V2L; q.ldb = kp;
+          q.A = TstackL; q.lda = kp; q.B = V2b; q.ldb = kp;
           q.C = Rb; q.ldc = N;
           q.ks = ks; q.work = lwork;
           q.k_padded = true;
@@ -855,6 +875,7 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
         ladder_scatter(Rp, Rb, M, rows_main, oab, n, p0, np, q0, nq, diag, s);
       }
     }
+    if (low && lcache) lcache_valid = true;
     if (mode == RECORD) {
       rcopy(TstackR, Tstack, rows_all * vu2, s);
       rcopy(RpR, Rp, rows_main * n2, s);

@@ -29,7 +29,8 @@ class Config(ctypes.Structure):
                 ("diis_start", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("tol_residual", ctypes.c_double), ("level_shift", ctypes.c_double),
                 ("ladder_block", ctypes.c_int32), ("term_mask", ctypes.c_uint32), ("precond", ctypes.c_int32),
-                ("refresh_every", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("guard_iters", ctypes.c_int32)]
+                ("refresh_every", ctypes.c_int32), ("adjoint", ctypes.c_int32), ("guard_iters", ctypes.c_int32),
+                ("ladder_cache", ctypes.c_int32)]
 
 
 class Energies(ctypes.Structure):

@@ -45,7 +45,7 @@ def test_amplitude_count_and_defaults(lib):
     assert L.amplitude_count(-1, 3, L.load(LIB)) == -1
     c = L.default_config(L.load(LIB))
     assert c.method == 0 and c.diis_dim == 8 and c.max_iter == 200 and c.term_mask == L.TERM_ALL
-    assert c.adjoint == 0 and c.guard_iters == 10
+    assert c.adjoint == 0 and c.guard_iters == 10 and c.ladder_cache == 1
 
 
 def test_ctypes_mirrors_match_the_header(tmp_path):
@@ -90,7 +90,7 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu(lib):
     c = L.default_config(lib2, nc=2, nv=3, naux=5)
     with pytest.raises(L.DcsdError):
         L.Context(c, 0, 0, 0, lib2)      # NULL B and F
-    for bad in (dict(guard_iters=-1), dict(adjoint=2)):
+    for bad in (dict(guard_iters=-1), dict(adjoint=2), dict(ladder_cache=2)):
         c = L.default_config(lib2, nc=2, nv=3, naux=5)
         for k, v in bad.items():
             setattr(c, k, v)
