@@ -118,6 +118,8 @@ def parse():
     ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
     ap.add_argument("--no-weak", action="store_true", help="skip the weak-integral solves")
     ap.add_argument("--no-highspin", action="store_true", help="skip the high-spin residual, solve and (T)")
+    ap.add_argument("--no-cache64", action="store_true",
+                    help="skip the weak-integral solves with the FP64 ladder integrals kept (ladder_cache = 2)")
     ap.add_argument("--largest", action="store_true",
                     help="also time single residual evaluations at nc=20 nv=600 naux=1800 (FP64, FP32, BF16) and "
                          "try the adjoint's reservation there")
@@ -313,6 +315,25 @@ def weak_integral_run(L, torch, args, stream, alg):
             d["median_delta_iteration_ms"] = 1e3 * statistics.median(delta) if delta else None
             d["median_refresh_iteration_ms"] = 1e3 * statistics.median(refresh) if refresh else None
         out[prec] = d
+    # the same solves with the FP64 ladder integrals kept as well (ladder_cache = 2): FP64
+    # iterations and the mixed solver's FP64 refreshes then skip the assembly after the first
+    if not args.no_cache64:
+        cached = {"ladder_cache": 2, "note": "FP64 (129 GB) and, in FP32/BF16, low-precision ladder integrals "
+                  "kept from the first evaluation of each precision; speed-ups against the FP64 solve with the "
+                  "FP64 cache"}
+        for prec in precs:
+            rep, T, recs, elapsed = timed_solve(L, torch, L.default_config(precision=prec, ladder_cache=2, **base),
+                                                Bd, Fd, stream, f"weak {prec} cache64")
+            cached[prec] = {"status": rep["status"], "iterations": rep["iterations"],
+                            "fp64_evaluations": sum(1 for r in recs if r["fp64"]), "solve_s": elapsed,
+                            "E_S": rep["E_S"], "E_T": rep["E_T"], "abs_dE_S_vs_fp64": abs(rep["E_S"] - r64["E_S"]),
+                            "abs_dE_T_vs_fp64": abs(rep["E_T"] - r64["E_T"]),
+                            "median_iteration_ms": 1e3 * statistics.median([r["dt"] for r in recs[1:]] or [0.0])}
+            del T
+        for prec in precs:
+            cached[prec]["speedup_solve_vs_fp64_cached"] = cached["fp64"]["solve_s"] / cached[prec]["solve_s"]
+            cached[prec]["speedup_solve_vs_fp64_assembled"] = solves["fp64"][3] / cached[prec]["solve_s"]
+        out["with_fp64_cache"] = cached
     # single evaluations at the converged FP64 amplitudes (plain mode: the operands themselves rounded)
     T64 = solves["fp64"][1]
     single = {"amplitudes": "converged FP64 amplitudes", "mode": "one residual evaluation, plain (no delta "

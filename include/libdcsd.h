@@ -140,14 +140,17 @@ typedef struct {
                              the iterations restart from the best amplitudes;
                              the third such event ends the solve with
                              DCSD_ERR_NOCONV (0 = off)                           */
-  int32_t ladder_cache;   /* low precision only: 1 (default) keeps the FP32/BF16
-                             particle-particle ladder integrals (pc|qd) of every
-                             orbital-pair batch in device memory after the first
-                             low-precision evaluation, so that later ones skip
-                             their assembly (they depend on B only, not on T;
-                             metric size nc=12 nv=400: 32 GB in BF16, 65 GB in
-                             FP32).  dcsd_init leaves the cache off when that
-                             memory cannot be allocated.  0: assemble every time */
+  int32_t ladder_cache;   /* 1 (default): keep the FP32/BF16 particle-particle
+                             ladder integrals (pc|qd) of every orbital-pair batch
+                             in device memory after the first low-precision
+                             evaluation, so that later ones skip their assembly
+                             (they depend on B only, not on T; nc=12 nv=400:
+                             32 GB in BF16, 65 GB in FP32).  2: the same, and
+                             also the FP64 integrals after the first FP64
+                             evaluation (129 GB at nc=12 nv=400), which serves
+                             FP64 solves and the FP64 refreshes of the mixed
+                             solver.  dcsd_init leaves a cache off when its memory
+                             cannot be allocated.  0: assemble every time        */
 } dcsd_config;
 
 typedef struct {

@@ -130,6 +130,10 @@ struct Ctx {
   void* lcache = nullptr;
   int64_t lcache_slot = 0;
   bool lcache_valid = false;
+  // FP64 ladder integrals of every batch (cfg.ladder_cache = 2), filled by the first FP64 evaluation
+  double* lcache64 = nullptr;
+  int64_t lcache64_slot = 0;
+  bool lcache64_valid = false;
   void *lpA = nullptr, *lpB = nullptr; // rounded ring operands, lp_cap elements each
   float* lwork = nullptr;              // FP32 split-K partials, lwork_cap floats
   int64_t ldk = 0, kp = 0, lp_cap = 0, lwork_cap = 0;

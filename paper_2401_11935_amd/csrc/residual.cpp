@@ -251,7 +251,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   if (cfg.refresh_every < 0) throw ArgError("refresh_every must be >= 0");
   if (cfg.guard_iters < 0) throw ArgError("guard_iters must be >= 0");
   if (cfg.adjoint != 0 && cfg.adjoint != 1) throw ArgError("adjoint must be 0 or 1");
-  if (cfg.ladder_cache != 0 && cfg.ladder_cache != 1) throw ArgError("ladder_cache must be 0 or 1");
+  if (cfg.ladder_cache < 0 || cfg.ladder_cache > 2) throw ArgError("ladder_cache must be 0, 1 or 2");
   if (cfg.diis_dim < 0 || cfg.diis_dim > 64) throw ArgError("diis_dim must be in [0, 64]");
   if (cfg.max_iter < 1) throw ArgError("max_iter must be >= 1");
   if (!(cfg.tol_residual > 0.0)) throw ArgError("tol_residual must be > 0");
@@ -364,6 +364,17 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   const int64_t vu2 = (int64_t)vu * vu;
   Tstack = alloc(rows_all * vu2);
   V2 = alloc((int64_t)lb * lb * vu2);
+  // FP64 ladder integral cache (ladder_cache = 2): one V2-sized slot per orbital-pair batch,
+  // left off when the memory is not available
+  if (cfg.ladder_cache == 2) {
+    const int64_t nblk = (n + lb - 1) / lb;
+    lcache64_slot = (int64_t)lb * lb * vu2;
+    try {
+      lcache64 = (double*)alloc_raw((size_t)(nblk * (nblk + 1) / 2 * lcache64_slot) * sizeof(double));
+    } catch (const std::bad_alloc&) {
+      lcache64 = nullptr;
+    }
+  }
   Rb = alloc(rows_all * (int64_t)lb * lb);
   Rp = alloc(rows_main * n2);
   Smt = alloc(rows_main * (int64_t)n * std::max(vs[0], vs[1]));
@@ -834,13 +845,14 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
         const bool diag = q0 == p0;
         // low precision with the cache: the batch's slot, assembled on the first evaluation only
         void* const V2b = low && lcache ? (char*)lcache + batch * lcache_slot * lp_size(prec_now) : V2L;
-        if (!low || !lcache_valid) {
+        double* const V2d = !low && lcache64 ? lcache64 + batch * lcache64_slot : V2;
+        if (low ? !lcache_valid : !lcache64_valid) {
           hipEvent_t ev0;
           const int rec = tbegin(&ev0);
           if (low)
             lp_pairs(prec_now, BlT, ldk, NA, vu, p0, np, q0, nq, kp, V2b, s);
           else
-            gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2, s);
+            gemm_f64_pairs(Bl, (int64_t)n * vu, vu, NA, p0, np, q0, nq, V2d, s);
           // algorithmic flops: a diagonal batch needs its np (np + 1) / 2 distinct pairs
           const double pairs = diag ? 0.5 * np * (np + 1.0) : (double)np * nq;
           if (rec) tend(ev0, 2.0 * pairs * vu * (double)vu * (double)NA, 0);
@@ -869,13 +881,14 @@ void Ctx::residual(const double* T, double* R, double* W_host, int prec, int md)
           }
           lp_gemm(q, s);
         } else {
-          G(M, N, vu2).A(Tstack, vu2, false).B(V2, vu2, false).C(Rb, N).split(ks, split).run(*this);
+          G(M, N, vu2).A(Tstack, vu2, false).B(V2d, vu2, false).C(Rb, N).split(ks, split).run(*this);
         }
         if (rec) tend(ev0, 2.0 * (double)M * (double)N * (double)vu2, 1);
         ladder_scatter(Rp, Rb, M, rows_main, oab, n, p0, np, q0, nq, diag, s);
       }
     }
     if (low && lcache) lcache_valid = true;
+    if (!low && lcache64) lcache64_valid = true;
     if (mode == RECORD) {
       rcopy(TstackR, Tstack, rows_all * vu2, s);
       rcopy(RpR, Rp, rows_main * n2, s);

@@ -167,26 +167,30 @@ def test_refresh_every_forces_fp64_iterations():
     assert all(flags[i] or flags[i + 1] for i in range(len(flags) - 1))
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp64"])
 @pytest.mark.parametrize("nc,nv,naux,lb", [(2, 5, 13, 3), (3, 16, 60, 5), (4, 40, 64, 0)])
 def test_ladder_cache_is_bitwise_the_assembly(precision, nc, nv, naux, lb):
-    """The cached low-precision ladder integrals give bitwise the residuals of the
-    assembly on every evaluation, and the mixed solves take identical steps."""
+    """The cached ladder integrals (low precision: ladder_cache 1; FP64 and, in a
+    low-precision context, its FP64 refreshes too: ladder_cache 2) give bitwise the
+    residuals of the assembly on every evaluation, and the solves take identical steps."""
     from gpu_util import GpuProblem
     say("ladder cache", precision, nc, nv, naux, lb)
     B, F = synth.make_inputs(nc, nv, naux, 70 + nv)
     Ts = [synth.random_amplitudes(nc, nv, 71 + k, 0.05) for k in range(3)]
+    modes = (0, 1, 2) if precision != "fp64" else (0, 2)
     out = {}
-    for cache in (0, 1):
+    for cache in modes:
         p = GpuProblem(B, F, nc, "dcsd", ladder_block=lb, precision=precision, ladder_cache=cache)
         out[cache] = [p.residual(T) for T in Ts + Ts[:1]]
         p.close()
-    for (Ra, Wa), (Rb, Wb) in zip(out[0], out[1]):
-        assert np.array_equal(Ra, Rb) and Wa == Wb
-    assert np.array_equal(out[1][0][0], out[1][3][0])   # the same T again, from the cache
+    for cache in modes[1:]:
+        for (Ra, Wa), (Rb, Wb) in zip(out[0], out[cache]):
+            assert np.array_equal(Ra, Rb) and Wa == Wb
+        assert np.array_equal(out[cache][0][0], out[cache][3][0])   # the same T again, from the cache
     reps = {}
-    for cache in (0, 1):
+    for cache in modes:
         p = GpuProblem(B, F, nc, "dcsd", ladder_block=lb, precision=precision, ladder_cache=cache, max_iter=12)
         reps[cache], _ = p.solve()
         p.close()
-    assert [r["res_max"] for r in reps[0]["records"]] == [r["res_max"] for r in reps[1]["records"]]
+    for cache in modes[1:]:
+        assert [r["res_max"] for r in reps[0]["records"]] == [r["res_max"] for r in reps[cache]["records"]]

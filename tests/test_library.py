@@ -90,7 +90,7 @@ def test_init_rejects_bad_arguments_without_touching_the_gpu(lib):
     c = L.default_config(lib2, nc=2, nv=3, naux=5)
     with pytest.raises(L.DcsdError):
         L.Context(c, 0, 0, 0, lib2)      # NULL B and F
-    for bad in (dict(guard_iters=-1), dict(adjoint=2), dict(ladder_cache=2)):
+    for bad in (dict(guard_iters=-1), dict(adjoint=2), dict(ladder_cache=3)):
         c = L.default_config(lib2, nc=2, nv=3, naux=5)
         for k, v in bad.items():
             setattr(c, k, v)
