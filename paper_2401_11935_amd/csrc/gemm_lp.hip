@@ -629,6 +629,16 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
   if (q.ks <= 1) {
     a.C = q.C; a.ldc = q.ldc; a.c_nc = q.c_nc ? 1 : 0;
     a.kchunk = q.K;
+    // BF16 products with at least one 256 x 256 tile per compute unit (the ring and delta
+    // products of the residual): 256 x 256 tiles on eight waves
+    const int64_t t256 = ((q.M + 255) / 256) * ((q.N + 255) / 256);
+    if (dl && sizeof(T) == 2 && t256 >= 256 && q.K >= 1024) {
+      a.tiles_n = (q.N + 255) / 256;
+      hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_F64, 256>), dim3((unsigned)t256),
+                         dim3(64 * DlTile<256>::NW), 0, s, a);
+      DCSD_CHECK_LAUNCH();
+      return;
+    }
     if (dl)
       hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_F64>), dim3((unsigned)tiles), dim3(NT),
                          0, s, a);

@@ -61,7 +61,7 @@ def test_round_to_bf16_is_nearest_even():
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (128, 128, 64), (129, 257, 31), (300, 70, 1000),
-                                   (513, 200, 77), (64, 64, 4100)])
+                                   (513, 200, 77), (64, 64, 4100), (4100, 4200, 1032)])
 def test_lowp_gemm_within_fp32_summation_bound(precision, M, N, K):
     import torch
     from paper_2401_11935_amd import libdcsd as L
