@@ -364,17 +364,6 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   const int64_t vu2 = (int64_t)vu * vu;
   Tstack = alloc(rows_all * vu2);
   V2 = alloc((int64_t)lb * lb * vu2);
-  // FP64 ladder integral cache (ladder_cache = 2): one V2-sized slot per orbital-pair batch,
-  // left off when the memory is not available
-  if (cfg.ladder_cache == 2) {
-    const int64_t nblk = (n + lb - 1) / lb;
-    lcache64_slot = (int64_t)lb * lb * vu2;
-    try {
-      lcache64 = (double*)alloc_raw((size_t)(nblk * (nblk + 1) / 2 * lcache64_slot) * sizeof(double));
-    } catch (const std::bad_alloc&) {
-      lcache64 = nullptr;
-    }
-  }
   Rb = alloc(rows_all * (int64_t)lb * lb);
   Rp = alloc(rows_main * n2);
   Smt = alloc(rows_main * (int64_t)n * std::max(vs[0], vs[1]));
@@ -392,19 +381,6 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     // padding of both operands is zeroed once here and nothing writes it afterwards
     fill((double*)TstackL, 0.0, (rows_all * kp * es + 7) / 8, s);
     fill((double*)V2L, 0.0, ((int64_t)lb * lb * kp * es + 7) / 8, s);
-    // ladder integral cache: one V2L-sized slot per orbital-pair batch (p-block <= q-block),
-    // row padding zeroed like V2L; left off when the memory is not available
-    if (cfg.ladder_cache) {
-      const int64_t nblk = (n + lb - 1) / lb;
-      lcache_slot = (int64_t)lb * lb * kp;
-      const int64_t cbytes = nblk * (nblk + 1) / 2 * lcache_slot * es;
-      try {
-        lcache = alloc_raw((size_t)cbytes);
-        fill((double*)lcache, 0.0, (cbytes + 7) / 8, s);
-      } catch (const std::bad_alloc&) {
-        lcache = nullptr;
-      }
-    }
     const int64_t lpm = std::max({tov, sfr, sfc});
     // the ring operands, and the dressed-integral operands of the delta form (rows of
     // length naux, or tov for the singles intermediate)
@@ -471,6 +447,49 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   reg(const_cast<double*>(F), n2, false);
   build_constants(true);
   if (cfg.adjoint) adj_reserve();
+  alloc_ladder_caches();
+}
+
+// Ladder integral caches (cfg.ladder_cache), allocated after everything else: one slot per
+// orbital-pair batch (p-block <= q-block), the low-precision slots of V2L's size with the
+// row padding zeroed like V2L, the FP64 slots of V2's size.  A cache is left off when it
+// would leave less than max(8 GiB, 5%) of the device memory free.
+void Ctx::alloc_ladder_caches() {
+  if (!cfg.ladder_cache) return;
+  const int64_t nblk = (n + lb - 1) / lb, nbat = nblk * (nblk + 1) / 2;
+  auto fits = [&](size_t b) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return fr > b && fr - b >= std::max<size_t>((size_t)8 << 30, tot / 20);
+  };
+  if (cfg.precision != DCSD_PREC_FP64) {
+    const int64_t es = (int64_t)lp_size(cfg.precision);
+    lcache_slot = (int64_t)lb * lb * kp;
+    const size_t cbytes = (size_t)(nbat * lcache_slot * es);
+    if (fits(cbytes)) {
+      try {
+        lcache = alloc_raw(cbytes);
+        fill((double*)lcache, 0.0, (int64_t)((cbytes + 7) / 8), s);
+      } catch (const std::bad_alloc&) {
+        lcache = nullptr;
+      }
+    }
+  }
+  if (cfg.ladder_cache == 2) {
+    lcache64_slot = (int64_t)lb * lb * vu * vu;
+    const size_t cbytes = (size_t)(nbat * lcache64_slot) * sizeof(double);
+    if (fits(cbytes)) {
+      try {
+        lcache64 = (double*)alloc_raw(cbytes);
+      } catch (const std::bad_alloc&) {
+        lcache64 = nullptr;
+      }
+    }
+  }
+  DCSD_HIP(hipStreamSynchronize(s));
 }
 
 // Quantities of Phi_A built from (B, F) once per context; re-run under a tape
