@@ -99,25 +99,65 @@ def triples_energy(ham: Hamiltonian, t1: np.ndarray, t2: np.ndarray) -> dict:
     return {"E_T4": e4, "E_ST5": e5, "E_DT": edt, "E_T": e4 + e5 + edt}
 
 
+class _DirectIntegrals:
+    """The integral slices one occupied triple needs, formed on demand from the DF
+    factors (for inputs whose dense <ei||bc> array would not fit in host memory)."""
+
+    def __init__(self, ham: Hamiltonian):
+        self.ham = ham
+        O, V = ham.O, ham.V
+        f_oo, f_vv = ham.fock(O, O), ham.fock(V, V)
+        self.fov, self.fo, self.fv = ham.fock(O, V), np.diag(f_oo).copy(), np.diag(f_vv).copy()
+
+    def vovv_slab(self, p):   # <ep||bc> as [e][b][c]
+        ham = self.ham
+        return ham.asym(ham.V, ham.sub(ham.O, p), ham.V, ham.V)[:, 0]
+
+    def ovoo_pair(self, q, r):   # <ma||qr> as [m][a]
+        ham = self.ham
+        return ham.asym(ham.O, ham.V, ham.sub(ham.O, q), ham.sub(ham.O, r))[:, :, 0, 0]
+
+    def oovv_pair(self, q, r):   # <qr||bc> as [b][c]
+        ham = self.ham
+        return ham.asym(ham.sub(ham.O, q), ham.sub(ham.O, r), ham.V, ham.V)[0, 0]
+
+
+class _DenseIntegrals:
+    def __init__(self, g: dict):
+        self.g = g
+        self.fov, self.fo, self.fv = g["fov"], g["fo"], g["fv"]
+
+    def vovv_slab(self, p):
+        return self.g["vovv"][:, p]
+
+    def ovoo_pair(self, q, r):
+        return self.g["ovoo"][:, :, q, r]
+
+    def oovv_pair(self, q, r):
+        return self.g["oovv"][q, r]
+
+
 def triple_contribution(ham: Hamiltonian, t1: np.ndarray, t2: np.ndarray, i: int, j: int, k: int,
-                        ints: dict | None = None) -> float:
+                        ints: dict | None = None, direct: bool = False) -> float:
     """Contribution of one occupied triple i < j < k, summed over all virtual
     (a, b, c): 1/6 sum_abc N^c (N^c + N^d) / D.  Each step is one matrix
     product or elementwise operation for the three orderings of (i, j, k), so
-    that large inputs can be sampled triple by triple."""
-    g = ints or _integrals(ham)
+    that large inputs can be sampled triple by triple; with direct=True only
+    the integrals of i, j and k are formed."""
+    src = _DirectIntegrals(ham) if direct else _DenseIntegrals(ints or _integrals(ham))
+    g = {"fov": src.fov, "fo": src.fo, "fv": src.fv}
     nv = t2.shape[2]
 
     def z(p, q, r):   # sum_e t_qr^ae <ep||bc> - sum_m t_pm^bc <ma||qr>, as [a][b][c]
-        xa = t2[q, r] @ g["vovv"][:, p].reshape(nv, nv * nv)
-        ya = g["ovoo"][:, :, q, r].T @ t2[p].reshape(-1, nv * nv)
+        xa = t2[q, r] @ src.vovv_slab(p).reshape(nv, nv * nv)
+        ya = src.ovoo_pair(q, r).T @ t2[p].reshape(-1, nv * nv)
         return (xa - ya).reshape(nv, nv, nv)
 
     zt = z(i, j, k) - z(j, i, k) - z(k, j, i)
     ncv = zt - zt.transpose(1, 0, 2) - zt.transpose(2, 1, 0)
 
     def s(p, q, r):   # t_p^a <qr||bc> + f_pa t_qr^bc, as [a][b][c]
-        return g["oovv"][q, r][None] * t1[p][:, None, None] + t2[q, r][None] * g["fov"][p][:, None, None]
+        return src.oovv_pair(q, r)[None] * t1[p][:, None, None] + t2[q, r][None] * g["fov"][p][:, None, None]
 
     st = s(i, j, k) - s(j, i, k) - s(k, j, i)
     ndv = st - st.transpose(1, 0, 2) - st.transpose(2, 1, 0)

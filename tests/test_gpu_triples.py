@@ -103,3 +103,34 @@ def test_triples_rejects_two_determinant_methods():
         p.ctx.triples(Td.data_ptr())
     p.close()
     assert e.value.status == L.DCSD_ERR_ARG
+
+
+def test_triples_at_the_bench_shape_sampled_by_triple():
+    """nc=8, nv=200, naux=600 with weak integrals (the shape bench.py times): the
+    per-triple contributions of eight seeded occupied triples, two of each spin
+    pattern (alpha^3, alpha^2 beta, alpha beta^2, beta^3), against the oracle's
+    triple-by-triple form with only those orbitals' integrals; and the total is the
+    sum of the per-triple contributions."""
+    from oracle.highspin import HighSpinHamiltonian
+    from oracle.triples import triple_contribution
+    cfg = synth.MEDIUM_WEAK
+    nc, nv = cfg.nc, cfg.nv
+    say("triples at the bench shape")
+    B, F = synth.make_config_inputs(cfg)
+    T = synth.hs_random_amplitudes(nc, nv, 91, 0.01)
+    e, contrib = _gpu_triples(B, F, nc, "hs-dcsd", T)
+    trips = list(itertools.combinations(range(2 * nc + 2), 3))
+    assert e["triples"] == len(trips) == contrib.size
+    assert abs(contrib.sum() - e["E_T"]) <= 1e-12 * max(1.0, abs(e["E_T"]))
+    oa = nc + 2
+    rng = np.random.default_rng(17)
+    picks = []
+    for nbeta in range(4):
+        cands = [q for q, t in enumerate(trips) if sum(x >= oa for x in t) == nbeta]
+        picks += [int(x) for x in rng.choice(cands, 2, replace=False)]
+    ham = HighSpinHamiltonian(B, F, nc)
+    t1, t2 = ham.to_so(T)
+    for q in picks:
+        ref = triple_contribution(ham, t1, t2, *trips[q], direct=True)
+        say(f"  triple {trips[q]}: GPU {contrib[q]:.15e} oracle {ref:.15e}")
+        assert _close(contrib[q], ref), (trips[q], contrib[q], ref)

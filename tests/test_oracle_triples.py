@@ -103,3 +103,9 @@ def test_triple_by_triple_sum_equals_dense_sum():
     dense = triples_energy(model.ham, t1, t2)["E_T"]
     assert abs(triples_by_triple(model.ham, t1, t2) - dense) <= 1e-14 + 1e-12 * abs(dense)
     assert abs(dense) > 1e-6
+    # the direct form (integrals of the three orbitals only) gives the same per-triple sums
+    from oracle.triples import triple_contribution
+    for ijk in ((0, 1, 2), (1, 4, 5), (3, 4, 5), (0, 2, 5)):
+        a = triple_contribution(model.ham, t1, t2, *ijk)
+        b = triple_contribution(model.ham, t1, t2, *ijk, direct=True)
+        assert abs(a - b) <= 1e-15 + 1e-12 * abs(a)
