@@ -118,6 +118,12 @@ def parse():
     ap.add_argument("--no-fr", action="store_true", help="skip timing the fixed-reference residuals")
     ap.add_argument("--no-weak", action="store_true", help="skip the weak-integral solves")
     ap.add_argument("--no-highspin", action="store_true", help="skip the high-spin residual, solve and (T)")
+    ap.add_argument("--largest-solves", action="store_true",
+                    help="with --largest: FP64 and BF16 solves at the largest shape with weak integrals (minutes)")
+    ap.add_argument("--largest-tol", type=float, default=1e-8, help="convergence of the largest-shape solves")
+    ap.add_argument("--weak-diis", type=int, default=16,
+                    help="DIIS subspace of the weak-integral solves (the library default, 8, suits the small "
+                         "strongly correlated systems; these larger ones converge in fewer iterations with 16)")
     ap.add_argument("--no-cache64", action="store_true",
                     help="skip the weak-integral solves with the FP64 ladder integrals kept (ladder_cache = 2)")
     ap.add_argument("--largest", action="store_true",
@@ -283,11 +289,11 @@ def weak_integral_run(L, torch, args, stream, alg):
     Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
     del B
     base = dict(nc=cfgw.nc, nv=cfgw.nv, naux=cfgw.naux, method=args.method, ladder_block=args.ladder_block,
-                tol_residual=args.tol, max_iter=args.weak_max_iter)
+                tol_residual=args.tol, max_iter=args.weak_max_iter, diis_dim=args.weak_diis)
     out = {"config": {"workload": f"2D-{args.method.upper()} nc={cfgw.nc} open-shell=2 nv={cfgw.nv} "
                                   f"naux={cfgw.naux} seed={cfgw.seed}, DF factors N(0, sigma^2) with "
                                   f"naux sigma^2 = {synth.WEAK_EXCHANGE} Eh", "sigma": cfgw.sigma,
-                      "tol_residual": args.tol, "preconditioner": "orbital-energy denominators, DIIS 8"},
+                      "tol_residual": args.tol, "preconditioner": f"orbital-energy denominators, DIIS {args.weak_diis}"},
            "reference": "the converged FP64 solve of the library (validated against the oracle per residual "
                         "at this size and by converged parity at nc=8 nv=200)"}
     solves = {}
@@ -536,6 +542,37 @@ def largest_config_run(L, torch, args, stream):
     except L.DcsdError as e:
         out["adjoint"] = {"reserved": False, "status": L.STATUS_NAMES[e.status], "message": str(e),
                           "device_total_gib": torch.cuda.mem_get_info()[1] / 2 ** 30}
+    if args.largest_solves:
+        del Bd, Fd
+        torch.cuda.empty_cache()
+        out["weak_solves"] = largest_weak_solves(L, torch, args, stream)
+    return out
+
+
+def largest_weak_solves(L, torch, args, stream):
+    """FP64 and BF16 solves from T = 0 at the largest shape with weak integrals
+    (dcsd_synth.LARGEST_WEAK), side by side: iterations, FP64 refreshes, solve times
+    and the energy difference (ladder integral caches as dcsd_init allots them)."""
+    import dcsd_synth as synth
+    cw = synth.LARGEST_WEAK
+    B, F = synth.make_config_inputs(cw)
+    dev = torch.device("cuda:0")
+    Bd, Fd = torch.from_numpy(B).to(dev), torch.from_numpy(F).to(dev)
+    del B
+    base = dict(nc=cw.nc, nv=cw.nv, naux=cw.naux, method=args.method, tol_residual=args.largest_tol,
+                max_iter=args.weak_max_iter, diis_dim=args.weak_diis)
+    out = {"config": f"2D-{args.method.upper()} nc={cw.nc} nv={cw.nv} naux={cw.naux} seed={cw.seed}, weak integrals "
+                     f"(naux sigma^2 = {synth.WEAK_EXCHANGE} Eh)", "tol_residual": args.largest_tol}
+    for prec in ("fp64", "bf16"):
+        rep, T, recs, elapsed = timed_solve(L, torch, L.default_config(precision=prec, **base), Bd, Fd, stream,
+                                            f"largest weak {prec}")
+        out[prec] = {"status": rep["status"], "iterations": rep["iterations"],
+                     "fp64_evaluations": sum(1 for r in recs if r["fp64"]), "solve_s": elapsed,
+                     "E_S": rep["E_S"], "E_T": rep["E_T"], "res_max": rep["res_max"]}
+        del T
+    out["bf16"]["abs_dE_S_vs_fp64"] = abs(out["bf16"]["E_S"] - out["fp64"]["E_S"])
+    out["bf16"]["abs_dE_T_vs_fp64"] = abs(out["bf16"]["E_T"] - out["fp64"]["E_T"])
+    out["bf16"]["speedup_solve_vs_fp64"] = out["fp64"]["solve_s"] / out["bf16"]["solve_s"]
     return out
 
 
