@@ -381,30 +381,21 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
     // padding of both operands is zeroed once here and nothing writes it afterwards
     fill((double*)TstackL, 0.0, (rows_all * kp * es + 7) / 8, s);
     fill((double*)V2L, 0.0, ((int64_t)lb * lb * kp * es + 7) / 8, s);
+    // the ring operands (the rounding buffers lpA, lpB are allocated at the end of init,
+    // sized also for the dressed-integral sites if those get their records)
     const int64_t lpm = std::max({tov, sfr, sfc});
-    // the ring operands, and the dressed-integral operands of the delta form (rows of
-    // length naux, or tov for the singles intermediate)
-    lp_cap = std::max({lpm * lp_ld(lpm), tov * lp_ld(NA), n2 * lp_ld(NA), NA * lp_ld(tov), too2 * lp_ld(NA)});
-    lpA = lp_alloc(lp_cap);
-    lpB = lp_alloc(lp_cap);
+    lp_cap = lpm * lp_ld(lpm);
     lwork_cap = std::max<int64_t>(split_cap * rows_all * (int64_t)lb * lb, (int64_t)1 << 22);
     lwork = (float*)alloc((lwork_cap + 1) / 2);
     TstackR = alloc(rows_all * vu2);
     RpR = alloc(rows_main * n2);
-    // ring sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 = spin-flip I T (CCSD); 4, 5 = spin-flip rings;
-    // dressed-integral sites (delta form only): 6 = (ai|bj)~, 7 = (kc|bj)~, 8, 9 = (kj|pq)~ per spin,
-    // 10 = the singles intermediate Z
-    const int64_t sf2 = std::max(sfr, sfc) * std::max(sfr, sfc);
-    const int64_t szA[Ctx::kSites] = {0, tov * tov, 0, 0, sf2, sf2, NA * tov, NA * tov, NA * too2, NA * too2, NA * tov};
-    const int64_t szB[Ctx::kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2, NA * tov, NA * tov, NA * n2, NA * n2,
-                                      tov * tov};
-    const int64_t szP[Ctx::kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2, tov * tov, tov * tov, too2 * n2,
-                                      too2 * n2, NA * tov};
-    for (int k = 0; k < Ctx::kSites; ++k) {
+    // ring sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 = spin-flip I T (CCSD); 4, 5 = spin-flip
+    // rings (the dressed-integral sites 6-10 are allocated at the end of init, when they fit)
+    for (int k = 0; k < 6; ++k) {
       if ((k == 2 || k == 3) && !method_cc(cfg.method)) continue;
-      if (szA[k]) site[k].Ar = alloc(szA[k]);
-      site[k].Br = alloc(szB[k]);
-      site[k].Pr = alloc(szP[k]);
+      if (site_size(k, 0)) site[k].Ar = alloc(site_size(k, 0));
+      site[k].Br = alloc(site_size(k, 1));
+      site[k].Pr = alloc(site_size(k, 2));
     }
   }
   gws_cap = std::max<int64_t>(1 << 22, 64 * (int64_t)v * v);
@@ -450,13 +441,13 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   alloc_ladder_caches();
 }
 
-// Ladder integral caches (cfg.ladder_cache), allocated after everything else: one slot per
-// orbital-pair batch (p-block <= q-block), the low-precision slots of V2L's size with the
-// row padding zeroed like V2L, the FP64 slots of V2's size.  A cache is left off when it
-// would leave less than max(8 GiB, 5%) of the device memory free.
+// Optional memory, allocated after everything else and only where it leaves max(8 GiB, 5%)
+// of the device memory free: in low precision the records of the dressed-integral delta
+// sites (with the rounding buffers, which are allocated here in any case), then the ladder
+// integral caches (cfg.ladder_cache): one slot per orbital-pair batch (p-block <= q-block),
+// the low-precision slots of V2L's size with the row padding zeroed like V2L, the FP64
+// slots of V2's size.
 void Ctx::alloc_ladder_caches() {
-  if (!cfg.ladder_cache) return;
-  const int64_t nblk = (n + lb - 1) / lb, nbat = nblk * (nblk + 1) / 2;
   auto fits = [&](size_t b) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
@@ -465,6 +456,31 @@ void Ctx::alloc_ladder_caches() {
     }
     return fr > b && fr - b >= std::max<size_t>((size_t)8 << 30, tot / 20);
   };
+  if (cfg.precision != DCSD_PREC_FP64) {
+    // the dressed-integral delta sites 6-10 (records of their changing operands and FP64
+    // products) and the rounding buffers, which those sites' operands enlarge; without the
+    // records those products stay FP64 in every evaluation
+    const int64_t es = (int64_t)lp_size(cfg.precision), NA = naux;
+    const int64_t cap6 = std::max({lp_cap, tov * lp_ld(NA), n2 * lp_ld(NA), NA * lp_ld(tov), too2 * lp_ld(NA)});
+    size_t rec = 0;
+    for (int k = 6; k < kSites; ++k) rec += (size_t)(site_size(k, 0) + site_size(k, 1) + site_size(k, 2)) * 8;
+    const bool with6 = fits(rec + (size_t)(2 * cap6 * es));
+    if (with6) {
+      lp_cap = cap6;
+      for (int k = 6; k < kSites; ++k) {
+        site[k].Ar = alloc(site_size(k, 0));
+        site[k].Br = alloc(site_size(k, 1));
+        site[k].Pr = alloc(site_size(k, 2));
+      }
+    }
+    lpA = alloc((lp_cap * es + 7) / 8);
+    lpB = alloc((lp_cap * es + 7) / 8);
+  }
+  if (!cfg.ladder_cache) {
+    DCSD_HIP(hipStreamSynchronize(s));
+    return;
+  }
+  const int64_t nblk = (n + lb - 1) / lb, nbat = nblk * (nblk + 1) / 2;
   if (cfg.precision != DCSD_PREC_FP64) {
     const int64_t es = (int64_t)lp_size(cfg.precision);
     lcache_slot = (int64_t)lb * lb * kp;
@@ -602,6 +618,20 @@ void Ctx::build_constants(bool full) {
     e_ref = e;
   }
   DCSD_HIP(hipStreamSynchronize(s));
+}
+
+// Doubles of a delta site's records: which = 0 the changing A operand (0: A constant),
+// 1 the B operand, 2 the product.  Sites: 0 = I T_sc^T, 1 = T_sc W_sc (2ov x 2ov); 2, 3 =
+// spin-flip I T (CCSD); 4, 5 = spin-flip rings; dressed integrals (delta form only): 6 =
+// (ai|bj)~, 7 = (kc|bj)~, 8, 9 = (kj|pq)~ per spin, 10 = the singles intermediate Z.
+int64_t Ctx::site_size(int k, int which) const {
+  const int64_t NA = naux, sf2 = std::max(sfr, sfc) * std::max(sfr, sfc);
+  const int64_t szA[kSites] = {0, tov * tov, 0, 0, sf2, sf2, NA * tov, NA * tov, NA * too2, NA * too2, NA * tov};
+  const int64_t szB[kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2, NA * tov, NA * tov, NA * n2, NA * n2,
+                               tov * tov};
+  const int64_t szP[kSites] = {tov * tov, tov * tov, sf2, sf2, sf2, sf2, tov * tov, tov * tov, too2 * n2, too2 * n2,
+                               NA * tov};
+  return which == 0 ? szA[k] : (which == 1 ? szB[k] : szP[k]);
 }
 
 // ---------------------------------------------------------------------------
