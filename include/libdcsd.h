@@ -149,8 +149,12 @@ typedef struct {
                              also the FP64 integrals after the first FP64
                              evaluation (129 GB at nc=12 nv=400), which serves
                              FP64 solves and the FP64 refreshes of the mixed
-                             solver.  dcsd_init leaves a cache off when its memory
-                             cannot be allocated.  0: assemble every time        */
+                             solver.  dcsd_init allocates the caches after all
+                             other memory and leaves a cache off when it would
+                             leave less than max(8 GiB, 5%) of the device free
+                             (the records of the dressed-integral delta products,
+                             allocated just before them, follow the same rule).
+                             0: assemble every time                              */
 } dcsd_config;
 
 typedef struct {
