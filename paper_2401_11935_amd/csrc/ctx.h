@@ -209,7 +209,7 @@ struct Ctx {
   void release();
 
   void init(const dcsd_config& c, const double* B, const double* F, hipStream_t stream);
-  void alloc_ladder_caches();
+  void alloc_optional();
   int64_t site_size(int k, int which) const;
   // prec < 0: the configured precision; DCSD_PREC_FP64 forces an FP64 evaluation.
   // mode: PLAIN, RECORD (FP64 only) or DELTA (low precision with a recorded reference).

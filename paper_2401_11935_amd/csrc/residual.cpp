@@ -438,7 +438,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
   reg(const_cast<double*>(F), n2, false);
   build_constants(true);
   if (cfg.adjoint) adj_reserve();
-  alloc_ladder_caches();
+  alloc_optional();
 }
 
 // Optional memory, allocated after everything else and only where it leaves max(8 GiB, 5%)
@@ -447,7 +447,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
 // integral caches (cfg.ladder_cache): one slot per orbital-pair batch (p-block <= q-block),
 // the low-precision slots of V2L's size with the row padding zeroed like V2L, the FP64
 // slots of V2's size.
-void Ctx::alloc_ladder_caches() {
+void Ctx::alloc_optional() {
   auto fits = [&](size_t b) {
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
