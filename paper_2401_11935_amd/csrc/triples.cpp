@@ -56,19 +56,23 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
   const int64_t nV2 = nV * nV, nV3 = nV2 * nV;
   const int64_t ntrip = nO * (nO - 1) * (nO - 2) / 6;
   if (!tri.ready) {
-    tri.t1so = alloc(nO * nV);
-    tri.fov = alloc(nO * nV);
-    tri.fo = alloc(nO);
-    tri.fv = alloc(nV);
-    tri.t2so = alloc(nO * nO * nV2);
-    tri.oovv = alloc(nO * nO * nV2);
-    tri.Q = alloc(nO * nO * nV * nO);
-    tri.I = alloc(nO * d.slab_rows() * nV2);
-    tri.Aop = alloc(3 * nV * (int64_t)n);
-    tri.Zt = alloc(nV3);
-    tri.ZtT = alloc(nV3);
-    tri.part = alloc(3 * TRI_PART_BLOCKS);
-    tri.out = alloc(std::max<int64_t>(4 * ntrip, 4));
+    // (a call that failed part-way, e.g. out of memory, keeps what it had allocated for the next)
+    auto once = [&](double*& p, int64_t count) {
+      if (!p) p = alloc(count);
+    };
+    once(tri.t1so, nO * nV);
+    once(tri.fov, nO * nV);
+    once(tri.fo, nO);
+    once(tri.fv, nV);
+    once(tri.t2so, nO * nO * nV2);
+    once(tri.oovv, nO * nO * nV2);
+    once(tri.Q, nO * nO * nV * nO);
+    once(tri.I, nO * d.slab_rows() * nV2);
+    once(tri.Aop, 3 * nV * (int64_t)n);
+    once(tri.Zt, nV3);
+    once(tri.ZtT, nV3);
+    once(tri.part, 3 * TRI_PART_BLOCKS);
+    once(tri.out, std::max<int64_t>(4 * ntrip, 4));
     // spatial factor blocks: U x U, occupied x U, occupied x occupied, U x occupied
     const double* Bsp = Bs[0];
     const int64_t ob = d.ob;
