@@ -221,7 +221,7 @@ struct Ctx {
   struct TriBuf {
     bool ready = false;
     double *t1so = nullptr, *t2so = nullptr, *fo = nullptr, *fv = nullptr, *fov = nullptr;
-    double *I = nullptr, *oovv = nullptr, *Q = nullptr, *Zt = nullptr, *ZtT = nullptr;
+    double *I = nullptr, *oovv = nullptr, *Q = nullptr, *Zt = nullptr;
     double *part = nullptr, *out = nullptr, *Aop = nullptr;
   } tri;
   void triples(const double* T, dcsd_triples_energy* out, double* contrib);

@@ -160,7 +160,6 @@ struct TriDims {
   __host__ __device__ int row_e(int E) const { return E + (E >= va ? oa : 0); }
   __host__ __device__ int row_m(int M) const { return va + M + (M >= oa ? vb : 0); }
 };
-constexpr int TRI_PART_BLOCKS = 1024;  // partial sums per triple in tri_energy
 // t1so[nO][nV], t2so[nO][nO][nV][nV] (antisymmetric), Fock diagonals fo[nO], fv[nV] and f_ov[nO][nV]
 void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov, const double* T, const double* fa,
                 const double* fb, const SpinLayout& L, const TriDims& d, hipStream_t s);
@@ -174,12 +173,12 @@ void tri_operand_a(double* A, const double* t2so, const double* Q, int i, int j,
 void tri_assemble_oovv(double* O, const double* S2, const TriDims& d, hipStream_t s);
 // Q[Y][Z][A][M] = <MA||YZ> from S3[(m,y)][(aU,z)] = (my|az)
 void tri_assemble_ovoo(double* Q, const double* S3, const TriDims& d, hipStream_t s);
-// dst[a][b][c] = src[c][b][a], n x n x n
-void tri_transpose(double* dst, const double* src, int n, hipStream_t s);
-// out4 = {E4, E5, EDT, total} of the occupied triple i < j < k (device, 4 doubles); part:
-// 3 * TRI_PART_BLOCKS doubles of work space
-void tri_energy(double* out4, double* part, const double* Zt, const double* ZtT, const double* t1so,
-                const double* t2so, const double* oovv, const double* fo, const double* fv, const double* fov, int i,
-                int j, int k, const TriDims& d, hipStream_t s);
+// workgroups of tri_energy (its work space is 3 doubles per workgroup)
+int64_t tri_energy_blocks(const TriDims& d);
+// out4 = {E4, E5, EDT, total} of the occupied triple i < j < k (device, 4 doubles) from
+// Zt[a][bc] = P(i/jk) of the GEMM sums; part: 3 * tri_energy_blocks(d) doubles
+void tri_energy(double* out4, double* part, const double* Zt, const double* t1so, const double* t2so,
+                const double* oovv, const double* fo, const double* fv, const double* fov, int i, int j, int k,
+                const TriDims& d, hipStream_t s);
 
 }  // namespace dcsd

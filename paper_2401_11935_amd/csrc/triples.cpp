@@ -15,9 +15,9 @@
 //      Zt[a][bc] = P(i/jk) [sum_e t_jk^ae <ei||bc> - sum_m t_im^bc <ma||jk>]
 //    as at most six FP64 GEMMs (three orders of (i, j, k) times the spins of
 //    a that spin conservation allows) accumulated into one n_vir x n_vir^2
-//    array, its 0 <-> 2 transpose, and one pass over a < b < c that forms
-//    N^c = P(a/bc) Zt, the disconnected numerator and the denominator and
-//    reduces the three energy parts in a fixed order.
+//    array, and one pass over a < b < c, tiled through LDS so that Zt[c][b][a]
+//    is read along a, that forms N^c = P(a/bc) Zt, the disconnected numerator
+//    and the denominator and reduces the three energy parts in a fixed order.
 #include <vector>
 
 #include "ops.h"
@@ -70,8 +70,7 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
     once(tri.I, nO * d.slab_rows() * nV2);
     once(tri.Aop, 3 * nV * (int64_t)n);
     once(tri.Zt, nV3);
-    once(tri.ZtT, nV3);
-    once(tri.part, 3 * TRI_PART_BLOCKS);
+    once(tri.part, 3 * tri_energy_blocks(d));
     once(tri.out, std::max<int64_t>(4 * ntrip, 4));
     // spatial factor blocks: U x U, occupied x U, occupied x occupied, U x occupied
     const double* Bsp = Bs[0];
@@ -135,9 +134,8 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
         }
         for (int sa = 0; sa < 2; ++sa)
           if (!written[sa]) fill(tri.Zt + off_v[sa] * nV2, 0.0, nvs[sa] * nV2, s);
-        tri_transpose(tri.ZtT, tri.Zt, (int)nV, s);
-        tri_energy(tri.out + 4 * t, tri.part, tri.Zt, tri.ZtT, tri.t1so, tri.t2so, tri.oovv, tri.fo, tri.fv, tri.fov, i,
-                   j, k, d, s);
+        tri_energy(tri.out + 4 * t, tri.part, tri.Zt, tri.t1so, tri.t2so, tri.oovv, tri.fo, tri.fv, tri.fov, i, j, k,
+                   d, s);
       }
   std::vector<double> h((size_t)std::max<int64_t>(4 * ntrip, 4), 0.0);
   if (ntrip > 0)

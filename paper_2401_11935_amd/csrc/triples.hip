@@ -1,7 +1,6 @@
 // Device kernels of the perturbative triples correction of the M_s = 1
 // determinant: spin-orbital unpacking of the amplitudes, integral assembly from
-// spatial DF products, the 0 <-> 2 axis transpose and the per-triple energy
-// reduction.  The contractions themselves are FP64 MFMA GEMMs (triples.cpp).
+// spatial DF products and the per-triple energy reduction.  The contractions themselves are FP64 MFMA GEMMs (triples.cpp).
 //
 // Spin-orbital order: occupied [alpha occupied (oa) | beta occupied (ob)],
 // virtual [alpha virtual (va) | beta virtual (vb)].  For the M_s = 1
@@ -17,6 +16,7 @@ namespace dcsd {
 namespace {
 
 constexpr int TRI_THREADS = 256;
+constexpr int TRI_BCHUNK = 16;  // values of b per workgroup of the energy pass
 
 inline unsigned tri_blocks(int64_t total, int threads, int64_t cap = 1 << 20) {
   int64_t b = (total + threads - 1) / threads;
@@ -132,30 +132,10 @@ __global__ void tri_ovoo(double* Q, const double* S3, TriDims d) {
   }
 }
 
-// dst[a][b][c] = src[c][b][a] for an n x n x n array: one (a, c) tile of 32 x 32 per
-// workgroup and b, staged through LDS so that both sides are read and written along
-// their contiguous index.
-__global__ void tri_transpose02(double* dst, const double* src, int n) {
-  __shared__ double tile[32][33];
-  const int64_t b = blockIdx.z;
-  const int a0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
-  const int64_t nn = (int64_t)n * n;
-  // read src[c][b][a] for c in the c-tile (rows) and a in the a-tile (contiguous)
-  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
-    const int c = c0 + r, a = a0 + threadIdx.x;
-    if (c < n && a < n) tile[r][threadIdx.x] = src[(int64_t)c * nn + b * n + a];
-  }
-  __syncthreads();
-  for (int r = threadIdx.y; r < 32; r += blockDim.y) {
-    const int a = a0 + r, c = c0 + threadIdx.x;
-    if (a < n && c < n) dst[(int64_t)a * nn + b * n + c] = tile[threadIdx.x][r];
-  }
-}
-
 // A[p][a][kk] (kk < n) of the three orders p of (i, j, k) -> (x; y z) = (i; j k), (j; i k),
 // (k; j i): for a of spin sa and s = s(y) + s(z) - s(a), the columns are t_yz^{a e} over the
 // virtuals e of spin s, then -<m a||y z> over the occupied m of spin s (v_s + o_s = n columns),
-// matching rows tri_row_e(e), tri_row_m(m) of slab x; zero where no spin s exists.
+// matching the slab rows row_e(e), row_m(m) of x; zero where no spin s exists.
 __global__ void tri_build_a(double* A, const double* t2so, const double* Q, int i, int j, int k, TriDims d) {
   const int64_t nO = d.nO(), nV = d.nV(), n = d.n;
   const int64_t total = 3 * nV * n;
@@ -176,11 +156,13 @@ __global__ void tri_build_a(double* A, const double* t2so, const double* Q, int 
   }
 }
 
+// sum over a workgroup of TRI_THREADS threads (one- or two-dimensional), fixed order
 __device__ double tri_block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
+  const int t = threadIdx.y * blockDim.x + threadIdx.x;
+  sh[t] = v;
   __syncthreads();
   for (int w = TRI_THREADS / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    if (t < w) sh[t] += sh[t + w];
     __syncthreads();
   }
   const double r = sh[0];
@@ -188,27 +170,39 @@ __device__ double tri_block_sum(double v, double* sh) {
   return r;
 }
 
-// Per-block partial sums over a < b < c of one occupied triple (i, j, k):
-// w = N^c / D, parts w N^c, w N^d1, w N^d2 with
-//   N^c = Zt[a][b][c] - Zt[b][a][c] - Zt[c][b][a]           (Zt = P(i/jk) of the GEMM sums)
+// Partial sums of one occupied triple (i, j, k) over a < b < c: w = N^c / D, parts w N^c,
+// w N^d1, w N^d2 with
+//   N^c = Zt[a][b][c] - Zt[b][a][c] - Zt[c][b][a]          (Zt = P(i/jk) of the GEMM sums)
 //   N^d = P(i/jk) P(a/bc) [t_i^a <jk||bc> + f_ia t_jk^bc]
+// One workgroup per (32 c) x (32 a) tile and chunk of TRI_BCHUNK values of b (grid x, y, z),
+// 32 x 8 threads: for each b the tile Zt[c][b][a] (rows c, contiguous a) goes through LDS,
+// so that all three reads run along their contiguous index.  part: three doubles per
+// workgroup, in grid order (zeros where the tile holds no a < b < c).
 __global__ void __launch_bounds__(TRI_THREADS)
-tri_energy_partial(double* part, const double* Zt, const double* ZtT, const double* t1so, const double* t2so,
-                   const double* oovv, const double* fo, const double* fv, const double* fov, int i, int j, int k,
-                   TriDims d) {
+tri_energy_tiled(double* part, const double* Zt, const double* t1so, const double* t2so, const double* oovv,
+                 const double* fo, const double* fv, const double* fov, int i, int j, int k, TriDims d) {
+  __shared__ double s3[32][33];
   __shared__ double sh[TRI_THREADS];
   const int64_t nO = d.nO(), nV = d.nV(), nV2 = nV * nV;
+  const int64_t a0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;
   const double fijk = fo[i] + fo[j] + fo[k];
   const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
   const double sg[3] = {1.0, -1.0, -1.0};
   double e4 = 0.0, e5 = 0.0, edt = 0.0;
-  // one (a, b) pair with a < b per workgroup step, c > b across the threads
-  for (int64_t pr = blockIdx.x; pr < nV2; pr += gridDim.x) {
-    const int64_t a = pr / nV, b = pr % nV;
-    if (a >= b) continue;
-    for (int64_t c = b + 1 + threadIdx.x; c < nV; c += blockDim.x) {
-      const int64_t x = (a * nV + b) * nV + c;
-      const double nc = Zt[x] - Zt[(b * nV + a) * nV + c] - ZtT[x];
+  const int64_t b0 = (int64_t)blockIdx.z * TRI_BCHUNK;
+  for (int64_t b = b0; b < b0 + TRI_BCHUNK && b < nV; ++b) {
+    if (!(a0 < b && c0 + 31 > b)) continue;  // uniform over the workgroup
+    __syncthreads();  // the previous b's reads of s3 are done
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t c = c0 + r, a = a0 + tx;
+      s3[r][tx] = (c < nV && a < nV) ? Zt[(c * nV + b) * nV + a] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t a = a0 + r, c = c0 + tx;
+      if (a >= b || c <= b || c >= nV) continue;
+      const double nc = Zt[(a * nV + b) * nV + c] - Zt[(b * nV + a) * nV + c] - s3[tx][r];
       if (nc == 0.0) continue;
       double d1 = 0.0, d2 = 0.0;
 #pragma unroll
@@ -229,10 +223,11 @@ tri_energy_partial(double* part, const double* Zt, const double* ZtT, const doub
   e4 = tri_block_sum(e4, sh);
   e5 = tri_block_sum(e5, sh);
   edt = tri_block_sum(edt, sh);
-  if (threadIdx.x == 0) {
-    part[3 * blockIdx.x + 0] = e4;
-    part[3 * blockIdx.x + 1] = e5;
-    part[3 * blockIdx.x + 2] = edt;
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    part[3 * blk + 0] = e4;
+    part[3 * blk + 1] = e5;
+    part[3 * blk + 2] = edt;
   }
 }
 
@@ -291,24 +286,21 @@ void tri_assemble_ovoo(double* Q, const double* S3, const TriDims& d, hipStream_
   DCSD_CHECK_LAUNCH();
 }
 
-void tri_transpose(double* dst, const double* src, int n, hipStream_t s) {
-  if (n <= 0) return;
-  if (n > 65535) throw ArgError("triples: too many virtual spin orbitals for the transpose grid");
-  const dim3 grid((n + 31) / 32, (n + 31) / 32, n);
-  hipLaunchKernelGGL(tri_transpose02, grid, dim3(32, 8), 0, s, dst, src, n);
-  DCSD_CHECK_LAUNCH();
+int64_t tri_energy_blocks(const TriDims& d) {
+  const int64_t t = (d.nV() + 31) / 32;
+  return t * t * ((d.nV() + TRI_BCHUNK - 1) / TRI_BCHUNK);
 }
 
-void tri_energy(double* out4, double* part, const double* Zt, const double* ZtT, const double* t1so,
-                const double* t2so, const double* oovv, const double* fo, const double* fv, const double* fov, int i,
-                int j, int k, const TriDims& d, hipStream_t s) {
-  const int64_t nV = d.nV();
-  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(nV * nV, TRI_PART_BLOCKS));
-  hipLaunchKernelGGL(tri_energy_partial, dim3(nb), dim3(TRI_THREADS), 0, s, part, Zt, ZtT, t1so, t2so, oovv, fo, fv,
+void tri_energy(double* out4, double* part, const double* Zt, const double* t1so, const double* t2so,
+                const double* oovv, const double* fo, const double* fv, const double* fov, int i, int j, int k,
+                const TriDims& d, hipStream_t s) {
+  const int nV = d.nV();
+  const dim3 grid((nV + 31) / 32, (nV + 31) / 32, (nV + TRI_BCHUNK - 1) / TRI_BCHUNK);
+  hipLaunchKernelGGL(tri_energy_tiled, grid, dim3(32, TRI_THREADS / 32), 0, s, part, Zt, t1so, t2so, oovv, fo, fv,
                      fov, i, j, k, d);
   DCSD_CHECK_LAUNCH();
   // 1/36 of the sum over all orders of (i, j, k) and (a, b, c) = the sum over i < j < k, a < b < c
-  hipLaunchKernelGGL(tri_energy_reduce, dim3(1), dim3(TRI_THREADS), 0, s, out4, part, (int)nb, 1.0);
+  hipLaunchKernelGGL(tri_energy_reduce, dim3(1), dim3(TRI_THREADS), 0, s, out4, part, (int)tri_energy_blocks(d), 1.0);
   DCSD_CHECK_LAUNCH();
 }
 
