@@ -257,8 +257,8 @@ typedef struct {
  * device memory of the correction and keeps it until dcsd_destroy: the
  * integrals <ei||bc> of every occupied spin orbital next to the amplitude
  * rows t_im^bc (n_occ (n_vir + n_occ) n_vir^2 doubles, n_occ = 2 nc + 2,
- * n_vir = 2 nv + 2), <jk||bc>, the spin-orbital amplitudes and two n_vir^3
- * work arrays.  Synchronises.  DCSD_ERR_ARG on NULL out or T
+ * n_vir = 2 nv + 2), <jk||bc>, the spin-orbital amplitudes and one n_vir^3
+ * work array.  Synchronises.  DCSD_ERR_ARG on NULL out or T
  * and for the two-determinant and fixed-reference methods, whose triples
  * correction is not defined here. */
 dcsd_status dcsd_triples(dcsd_ctx* ctx, const double* T_dev, dcsd_triples_energy* out, double* contrib_dev);
