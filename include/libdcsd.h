@@ -402,7 +402,13 @@ dcsd_status dcsd_selftest_gemm(int32_t precision, int64_t M, int64_t N, int64_t 
  * splits K into that many chunks summed by a second kernel (the library
  * allocates and frees the partial sums).  With ksplit = 1, outputs of at most
  * 16 x 16 over K >= 65536 with both operands k-contiguous take the split dot
- * product kernels, as in the method's products.  Returns DCSD_ERR_ARG on
+ * product kernels, as in the method's products.  As there too, an operand
+ * with an odd contiguous extent or leading dimension or a base that is not
+ * 16-byte aligned is first copied, zero-padded to an even leading dimension,
+ * into memory the library allocates and frees, when the output has at least
+ * 128 tiles of 128 x 128 and the product at least 256 flops per copied
+ * element (the direct-to-LDS kernel streams 16-byte chunks of aligned rows);
+ * the other such products take the register-staged kernel.  Returns DCSD_ERR_ARG on
  * non-positive sizes, ksplit < 1 or leading dimensions smaller than the
  * stored extents. */
 dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const double* A_dev, int64_t lda,
@@ -414,7 +420,8 @@ dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const dou
  * product as dcsd_selftest_gemm_layout, with the same arguments, kernels and
  * results, allocating nothing.  The scratch that call allocates (ksplit > 1:
  * ksplit * M * ldc partial sums; small outputs over a long K: one partial per
- * 2048-long K chunk and output element) comes from a per-GPU device array of
+ * 2048-long K chunk and output element; the zero-padded operand copies)
+ * comes from a per-GPU device array of
  * 4194304 doubles (32 MiB) that the library holds on each GPU it has run this
  * call on until the process ends; a call needing more returns DCSD_ERR_ARG
  * (dcsd_last_error(NULL) says why) without launching anything.  Every call on

@@ -339,7 +339,7 @@ dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const dou
   if (M <= 0 || N <= 0 || K <= 0 || !A_dev || !B_dev || !C_dev || ksplit < 1) return DCSD_ERR_ARG;
   if (lda < (a_mc ? M : K) || ldb < (b_nc ? N : K) || ldc < N) return DCSD_ERR_ARG;
   const hipStream_t st = (hipStream_t)hip_stream;
-  double* w = nullptr;
+  double *w = nullptr, *pw = nullptr;
   dcsd_status st_out = DCSD_OK;
   try {
     dcsd::GemmArgs g;
@@ -360,6 +360,14 @@ dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const dou
           throw dcsd::HipError("allocation failed");
         g.work = w;
       }
+      // operands the direct-to-LDS kernel cannot stream are copied, zero-padded, as in the method
+      const int64_t padw = dcsd::gemm_f64_pad_work(g);
+      if (padw > 0) {
+        if (hipMalloc((void**)&pw, (size_t)padw * sizeof(double)) != hipSuccess)
+          throw dcsd::HipError("allocation failed");
+        g.pad = pw;
+        g.pad_cap = padw;
+      }
       dcsd::gemm_f64(g, st);
     }
     if (hipStreamSynchronize(st) != hipSuccess) st_out = DCSD_ERR_HIP;
@@ -370,6 +378,7 @@ dcsd_status dcsd_selftest_gemm_layout(int64_t M, int64_t N, int64_t K, const dou
   }
   (void)hipStreamSynchronize(st);
   if (w) (void)hipFree(w);
+  if (pw) (void)hipFree(pw);
   return st_out;
 }
 

@@ -52,8 +52,16 @@ struct GemmArgs {
   int64_t batch = 1, sA = 0, sB = 0, sC = 0;
   int ksplit = 1;
   double* work = nullptr;
+  // Workspace (pad_cap doubles, 16-byte aligned) for zero-padded copies of operands that the
+  // direct-to-LDS kernel cannot stream as they are (an odd contiguous extent or leading
+  // dimension, a base off 16 bytes, an odd batch stride); NULL: such products take the
+  // register-staged kernel.
+  double* pad = nullptr;
+  int64_t pad_cap = 0;
 };
 void gemm_f64(const GemmArgs& g, hipStream_t s);
+// Doubles of `pad` that gemm_f64 uses for g (0 if it copies no operand).
+int64_t gemm_f64_pad_work(const GemmArgs& g);
 
 // Generic strided copy with scaling, up to 6 dimensions:
 //   dst[sum_d i_d*ds[d]] = alpha * src[sum_d i_d*ss[d]] + beta * dst[...]

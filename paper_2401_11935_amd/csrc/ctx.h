@@ -86,6 +86,8 @@ struct Ctx {
   double* Kpq = nullptr;               // (pq|qp), spatial
   double* gws = nullptr;               // split-K workspace
   int64_t gws_cap = 0;
+  double* pws = nullptr;               // padded operand copies of the FP64 GEMMs (optional)
+  int64_t pws_cap = 0;
   double* Isc = nullptr;               // undressed (kc|ld), spin-conserving ph matrix (2ov x 2ov)
   double* Icc = nullptr;               // antisymmetrised <kl||cd> ph matrix (CCSD only)
   double* Isf1 = nullptr;              // spin-flip <kl||cd> blocks (CCSD only)

@@ -455,13 +455,65 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
       }
 }
 
-// the direct-to-LDS kernel's layout and alignment conditions
+// The direct-to-LDS kernel streams each operand row in 16-byte chunks along its contiguous
+// extent (K for a K-contiguous operand, M or N for a K-major one): every row must start
+// 16-byte aligned (even leading dimension and batch stride, aligned base) and an odd extent
+// needs an element past its end that is zero, which the padded copy below provides.
+bool operand_ok(const double* p, int64_t ld, int64_t extent, int64_t stride, int64_t batch) {
+  return extent % 2 == 0 && ld % 2 == 0 && ((uintptr_t)p & 15) == 0 && (batch == 1 || stride % 2 == 0);
+}
 bool dl_ok(const GemmArgs& g) {
-  const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-  const bool a = g.a_mc ? g.M % 2 == 0 : g.K % 2 == 0;
-  const bool b = g.b_nc ? g.N % 2 == 0 : g.K % 2 == 0;
-  return a && b && g.lda % 2 == 0 && g.ldb % 2 == 0 && al16(g.A) && al16(g.B) &&
-         (g.batch == 1 || (g.sA % 2 == 0 && g.sB % 2 == 0));
+  return operand_ok(g.A, g.lda, g.a_mc ? g.M : g.K, g.sA, g.batch) &&
+         operand_ok(g.B, g.ldb, g.b_nc ? g.N : g.K, g.sB, g.batch);
+}
+// whether the output has the tiles the direct-to-LDS kernel takes
+bool dl_shape(const GemmArgs& g) {
+  const int64_t tiles128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
+  return g.M >= 128 && g.N >= 128 && tiles128 >= 128;
+}
+
+// Zero-padded copy of an operand: `rows` rows of `extent` contiguous elements (leading
+// dimension ld, batch stride stride; stride 0: one matrix shared by the batch) into rows of
+// ldp = extent rounded up to even, the batch's matrices back to back.
+struct PadPlan {
+  bool copy = false;
+  int64_t rows = 0, extent = 0, ldp = 0, nb = 0;
+  int64_t elems() const { return copy ? (nb * rows * ldp + 1) / 2 * 2 : 0; }  // keeps what follows aligned
+  int64_t stride() const { return nb > 1 ? rows * ldp : 0; }
+};
+PadPlan pad_plan(const double* p, int64_t ld, int64_t extent, int64_t rows, int64_t stride, int64_t batch) {
+  PadPlan q;
+  if (operand_ok(p, ld, extent, stride, batch)) return q;
+  q.copy = true;
+  q.rows = rows;
+  q.extent = extent;
+  q.ldp = extent + (extent & 1);
+  q.nb = batch > 1 && stride != 0 ? batch : 1;
+  return q;
+}
+PadPlan pad_plan_a(const GemmArgs& g) {
+  return pad_plan(g.A, g.lda, g.a_mc ? g.M : g.K, g.a_mc ? g.K : g.M, g.sA, g.batch);
+}
+PadPlan pad_plan_b(const GemmArgs& g) {
+  return pad_plan(g.B, g.ldb, g.b_nc ? g.N : g.K, g.b_nc ? g.K : g.N, g.sB, g.batch);
+}
+
+// dst[(b * rows + r) * ldp + c] = c < extent ? src[b * stride + r * ld + c] : 0
+__global__ __launch_bounds__(256) void pad_copy_kernel(double* dst, int64_t ldp, const double* src, int64_t ld,
+                                                      int64_t stride, int64_t rows, int64_t extent, int64_t total) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = i / ldp, c = i - row * ldp, b = row / rows, r = row - b * rows;
+    dst[i] = c < extent ? src[b * stride + r * ld + c] : 0.0;
+  }
+}
+
+void pad_copy(const PadPlan& q, double* dst, const double* src, int64_t ld, int64_t stride, hipStream_t s) {
+  const int64_t total = q.nb * q.rows * q.ldp;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(pad_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, q.ldp, src, ld, stride, q.rows,
+                     q.extent, total);
+  DCSD_CHECK_LAUNCH();
 }
 
 template <bool A_KM, bool B_KM, bool C_NC>
@@ -537,6 +589,17 @@ void dispatch(const GemmArgs& g, KArgs& k, hipStream_t s) {
 
 }  // namespace
 
+// Padding pays where the copies are small against the product: at least 256 flops per
+// copied element (for a single operand, the other operand's extent of 128 or more).
+int64_t gemm_f64_pad_work(const GemmArgs& g) {
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0 || g.batch <= 0 || !dl_shape(g) || dl_ok(g)) return 0;
+  const PadPlan pa = pad_plan_a(g), pb = pad_plan_b(g);
+  if (pa.ldp >= ((int64_t)1 << 25) || pb.ldp >= ((int64_t)1 << 25)) return 0;
+  const int64_t n = pa.elems() + pb.elems();
+  const double flops = 2.0 * (double)g.M * (double)g.N * (double)g.K * (double)g.batch;
+  return flops >= 256.0 * (double)n ? n : 0;
+}
+
 void gemm_f64(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
   if (g.batch > 65535 || g.ksplit > 65535 || g.ksplit < 1) throw ArgError("gemm_f64: grid too large");
@@ -561,10 +624,28 @@ void gemm_f64(const GemmArgs& g, hipStream_t s) {
     k.kchunk = g.K;
     k.split_stride = 0;
   }
-  const int64_t tiles128 = ((g.M + 127) / 128) * ((g.N + 127) / 128) * g.batch * g.ksplit;
-  if (g.M >= 128 && g.N >= 128 && tiles128 >= 128 && dl_ok(g)) {
+  const int64_t pad = gemm_f64_pad_work(g);
+  if (dl_shape(g) && pad > 0 && g.pad && pad <= g.pad_cap) {
+    // copy the operands the direct-to-LDS kernel cannot stream into the padded workspace
+    const PadPlan pa = pad_plan_a(g), pb = pad_plan_b(g);
+    double* w = g.pad;
+    if (pa.copy) {
+      pad_copy(pa, w, g.A, g.lda, g.sA, s);
+      k.A = w;
+      k.lda = pa.ldp;
+      k.sA = pa.stride();
+      w += pa.elems();
+    }
+    if (pb.copy) {
+      pad_copy(pb, w, g.B, g.ldb, g.sB, s);
+      k.B = w;
+      k.ldb = pb.ldp;
+      k.sB = pb.stride();
+    }
     launch_dl(g, k, s);
-  } else if (g.M >= 128 && g.N >= 128 && tiles128 >= 128)
+  } else if (dl_shape(g) && dl_ok(g)) {
+    launch_dl(g, k, s);
+  } else if (dl_shape(g))
     dispatch<128, 128>(g, k, s);
   else
     dispatch<64, 64>(g, k, s);

@@ -2,8 +2,8 @@
 // cannot allocate device memory (code under HIP graph capture, serving loops,
 // harnesses that forbid hipMalloc).  Same arguments and the same kernels as
 // dcsd_selftest_gemm_layout; the scratch that call allocates (split-K partial
-// sums, or the partial dot products of small outputs over a long K) lives in a
-// file-scope device array instead.  Each GPU holds its own copy of the array
+// sums, or the partial dot products of small outputs over a long K, and the
+// zero-padded operand copies) lives in a file-scope device array instead.  Each GPU holds its own copy of the array
 // at its own address, looked up once per device with hipGetSymbolAddress; the
 // array's name is never used as a device address in host code.
 #include <hip/hip_runtime.h>
@@ -20,7 +20,7 @@ void set_call_error(const char* msg);
 
 namespace {
 
-// 32 MiB of FP64 partial sums per GPU, kept until the process ends.
+// 32 MiB of FP64 scratch per GPU, kept until the process ends.
 constexpr int64_t kScratchDoubles = (int64_t)1 << 22;
 static __device__ __align__(256) double scratch[kScratchDoubles];
 
@@ -70,7 +70,10 @@ extern "C" dcsd_status dcsd_selftest_gemm_layout_noalloc(int64_t M, int64_t N, i
   g.ksplit = ksplit;
   // the same dispatch as dcsd_selftest_gemm_layout, with the same scratch sizes
   const int64_t small = ksplit == 1 ? dcsd::gemm_f64_small_work(g) : 0;
-  const double need = small > 0 ? (double)small : (ksplit > 1 ? (double)ksplit * (double)M * (double)ldc : 0.0);
+  // split-K partials, then (16-byte aligned) the zero-padded operand copies
+  const int64_t split = small > 0 || ksplit == 1 ? 0 : (ksplit * M * ldc + 1) / 2 * 2;
+  const int64_t padw = small > 0 ? 0 : dcsd::gemm_f64_pad_work(g);
+  const double need = small > 0 ? (double)small : (double)split + (double)padw;
   if (need > (double)kScratchDoubles) {
     dcsd::set_call_error("gemm_layout_noalloc: the scratch it needs exceeds its 4194304 doubles (32 MiB)");
     return DCSD_ERR_ARG;
@@ -87,7 +90,11 @@ extern "C" dcsd_status dcsd_selftest_gemm_layout_noalloc(int64_t M, int64_t N, i
         return DCSD_ERR_HIP;
       }
     } else {
-      g.work = work;
+      g.work = split > 0 ? work : nullptr;
+      if (padw > 0) {
+        g.pad = work + split;
+        g.pad_cap = padw;
+      }
       dcsd::gemm_f64(g, st);
     }
     if (hipStreamSynchronize(st) != hipSuccess) return DCSD_ERR_HIP;

@@ -63,6 +63,8 @@ struct G {
         }
       }
     }
+    a.pad = c.pws;
+    a.pad_cap = c.pws_cap;
     if (t_tape) tape_gemm(a);
     gemm_f64(a, c.s);
   }

@@ -446,7 +446,7 @@ void Ctx::init(const dcsd_config& cf, const double* Bin, const double* Fin, hipS
 // sites (with the rounding buffers, which are allocated here in any case), then the ladder
 // integral caches (cfg.ladder_cache): one slot per orbital-pair batch (p-block <= q-block),
 // the low-precision slots of V2L's size with the row padding zeroed like V2L, the FP64
-// slots of V2's size.
+// slots of V2's size; then the FP64 GEMMs' padded operand workspace.
 void Ctx::alloc_optional() {
   auto fits = [&](size_t b) {
     size_t fr = 0, tot = 0;
@@ -476,7 +476,23 @@ void Ctx::alloc_optional() {
     lpA = alloc((lp_cap * es + 7) / 8);
     lpB = alloc((lp_cap * es + 7) / 8);
   }
+  // last, the padded operand copies of the FP64 GEMMs whose extents (o, v) are odd: the largest
+  // products pad both operands of about o^2 v^2 elements each
+  auto alloc_pad = [&]() {
+    const int64_t om = std::max(L.o[0], L.o[1]), vm = std::max(L.v[0], L.v[1]) + 1;
+    const int64_t cap = 2 * (om * om + 1) * vm * vm;
+    if (fits((size_t)cap * sizeof(double))) {
+      try {
+        pws = (double*)alloc_raw((size_t)cap * sizeof(double));
+        pws_cap = cap;
+      } catch (const std::bad_alloc&) {
+        pws = nullptr;
+        pws_cap = 0;
+      }
+    }
+  };
   if (!cfg.ladder_cache) {
+    alloc_pad();
     DCSD_HIP(hipStreamSynchronize(s));
     return;
   }
@@ -505,6 +521,7 @@ void Ctx::alloc_optional() {
       }
     }
   }
+  alloc_pad();
   DCSD_HIP(hipStreamSynchronize(s));
 }
 

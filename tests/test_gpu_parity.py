@@ -52,11 +52,13 @@ def test_gemm_matches_numpy(M, N, K):
     assert err <= tol, f"max |C - A B| = {err:.3e} > {tol:.3e}"
 
 
-# (M, N, K, a_mc, b_nc, ksplit, alpha, beta, pad, shift): outputs of at least 128 tiles with
-# K-major operands take the direct-to-LDS kernel when M, N, the leading dimensions and the
-# batch strides are even and both bases are 16-byte aligned (K-major operands need an even
-# extent along M (N), K-contiguous ones an even K); the other rows check its fallbacks (odd
-# M or K, an 8-byte shifted base, small outputs)
+# (M, N, K, a_mc, b_nc, ksplit, alpha, beta, pad, shift): outputs of at least 128 tiles of
+# 128 x 128 take the direct-to-LDS kernel, which streams every operand row in 16-byte chunks
+# along its contiguous extent (M or N for a K-major operand, K for a K-contiguous one): an
+# operand with an odd extent or leading dimension or an 8-byte shifted base is first copied,
+# zero-padded (odd M or K, the shifted bases below); where the copy would cost more than the
+# product gains (the 16384 x 128 row) it takes the register-staged kernel, and small outputs
+# take the 64-wide kernels
 LAYOUTS = [(1536, 1536, 37, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1408, 100, 1, 1, 3, 0.5, 1.0, 0, 0),
            (1530, 1542, 8, 1, 1, 1, -1.0, 1.0, 0, 0), (1536, 1536, 24, 1, 1, 1, 1.0, 0.0, 6, 0),
            (1535, 1536, 20, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1536, 20, 1, 1, 1, 1.0, 0.0, 0, 1),
@@ -66,6 +68,8 @@ LAYOUTS = [(1536, 1536, 37, 1, 1, 1, 1.0, 0.0, 0, 0), (1536, 1408, 100, 1, 1, 3,
            (1536, 1280, 34, 1, 0, 1, 2.0, 0.0, 2, 0), (1501, 1527, 50, 0, 0, 1, -0.5, 1.0, 4, 0),
            (1500, 1530, 26, 0, 1, 2, 1.0, 1.0, 0, 0), (1500, 1530, 120, 1, 1, 8, 0.5, 1.0, 0, 0),
            (338, 1024, 1000, 0, 0, 16, 1.0, 0.0, 0, 0),
+           # both operands padded: odd K in K-contiguous rows with odd leading dimensions, split
+           (1537, 1281, 45, 0, 0, 3, 1.0, 0.5, 1, 0), (16384, 128, 33, 0, 1, 1, 1.0, 0.0, 0, 0),
            # small outputs over a long K (split dot products): full, ragged, single row and
            # column, padded rows, an 8-byte shifted base, K not a multiple of the 2048 chunk
            (16, 16, 65536, 0, 0, 1, 1.0, 0.0, 0, 0), (13, 13, 67769, 0, 0, 1, 1.0, 1.0, 0, 0),

@@ -1,6 +1,7 @@
 """GPU: dcsd_selftest_gemm_layout_noalloc, the FP64 layout GEMM that allocates
-nothing (its split-K and small-output partial sums live in a per-GPU static
-array), against dcsd_selftest_gemm_layout, which allocates the same scratch.
+nothing (its split-K and small-output partial sums and its zero-padded operand
+copies live in a per-GPU static array), against dcsd_selftest_gemm_layout,
+which allocates the same scratch.
 
 Two calls in a row per path, the second with a smaller input, each compared
 bitwise with the allocating entry point (the same kernels in the same order);
@@ -52,6 +53,7 @@ CASES = {
     "split-K": [(1280, 1152, 700, 1, 1, 2, 0.5, 1.0, 0), (900, 700, 300, 0, 1, 2, -1.0, 0.5, 4)],
     "small outputs over a long K": [(16, 16, 200000, 0, 0, 1, 1.0, 0.0, 0), (7, 11, 70001, 0, 0, 1, 2.0, 0.5, 3)],
     "no scratch": [(1536, 1536, 40, 0, 1, 1, 1.0, 0.5, 0), (300, 200, 20, 1, 0, 1, 1.0, 0.0, 2)],
+    "zero-padded operand copies": [(1536, 1280, 33, 0, 1, 1, 1.0, 0.0, 0), (1300, 1400, 21, 1, 0, 2, -1.0, 0.5, 1)],
 }
 
 
