@@ -32,6 +32,8 @@ struct KArgs {
   int64_t split_stride;  // element stride between split partial outputs
   int64_t vu, nq;        // pair-blocked output (EPI = 1)
   int64_t skip_lower;    // EPI = 1, diagonal batch: skip tiles whose pairs all have p > q
+  const double* bseg[3]; // EPI = 2: row k of B is row k % segk of bseg[k / segk]
+  int64_t segk;
 };
 
 template <int BM, int BN, bool A_MC, bool B_NC, bool C_NC, bool SPLIT, int EPI = 0>
@@ -302,6 +304,7 @@ constexpr int waitcnt_vm(int vm) { return (vm & 0xF) | ((vm >> 4) << 14) | (7 <<
 
 template <bool A_KM, bool B_KM, int EPI, bool SPLIT, bool C_NC>
 __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
+  static_assert(EPI != 2 || (B_KM && !SPLIT), "segmented B: K-major, whole K");
   constexpr int BM = 128, BN = 128;
   constexpr int WM = BM / DL_WGM, WN = BN / DL_WGN, TM = WM / 16, TN = WN / 16, KS = DL_BK / 4;
   static_assert(DL_NW == DL_BK && DL_NW * 16 == BM, "one wave instruction per operand per step");
@@ -335,7 +338,18 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
   const double* B = g.B + batch * g.sB;
   auto issue = [&](int slot, int64_t k0) {
     const double* sa = TA::src(A, g.lda, m0, g.M, k0, kend, wave, lane, zrow);
-    const double* sb = TB::src(B, g.ldb, n0, g.N, k0, kend, wave, lane, zrow);
+    const double* sb;
+    if constexpr (EPI == 2) {
+      // K-major B in segments: this wave's row k lies in segment k / segk (wave-uniform)
+      const int64_t k = k0 + wave;
+      sb = zrow;
+      if (n0 + 2 * lane < g.N && k < kend) {
+        const int64_t q = k / g.segk;
+        sb = g.bseg[q] + (k - q * g.segk) * g.ldb + n0 + 2 * lane;
+      }
+    } else {
+      sb = TB::src(B, g.ldb, n0, g.N, k0, kend, wave, lane, zrow);
+    }
     __builtin_amdgcn_global_load_lds((const void*)sa, (void __attribute__((address_space(3)))*)&sA[slot][TA::dst(wave)],
                                      16, 0, 0);
     __builtin_amdgcn_global_load_lds((const void*)sb, (void __attribute__((address_space(3)))*)&sB[slot][TB::dst(wave)],
@@ -658,6 +672,30 @@ void gemm_f64(const GemmArgs& g, hipStream_t s) {
                        g.ldc, g.c_nc, g.batch, g.sC, g.ksplit, k.split_stride, g.alpha, g.beta);
     DCSD_CHECK_LAUNCH();
   }
+}
+
+bool gemm_f64_bseg(int64_t M, int64_t N, int64_t segk, int nseg, const double* A, int64_t lda,
+                   const double* const* bseg, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                   hipStream_t s) {
+  if (nseg < 1 || nseg > 3 || segk < 1 || M < 128 || N < 128) return false;
+  const int64_t K = nseg * segk, tm = (M + 127) / 128, tn = (N + 127) / 128;
+  const auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  bool ok = tm * tn >= 128 && lda % 2 == 0 && lda >= K + (K & 1) && al16(A) && N % 2 == 0 && ldb % 2 == 0 &&
+            lda < ((int64_t)1 << 25) && ldb < ((int64_t)1 << 25);
+  for (int q = 0; q < nseg; ++q) ok = ok && bseg[q] && al16(bseg[q]);
+  if (!ok) return false;
+  KArgs k{};
+  k.M = M; k.N = N; k.K = K;
+  k.A = A; k.lda = lda;
+  k.B = bseg[0]; k.ldb = ldb;
+  for (int q = 0; q < 3; ++q) k.bseg[q] = bseg[q < nseg ? q : 0];
+  k.segk = segk;
+  k.C = C; k.ldc = ldc; k.alpha = alpha; k.beta = beta;
+  k.kchunk = K;
+  k.tiles_n = tn;
+  hipLaunchKernelGGL((gemm_dl_kernel<false, true, 2, false, true>), dim3((unsigned)(tm * tn)), dim3(DL_NT), 0, s, k);
+  DCSD_CHECK_LAUNCH();
+  return true;
 }
 
 // Ladder integral batch: V2[(p*nq + q)][c][d] = sum_P Bl[P][p0+p][c] Bl[P][q0+q][d]

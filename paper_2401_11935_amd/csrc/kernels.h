@@ -47,6 +47,13 @@ void batch_reduce(double* dst, const double* src, int64_t nb, int64_t bstride, i
                   int64_t ldd, bool transpose, double alpha, hipStream_t s);
 
 // ladder
+// C(m,n) = alpha * sum_{q < nseg} sum_{k < segk} A[m*lda + q*segk + k] * bseg[q][k*ldb + n] + beta * C(m,n),
+// C row-major (ldc), on the direct-to-LDS kernel: A K-contiguous (16-byte aligned, lda even; an odd
+// K = nseg*segk needs A's column K zero), the bseg n-contiguous (aligned, N and ldb even), at least
+// 128 output tiles of 128 x 128.  False (nothing launched) where these conditions fail.
+bool gemm_f64_bseg(int64_t M, int64_t N, int64_t segk, int nseg, const double* A, int64_t lda,
+                   const double* const* bseg, int64_t ldb, double* C, int64_t ldc, double alpha, double beta,
+                   hipStream_t s);
 void gemm_f64_pairs(const double* Bl, int64_t ld, int64_t vu, int64_t naux, int64_t p0, int64_t np, int64_t q0,
                     int64_t nq, double* V2, hipStream_t s);
 // Stack rows: [ab (o0 o1) | aa pairs i<j (P0) | bb pairs i<j (P1) | ab transposed (o0 o1)], each a
@@ -166,9 +173,15 @@ void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov,
 // slab rows row_e(E) of every X: <EX||BC> from S[(eU,bU)][(x,cU)] = (eb|xc) (x spatial occupied,
 // row length oa*nU)
 void tri_assemble_vovv(double* I, const double* S, const TriDims& d, hipStream_t s);
-// A[3][nV][n]: the combined t2 / -<ma||yz> operand of the three orders of (i, j, k)
-void tri_operand_a(double* A, const double* t2so, const double* Q, int i, int j, int k, const TriDims& d,
-                   hipStream_t s);
+// Orders p of (i, j, k) that contribute to the virtuals a of each spin, in segment order.
+struct TriSegs {
+  int nseg[2] = {0, 0};
+  int p[2][3] = {{0, 0, 0}, {0, 0, 0}};
+};
+// A[nV][lda]: per virtual a, the signed t2 / -<ma||yz> operands of its spin's orders side by
+// side (n columns each), zeros after them (lda >= 3n)
+void tri_operand_a(double* A, int64_t lda, const double* t2so, const double* Q, int i, int j, int k, const TriSegs& g,
+                   const TriDims& d, hipStream_t s);
 // O[J][K][B][C] = <JK||BC> from S2[(j,bU)][(k,cU)] = (jb|kc)
 void tri_assemble_oovv(double* O, const double* S2, const TriDims& d, hipStream_t s);
 // Q[Y][Z][A][M] = <MA||YZ> from S3[(m,y)][(aU,z)] = (my|az)

@@ -13,9 +13,11 @@
 //  * per call: the packed amplitudes unpacked to spin orbitals, then for each
 //    occupied triple i < j < k
 //      Zt[a][bc] = P(i/jk) [sum_e t_jk^ae <ei||bc> - sum_m t_im^bc <ma||jk>]
-//    as at most six FP64 GEMMs (three orders of (i, j, k) times the spins of
-//    a that spin conservation allows) accumulated into one n_vir x n_vir^2
-//    array, and one pass over a < b < c, tiled through LDS so that Zt[c][b][a]
+//    as one FP64 GEMM per spin of a, written once into one n_vir x n_vir^2
+//    array: its K runs over the orders of (i, j, k) that spin conservation
+//    allows for that spin (up to three segments of n), each segment reading
+//    the slab rows of its own x; then one pass over a < b < c, tiled through
+//    LDS so that Zt[c][b][a]
 //    is read along a, that forms N^c = P(a/bc) Zt, the disconnected numerator
 //    and the denominator and reduces the three energy parts in a fixed order.
 #include <vector>
@@ -68,7 +70,7 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
     once(tri.oovv, nO * nO * nV2);
     once(tri.Q, nO * nO * nV * nO);
     once(tri.I, nO * d.slab_rows() * nV2);
-    once(tri.Aop, 3 * nV * (int64_t)n);
+    once(tri.Aop, nV * (3 * (int64_t)n + 1));
     once(tri.Zt, nV3);
     once(tri.part, 3 * tri_energy_blocks(d));
     once(tri.out, std::max<int64_t>(4 * ntrip, 4));
@@ -107,33 +109,40 @@ void Ctx::triples(const double* T, dcsd_triples_energy* out, double* contrib) {
         {nO * nV2, nV2, 1}, 1.0, 0.0, s);
 
   const int64_t off_v[2] = {0, d.va}, nvs[2] = {d.va, d.vb}, row_e[2] = {0, (int64_t)d.va + d.oa};
+  const int64_t lda3 = 3 * (int64_t)n + ((3 * n) & 1);  // even, with a zero column after 3n
   int64_t t = 0;
   for (int i = 0; i < nO; ++i)
     for (int j = i + 1; j < nO; ++j)
       for (int k = j + 1; k < nO; ++k, ++t) {
-        // P(i/jk): (x; y z) = (i; j k), (j; i k), (k; j i) with signs +, -, -
+        // P(i/jk): (x; y z) = (i; j k), (j; i k), (k; j i) with signs +, -, - (in the A operand).
+        // Spin conservation: t_yz^{ae} and <ma||yz> need s(e) = s(m) = s(y) + s(z) - s(a); the
+        // orders allowed for a of spin sa form the K segments of one product per spin, each
+        // segment against the slab rows of its own x.
         const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
-        const double sg[3] = {1.0, -1.0, -1.0};
-        tri_operand_a(tri.Aop, tri.t2so, tri.Q, i, j, k, d, s);
-        bool written[2] = {false, false};
-        for (int p = 0; p < 3; ++p) {
-          const int64_t x = xs[p];
-          const int sy = ys[p] >= d.oa, sz = zs[p] >= d.oa;
-          for (int sa = 0; sa < 2; ++sa) {
-            // spin conservation: t_yz^{ae} and <ma||yz> need s(e) = s(m) = s(y) + s(z) - s(a)
-            const int se = sy + sz - sa;
-            if (se < 0 || se > 1 || nvs[sa] == 0) continue;
-            G(nvs[sa], nV2, n)
-                .A(tri.Aop + (p * nV + off_v[sa]) * n, n, false)
-                .B(tri.I + (x * R + row_e[se]) * nV2, nV2, true)
-                .C(tri.Zt + off_v[sa] * nV2, nV2)
-                .ab(sg[p], written[sa] ? 1.0 : 0.0)
-                .run(*this);
-            written[sa] = true;
-          }
-        }
+        TriSegs g;
+        int seg_se[2][3] = {};
         for (int sa = 0; sa < 2; ++sa)
-          if (!written[sa]) fill(tri.Zt + off_v[sa] * nV2, 0.0, nvs[sa] * nV2, s);
+          for (int p = 0; p < 3 && nvs[sa] > 0; ++p) {
+            const int se = (ys[p] >= d.oa) + (zs[p] >= d.oa) - sa;
+            if (se < 0 || se > 1) continue;
+            seg_se[sa][g.nseg[sa]] = se;
+            g.p[sa][g.nseg[sa]++] = p;
+          }
+        tri_operand_a(tri.Aop, lda3, tri.t2so, tri.Q, i, j, k, g, d, s);
+        for (int sa = 0; sa < 2; ++sa) {
+          if (nvs[sa] == 0) continue;
+          double* Zs = tri.Zt + off_v[sa] * nV2;
+          if (g.nseg[sa] == 0) {
+            fill(Zs, 0.0, nvs[sa] * nV2, s);
+            continue;
+          }
+          const double* As = tri.Aop + off_v[sa] * lda3;
+          const double* bs[3] = {nullptr, nullptr, nullptr};
+          for (int q = 0; q < g.nseg[sa]; ++q) bs[q] = tri.I + (xs[g.p[sa][q]] * R + row_e[seg_se[sa][q]]) * nV2;
+          if (gemm_f64_bseg(nvs[sa], nV2, n, g.nseg[sa], As, lda3, bs, nV2, Zs, nV2, 1.0, 0.0, s)) continue;
+          for (int q = 0; q < g.nseg[sa]; ++q)  // shapes the segmented product does not take
+            G(nvs[sa], nV2, n).A(As + q * n, lda3, false).B(bs[q], nV2, true).C(Zs, nV2).ab(1.0, q ? 1.0 : 0.0).run(*this);
+        }
         tri_energy(tri.out + 4 * t, tri.part, tri.Zt, tri.t1so, tri.t2so, tri.oovv, tri.fo, tri.fv, tri.fov, i, j, k,
                    d, s);
       }

@@ -132,25 +132,29 @@ __global__ void tri_ovoo(double* Q, const double* S3, TriDims d) {
   }
 }
 
-// A[p][a][kk] (kk < n) of the three orders p of (i, j, k) -> (x; y z) = (i; j k), (j; i k),
-// (k; j i): for a of spin sa and s = s(y) + s(z) - s(a), the columns are t_yz^{a e} over the
+// A[a][q*n + kk] (row stride lda, kk < n): for a of spin sa, segment q < g.nseg[sa] holds the
+// order p = g.p[sa][q] of (i, j, k) -> (x; y z) = (i; j k), (j; i k), (k; j i) with its sign
+// (+, -, -) of P(i/jk): over the spin s = s(y) + s(z) - s(a), the columns are t_yz^{a e} over the
 // virtuals e of spin s, then -<m a||y z> over the occupied m of spin s (v_s + o_s = n columns),
-// matching the slab rows row_e(e), row_m(m) of x; zero where no spin s exists.
-__global__ void tri_build_a(double* A, const double* t2so, const double* Q, int i, int j, int k, TriDims d) {
+// matching the slab rows row_e(e), row_m(m) of x.  Every other column is zero.
+__global__ void tri_build_a(double* A, int64_t lda, const double* t2so, const double* Q, int i, int j, int k,
+                            TriSegs g, TriDims d) {
   const int64_t nO = d.nO(), nV = d.nV(), n = d.n;
-  const int64_t total = 3 * nV * n;
+  const int64_t total = nV * lda;
   for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t kk = x % n, a = (x / n) % nV;
-    const int p = (int)(x / (n * nV));
-    const int64_t y = p == 0 ? j : (p == 1 ? i : j), z = p == 2 ? i : k;
-    const int se = ospin(d, (int)y) + ospin(d, (int)z) - vspin(d, (int)a);
+    const int64_t a = x / lda, col = x - a * lda, q = col / n, kk = col - q * n;
+    const int sa = vspin(d, (int)a);
     double v = 0.0;
-    if (se == 0 || se == 1) {
+    if (q < g.nseg[sa]) {
+      const int p = g.p[sa][q];
+      const int64_t y = p == 0 ? j : (p == 1 ? i : j), z = p == 2 ? i : k;
+      const int se = ospin(d, (int)y) + ospin(d, (int)z) - sa;  // 0 or 1 for a listed segment
       const int64_t nve = se ? d.vb : d.va;
       if (kk < nve)
         v = t2so[((y * nO + z) * nV + a) * nV + (se ? d.va : 0) + kk];
       else
         v = -Q[((y * nO + z) * nV + a) * nO + (se ? d.oa : 0) + (kk - nve)];
+      if (p != 0) v = -v;
     }
     A[x] = v;
   }
@@ -260,11 +264,11 @@ void tri_unpack(double* t1so, double* t2so, double* fo, double* fv, double* fov,
   DCSD_CHECK_LAUNCH();
 }
 
-void tri_operand_a(double* A, const double* t2so, const double* Q, int i, int j, int k, const TriDims& d,
-                   hipStream_t s) {
-  const int64_t total = 3 * (int64_t)d.nV() * d.n;
-  hipLaunchKernelGGL(tri_build_a, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, A, t2so, Q, i, j, k,
-                     d);
+void tri_operand_a(double* A, int64_t lda, const double* t2so, const double* Q, int i, int j, int k, const TriSegs& g,
+                   const TriDims& d, hipStream_t s) {
+  const int64_t total = (int64_t)d.nV() * lda;
+  hipLaunchKernelGGL(tri_build_a, dim3(tri_blocks(total, TRI_THREADS)), dim3(TRI_THREADS), 0, s, A, lda, t2so, Q, i, j,
+                     k, g, d);
   DCSD_CHECK_LAUNCH();
 }
 

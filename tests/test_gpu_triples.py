@@ -134,3 +134,35 @@ def test_triples_at_the_bench_shape_sampled_by_triple():
         ref = triple_contribution(ham, t1, t2, *trips[q], direct=True)
         say(f"  triple {trips[q]}: GPU {contrib[q]:.15e} oracle {ref:.15e}")
         assert _close(contrib[q], ref), (trips[q], contrib[q], ref)
+
+
+def test_triples_segmented_product_sampled_by_triple():
+    """nc=3, nv=130, naux=24 (weak integrals): with at least 128 virtuals of each spin the
+    connected numerator is one segmented product per spin of a (the K segments of the allowed
+    orders of (i, j, k), each against the slabs of its own x); the smaller shapes above take
+    the per-segment products.  Two seeded triples of each spin pattern (the one beta^3 triple)
+    against the oracle's triple-by-triple form, and the total is the sum of the per-triple
+    contributions."""
+    from oracle.highspin import HighSpinHamiltonian
+    from oracle.triples import triple_contribution
+    nc, nv, naux = 3, 130, 24
+    say("triples segmented product", nc, nv, naux)
+    B, F = synth.make_inputs(nc, nv, naux, 77, sigma=synth.weak_sigma(naux))
+    T = synth.hs_random_amplitudes(nc, nv, 78, 0.02)
+    e, contrib = _gpu_triples(B, F, nc, "hs-ccsd", T)
+    trips = list(itertools.combinations(range(2 * nc + 2), 3))
+    assert e["triples"] == len(trips) == contrib.size
+    assert abs(contrib.sum() - e["E_T"]) <= 1e-12 * max(1.0, abs(e["E_T"]))
+    oa = nc + 2
+    rng = np.random.default_rng(79)
+    picks = []
+    for nbeta in range(4):  # beta^3: the one triple of the three beta orbitals
+        cands = [q for q, t in enumerate(trips) if sum(x >= oa for x in t) == nbeta]
+        picks += [int(x) for x in rng.choice(cands, min(2, len(cands)), replace=False)]
+    ham = HighSpinHamiltonian(B, F, nc)
+    t1, t2 = ham.to_so(T)
+    for q in picks:
+        ref = triple_contribution(ham, t1, t2, *trips[q], direct=True)
+        say(f"  triple {trips[q]}: GPU {contrib[q]:.15e} oracle {ref:.15e}")
+        assert _close(contrib[q], ref), (trips[q], contrib[q], ref)
+    assert abs(e["E_T"]) > 1e-8
