@@ -179,46 +179,91 @@ __device__ double tri_block_sum(double v, double* sh) {
 //   N^c = Zt[a][b][c] - Zt[b][a][c] - Zt[c][b][a]          (Zt = P(i/jk) of the GEMM sums)
 //   N^d = P(i/jk) P(a/bc) [t_i^a <jk||bc> + f_ia t_jk^bc]
 // One workgroup per (32 c) x (32 a) tile and chunk of TRI_BCHUNK values of b (grid x, y, z),
-// 32 x 8 threads: for each b the tile Zt[c][b][a] (rows c, contiguous a) goes through LDS,
-// so that all three reads run along their contiguous index.  part: three doubles per
-// workgroup, in grid order (zeros where the tile holds no a < b < c).
+// 32 x 8 threads, thread (tx, ty) on c = c0 + tx and the four a = a0 + ty + 8q.  For each b the
+// tile Zt[c][b][a] (rows c, contiguous a) and the rows b of the six matrices of the disconnected
+// numerator go through LDS, so that all three Zt reads run along their contiguous index; the
+// matrix elements at (a, c) and the vectors at a and c, which do not depend on b, stay in
+// registers.  part: three doubles per workgroup, in grid order (zeros where the tile holds no
+// a < b < c).
 __global__ void __launch_bounds__(TRI_THREADS)
 tri_energy_tiled(double* part, const double* Zt, const double* t1so, const double* t2so, const double* oovv,
                  const double* fo, const double* fv, const double* fov, int i, int j, int k, TriDims d) {
   __shared__ double s3[32][33];
+  __shared__ double sb[2][6][32];  // rows b of the six matrices at columns c0 + u ([0]) and a0 + u ([1])
   __shared__ double sh[TRI_THREADS];
   const int64_t nO = d.nO(), nV = d.nV(), nV2 = nV * nV;
   const int64_t a0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
-  const int tx = threadIdx.x, ty = threadIdx.y;
-  const double fijk = fo[i] + fo[j] + fo[k];
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 32 + tx;
+  const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.z * TRI_BCHUNK;
+  const int64_t blo = b0 > a0 + 1 ? b0 : a0 + 1;  // some a < b in the tile
+  int64_t bhi = b0 + TRI_BCHUNK < nV ? b0 + TRI_BCHUNK : nV;
+  if (bhi > c0 + 31) bhi = c0 + 31;                // some c > b in the tile
+  if (blo >= bhi) {                                // uniform over the workgroup
+    if (tid == 0) part[3 * blk] = part[3 * blk + 1] = part[3 * blk + 2] = 0.0;
+    return;
+  }
+  // matrices m < 3: <y z||..> of the orders p = m, m >= 3: t_yz of p = m - 3; vectors t1_x, f_x
   const int xs[3] = {i, j, k}, ys[3] = {j, i, j}, zs[3] = {k, k, i};
   const double sg[3] = {1.0, -1.0, -1.0};
+  const double* Mx[6];
+  const double* vx[6];
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    Mx[p] = oovv + ((int64_t)ys[p] * nO + zs[p]) * nV2;
+    Mx[3 + p] = t2so + ((int64_t)ys[p] * nO + zs[p]) * nV2;
+    vx[p] = t1so + (int64_t)xs[p] * nV;
+    vx[3 + p] = fov + (int64_t)xs[p] * nV;
+  }
+  const double fijk = fo[i] + fo[j] + fo[k];
+  const int64_t c = c0 + tx;
+  const bool cin = c < nV;
+  double mac[4][6], va[4][6], vc[6], fva[4];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) vc[m] = cin ? vx[m][c] : 0.0;
+  const double fvc = cin ? fv[c] : 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t a = a0 + ty + 8 * q;
+    const bool ain = a < nV;
+    fva[q] = ain ? fv[a] : 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      mac[q][m] = ain && cin ? Mx[m][a * nV + c] : 0.0;
+      va[q][m] = ain ? vx[m][a] : 0.0;
+    }
+  }
   double e4 = 0.0, e5 = 0.0, edt = 0.0;
-  const int64_t b0 = (int64_t)blockIdx.z * TRI_BCHUNK;
-  for (int64_t b = b0; b < b0 + TRI_BCHUNK && b < nV; ++b) {
-    if (!(a0 < b && c0 + 31 > b)) continue;  // uniform over the workgroup
-    __syncthreads();  // the previous b's reads of s3 are done
+  for (int64_t b = blo; b < bhi; ++b) {
+    double vb[6];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) vb[m] = vx[m][b];
+    const double fvb = fv[b];
+    __syncthreads();  // the previous b's reads of s3 and sb are done
     for (int r = ty; r < 32; r += 8) {
-      const int64_t c = c0 + r, a = a0 + tx;
-      s3[r][tx] = (c < nV && a < nV) ? Zt[(c * nV + b) * nV + a] : 0.0;
+      const int64_t cr = c0 + r, a = a0 + tx;
+      s3[r][tx] = (cr < nV && a < nV) ? Zt[(cr * nV + b) * nV + a] : 0.0;
+    }
+    for (int t = tid; t < 2 * 6 * 32; t += TRI_THREADS) {
+      const int h = t / 192, m = (t / 32) % 6, u = t % 32;
+      const int64_t col = (h ? a0 : c0) + u;
+      sb[h][m][u] = col < nV ? Mx[m][b * nV + col] : 0.0;
     }
     __syncthreads();
-    for (int r = ty; r < 32; r += 8) {
-      const int64_t a = a0 + r, c = c0 + tx;
-      if (a >= b || c <= b || c >= nV) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = ty + 8 * q;
+      const int64_t a = a0 + r;
+      if (a >= b || c <= b || !cin) continue;
       const double nc = Zt[(a * nV + b) * nV + c] - Zt[(b * nV + a) * nV + c] - s3[tx][r];
       if (nc == 0.0) continue;
       double d1 = 0.0, d2 = 0.0;
 #pragma unroll
       for (int p = 0; p < 3; ++p) {
-        const double* O = oovv + ((int64_t)ys[p] * nO + zs[p]) * nV2;
-        const double* T2 = t2so + ((int64_t)ys[p] * nO + zs[p]) * nV2;
-        const double* t1 = t1so + (int64_t)xs[p] * nV;
-        const double* f = fov + (int64_t)xs[p] * nV;
-        d1 += sg[p] * (t1[a] * O[b * nV + c] - t1[b] * O[a * nV + c] - t1[c] * O[b * nV + a]);
-        d2 += sg[p] * (f[a] * T2[b * nV + c] - f[b] * T2[a * nV + c] - f[c] * T2[b * nV + a]);
+        d1 += sg[p] * (va[q][p] * sb[0][p][tx] - vb[p] * mac[q][p] - vc[p] * sb[1][p][r]);
+        d2 += sg[p] * (va[q][3 + p] * sb[0][3 + p][tx] - vb[3 + p] * mac[q][3 + p] - vc[3 + p] * sb[1][3 + p][r]);
       }
-      const double w = nc / (fijk - fv[a] - fv[b] - fv[c]);
+      const double w = nc / (fijk - fva[q] - fvb - fvc);
       e4 += w * nc;
       e5 += w * d1;
       edt += w * d2;
@@ -227,8 +272,7 @@ tri_energy_tiled(double* part, const double* Zt, const double* t1so, const doubl
   e4 = tri_block_sum(e4, sh);
   e5 = tri_block_sum(e5, sh);
   edt = tri_block_sum(edt, sh);
-  if (threadIdx.x == 0 && threadIdx.y == 0) {
-    const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  if (tid == 0) {
     part[3 * blk + 0] = e4;
     part[3 * blk + 1] = e5;
     part[3 * blk + 2] = edt;
