@@ -464,50 +464,60 @@ __global__ __launch_bounds__(64 * DlTile<BT>::NW) void gemm_lp_dl_kernel(LArgs g
             }
           }
     } else {
-      // 128 x 64 wave tiles: each sub-step's fragments are read just before its MFMAs
-      // (12 reads of 16 bytes), which keeps the fragment registers at 48
+      // 128 x 64 wave tiles: each sub-step's fragments are read just before its MFMAs, in two
+      // groups: the four B fragments with the first four A fragments, whose 16 MFMAs then run
+      // while the other four A fragments are read (48 fragment registers; each accumulator
+      // takes the same MFMAs in the same order as with one group of 12 reads)
 #pragma unroll
       for (int h = 0; h < H; ++h) {
         u4v af[TM], bf[TN];
         const uint32_t pa = sa + ao[h], pb = sb + bo[h];
         asm volatile(
-            "ds_read_b128 %0, %12\n"
-            "ds_read_b128 %1, %12 offset:%14\n"
-            "ds_read_b128 %2, %12 offset:%15\n"
-            "ds_read_b128 %3, %12 offset:%16\n"
-            "ds_read_b128 %4, %12 offset:%17\n"
-            "ds_read_b128 %5, %12 offset:%18\n"
-            "ds_read_b128 %6, %12 offset:%19\n"
-            "ds_read_b128 %7, %12 offset:%20\n"
-            "ds_read_b128 %8, %13\n"
-            "ds_read_b128 %9, %13 offset:%14\n"
-            "ds_read_b128 %10, %13 offset:%15\n"
-            "ds_read_b128 %11, %13 offset:%16\n"
+            "ds_read_b128 %0, %8\n"
+            "ds_read_b128 %1, %8 offset:%10\n"
+            "ds_read_b128 %2, %8 offset:%11\n"
+            "ds_read_b128 %3, %8 offset:%12\n"
+            "ds_read_b128 %4, %9\n"
+            "ds_read_b128 %5, %9 offset:%10\n"
+            "ds_read_b128 %6, %9 offset:%11\n"
+            "ds_read_b128 %7, %9 offset:%12\n"
             "s_waitcnt lgkmcnt(0)"
-            : "=&v"(af[0]), "=&v"(af[1]), "=&v"(af[2]), "=&v"(af[3]), "=&v"(af[4]), "=&v"(af[5]), "=&v"(af[6]),
-              "=&v"(af[7]), "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3])
-            : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB), "n"(64 * RB), "n"(80 * RB),
-              "n"(96 * RB), "n"(112 * RB)
+            : "=&v"(af[0]), "=&v"(af[1]), "=&v"(af[2]), "=&v"(af[3]), "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]),
+              "=&v"(bf[3])
+            : "v"(pa), "v"(pb), "n"(16 * RB), "n"(32 * RB), "n"(48 * RB)
             : "memory");
         if (h == 0) {  // every wave has read the stage's first fragments: refill the oldest stage
           issue(fill, kbeg + (kt + S - 1) * BK);  // past the K range: zero rows
           slot = slot + 1 == S ? 0 : slot + 1;
           fill = fill + 1 == S ? 0 : fill + 1;
         }
+        auto mma = [&](int i0) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+          for (int i = i0; i < i0 + 4; ++i)
 #pragma unroll
-          for (int j = 0; j < TN; ++j) {
-            if constexpr (VL == 8) {
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af[i]),
-                                                                  __builtin_bit_cast(bf8, bf[j]), acc[i][j], 0, 0, 0);
-            } else {
-              const f4 a = __builtin_bit_cast(f4, af[i]), b = __builtin_bit_cast(f4, bf[j]);
+            for (int j = 0; j < TN; ++j) {
+              if constexpr (VL == 8) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, af[i]),
+                                                                    __builtin_bit_cast(bf8, bf[j]), acc[i][j], 0, 0, 0);
+              } else {
+                const f4 a = __builtin_bit_cast(f4, af[i]), b = __builtin_bit_cast(f4, bf[j]);
 #pragma unroll
-              for (int e = 0; e < 4; ++e)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc[i][j], 0, 0, 0);
+                for (int e = 0; e < 4; ++e)
+                  acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc[i][j], 0, 0, 0);
+              }
             }
-          }
+        };
+        mma(0);
+        asm volatile(
+            "ds_read_b128 %0, %4 offset:%5\n"
+            "ds_read_b128 %1, %4 offset:%6\n"
+            "ds_read_b128 %2, %4 offset:%7\n"
+            "ds_read_b128 %3, %4 offset:%8\n"
+            "s_waitcnt lgkmcnt(0)"
+            : "=&v"(af[4]), "=&v"(af[5]), "=&v"(af[6]), "=&v"(af[7])
+            : "v"(pa), "n"(64 * RB), "n"(80 * RB), "n"(96 * RB), "n"(112 * RB)
+            : "memory");
+        mma(4);
       }
     }
   }
