@@ -383,27 +383,38 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
     const int slot = (int)(kt & (S - 1));
     const uint32_t sa = lds_byte_address(sA[slot]), sb = lds_byte_address(sB[slot]);
     // each k sub-step's fragments are read just before its MFMAs, so that a wave's
-    // second read overlaps the MFMAs it has already issued
+    // second read overlaps the MFMAs it has already issued; B fragments 2-3 are read after
+    // the MFMAs of fragments 0-1 are issued (each accumulator's MFMA order is unchanged)
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       double af[TM], bf[TN];
       const uint32_t pa = sa + ao[ks], pb = sb + bo[ks];
       asm volatile(
-          "ds_read_b64 %0, %6\n"
-          "ds_read_b64 %1, %6 offset:%8\n"
-          "ds_read_b64 %2, %7\n"
-          "ds_read_b64 %3, %7 offset:%9\n"
-          "ds_read_b64 %4, %7 offset:%10\n"
-          "ds_read_b64 %5, %7 offset:%11\n"
+          "ds_read_b64 %0, %4\n"
+          "ds_read_b64 %1, %4 offset:%6\n"
+          "ds_read_b64 %2, %5\n"
+          "ds_read_b64 %3, %5 offset:%7\n"
           "s_waitcnt lgkmcnt(0)"
-          : "=&v"(af[0]), "=&v"(af[1]), "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3])
-          : "v"(pa), "v"(pb), "n"(AI), "n"(BJ), "n"(2 * BJ), "n"(3 * BJ)
+          : "=&v"(af[0]), "=&v"(af[1]), "=&v"(bf[0]), "=&v"(bf[1])
+          : "v"(pa), "v"(pb), "n"(AI), "n"(BJ)
           : "memory");
       if (ks == 0) issue((int)((kt + S - 1) & (S - 1)), kbeg + (kt + S - 1) * DL_BK);  // past kend: zero rows
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
+      asm volatile(
+          "ds_read_b64 %0, %2 offset:%3\n"
+          "ds_read_b64 %1, %2 offset:%4\n"
+          "s_waitcnt lgkmcnt(0)"
+          : "=&v"(bf[2]), "=&v"(bf[3])
+          : "v"(pb), "n"(2 * BJ), "n"(3 * BJ)
+          : "memory");
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 2; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
