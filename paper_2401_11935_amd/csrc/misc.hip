@@ -348,10 +348,10 @@ void swap_tu(double* dst, const double* src, int64_t batch, int n, int nc, hipSt
 // ---------------------------------------------------------------------------
 // Strided copy dst[od] = alpha * src[os] + beta * dst[od] over an index box of up to
 // six dimensions (od, os: sums of index times stride).  Two kernels, both HBM-bound:
-//  * rows: one workgroup per row of the box, the row being every dimension but one
-//    (`in`), decomposed once per workgroup from blockIdx (uniform, so in scalar
-//    registers); the threads run along `in`.  Used when the destination and the
-//    source have their unit stride in the same dimension (both accesses coalesced).
+//  * rows: a workgroup per row of the box (or per few rows, when rows are short), the
+//    row being every dimension but one (`in`), its offsets decomposed once per row;
+//    the threads run along `in`.  Used when the destination and the source have their
+//    unit stride in the same dimension (both accesses coalesced).
 //  * tiles: the destination's unit-stride dimension a and the source's b are tiled
 //    32 x 32 through LDS, so that both the reads (along b) and the writes (along a)
 //    are coalesced; a workgroup per tile and per index of the remaining dimensions.
@@ -373,15 +373,33 @@ __device__ inline void copy_outer(const CopyPlan& p, int64_t r, int skip0, int s
   }
 }
 
+// A workgroup takes rpb consecutive rows (rpb > 1 only for rows of at most 2048 elements), their
+// offsets decomposed once each into LDS; the threads run over the rpb x n elements.
+constexpr int kCopyMaxRows = 64;
 __global__ __launch_bounds__(256) void copy_rows_kernel(double* dst, const double* src, CopyPlan p, int in,
-                                                        double alpha, double beta) {
-  int64_t od, os;
-  copy_outer(p, blockIdx.x, in, -1, od, os);
+                                                        int64_t rows, int rpb, double alpha, double beta) {
+  __shared__ int64_t rod[kCopyMaxRows], ros[kCopyMaxRows];
   const int64_t n = p.dims[in], sd = p.ds[in], ss = p.ss[in];
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    double v = alpha * src[os + i * ss];
-    if (beta != 0.0) v += beta * dst[od + i * sd];
-    dst[od + i * sd] = v;
+  const int64_t r0 = (int64_t)blockIdx.x * rpb;
+  const int nr = rows - r0 < rpb ? (int)(rows - r0) : rpb;
+  if ((int)threadIdx.x < nr) copy_outer(p, r0 + threadIdx.x, in, -1, rod[threadIdx.x], ros[threadIdx.x]);
+  __syncthreads();
+  if (rpb == 1) {
+    const int64_t od = rod[0], os = ros[0];
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      double v = alpha * src[os + i * ss];
+      if (beta != 0.0) v += beta * dst[od + i * sd];
+      dst[od + i * sd] = v;
+    }
+    return;
+  }
+  const unsigned un = (unsigned)n, total = (unsigned)nr * un;
+  for (unsigned e = threadIdx.x; e < total; e += 256) {
+    const unsigned r = e / un, i = e - r * un;
+    const int64_t o = rod[r] + (int64_t)i * sd;
+    double v = alpha * src[ros[r] + (int64_t)i * ss];
+    if (beta != 0.0) v += beta * dst[o];
+    dst[o] = v;
   }
 }
 
@@ -450,8 +468,11 @@ void strided_copy(double* dst, const double* src, const Strided& st, double alph
       for (int d = 0; d < st.nd; ++d)
         if (st.dims[d] > st.dims[in]) in = d;
     const int64_t rows = total / st.dims[in];
-    if (rows >= ((int64_t)1 << 31)) throw ArgError("strided_copy: box too large");
-    hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)rows), dim3(256), 0, s, dst, src, p, in, alpha, beta);
+    const int rpb = st.dims[in] > 2048 ? 1 : (int)std::min<int64_t>(kCopyMaxRows, std::max<int64_t>(1, 2048 / st.dims[in]));
+    const int64_t blocks = (rows + rpb - 1) / rpb;
+    if (blocks >= ((int64_t)1 << 31)) throw ArgError("strided_copy: box too large");
+    hipLaunchKernelGGL(copy_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, dst, src, p, in, rows, rpb, alpha,
+                       beta);
   }
   DCSD_CHECK_LAUNCH();
 }
