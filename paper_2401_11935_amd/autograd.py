@@ -6,7 +6,12 @@ life of the problem).  Two differentiable maps:
 
 * ``problem.residual(T, B, F) -> (R, W, dE_A)`` (``DCSDResidual``): one
   residual evaluation; backward is ``dcsd_residual_vjp`` (cotangents of T and
-  of every stored entry of B and F);
+  of every stored entry of B and F).  The gradient of T is taken entry by
+  entry over the packed vector, which stores every same-spin double in its
+  four signed copies: ``T.grad . dT`` is the derivative of the loss only along
+  changes dT with that antisymmetry (and with dT = 0 at the A->B double), the
+  directions that are amplitude changes.  Project it onto that subspace (the
+  mean of the four signed copies) before using it along any other direction;
 * ``problem.energies(B, F) -> (E_S, E_T)`` (``DCSDEnergy``): the converged
   correlation energies of the singlet and triplet; backward is
   ``dcsd_backward`` (the lambda equations of the energy Lagrangian, then
