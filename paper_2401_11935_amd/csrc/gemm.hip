@@ -32,6 +32,7 @@ struct KArgs {
   int64_t split_stride;  // element stride between split partial outputs
   int64_t vu, nq;        // pair-blocked output (EPI = 1)
   int64_t skip_lower;    // EPI = 1, diagonal batch: skip tiles whose pairs all have p > q
+  int64_t xcd_split;     // split product on a one-dimensional grid, K chunks grouped per XCD
   const double* bseg[3]; // EPI = 2: row k of B is row k % segk of bseg[k / segk]
   int64_t segk;
 };
@@ -319,10 +320,19 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / DL_WGN, wn = wave % DL_WGN;
   int64_t tm, tn;
-  const int64_t z = blockIdx.z;
+  int64_t z = blockIdx.z;
   if (EPI == 1 && g.skip_lower) {
     if (!diag_tile(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, g.N, g.vu, BM, BN, tm, tn))
       return;  // whole workgroup, before any barrier
+  } else if (SPLIT && g.xcd_split) {
+    // one-dimensional grid of tiles x K chunks (chunk count a multiple of 8, one matrix):
+    // workgroup L runs on XCD L % 8, so every tile of one K chunk goes to one XCD,
+    // dispatched together; the chunk's A rows and B columns are then fetched once into
+    // that XCD's L2 instead of once per XCD that holds one of its tiles
+    const int64_t tiles = ((g.M + BM - 1) / BM) * g.tiles_n;
+    const int64_t L = blockIdx.x, j = L / 8;
+    z = L % 8 + 8 * (j / tiles);
+    tile_of(j % tiles, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
   } else {
     tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
   }
@@ -546,6 +556,8 @@ void launch_dl3(const GemmArgs& g, KArgs& k, hipStream_t s) {
   const int64_t tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
   k.tiles_n = tn;
   dim3 grid((unsigned)(tm * tn), (unsigned)g.batch, (unsigned)g.ksplit);
+  k.xcd_split = g.ksplit > 1 && g.ksplit % 8 == 0 && g.batch == 1 ? 1 : 0;
+  if (k.xcd_split) grid = dim3((unsigned)(tm * tn * g.ksplit));
   if (g.ksplit > 1)
     hipLaunchKernelGGL((gemm_dl_kernel<A_KM, B_KM, 0, true, C_NC>), grid, dim3(DL_NT), 0, s, k);
   else

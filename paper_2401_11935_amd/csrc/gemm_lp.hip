@@ -674,10 +674,11 @@ void launch_gemm(const LpGemm& q, hipStream_t s) {
     else
       hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT, 256>),
                          dim3((unsigned)t256, 1, (unsigned)ks), dim3(64 * DlTile<256>::NW), 0, s, a);
-  } else if (dl)
-    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT>),
-                       dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
-  else
+  } else if (dl) {
+    a.xcd_split = ks % 8 == 0 ? 1 : 0;
+    const dim3 grid = a.xcd_split ? dim3((unsigned)(tiles * ks)) : dim3((unsigned)tiles, 1, (unsigned)ks);
+    hipLaunchKernelGGL((gemm_lp_dl_kernel<T, DlShape<T>::S, DlShape<T>::CPR, EPI_SPLIT>), grid, dim3(NT), 0, s, a);
+  } else
     hipLaunchKernelGGL((gemm_lp_kernel<T, EPI_SPLIT, true>), dim3((unsigned)tiles, 1, (unsigned)ks), dim3(NT), 0, s, a);
   DCSD_CHECK_LAUNCH();
   hipLaunchKernelGGL(lp_split_reduce, dim3(nb(q.M * q.N)), dim3(256), 0, s, (const float*)q.work, q.C, q.M, q.N, ks,
