@@ -70,9 +70,11 @@ LARGEST = Config("largest", nc=20, nv=600, naux=1800, seed=3)
 CONFIGS = {c.name: c for c in (TINY, MEDIUM, ADJOINT, MIXED, LARGEST)}
 # The same shapes and seeds with weak integrals (added configurations).
 MEDIUM_WEAK = Config("medium-weak", nc=8, nv=200, naux=600, seed=1, sigma=weak_sigma(600))
+# the medium core count and seed with half its virtuals (converged solves of the oracle in minutes)
+MEDIUM_HALF_WEAK = Config("medium-half-weak", nc=8, nv=100, naux=300, seed=1, sigma=weak_sigma(300))
 MIXED_WEAK = Config("mixed-weak", nc=12, nv=400, naux=1200, seed=2, sigma=weak_sigma(1200))
 LARGEST_WEAK = Config("largest-weak", nc=20, nv=600, naux=1800, seed=3, sigma=weak_sigma(1800))
-WEAK_CONFIGS = {c.name: c for c in (MEDIUM_WEAK, MIXED_WEAK, LARGEST_WEAK)}
+WEAK_CONFIGS = {c.name: c for c in (MEDIUM_HALF_WEAK, MEDIUM_WEAK, MIXED_WEAK, LARGEST_WEAK)}
 
 
 def amplitude_count(nc: int, nv: int) -> int:

@@ -17,7 +17,11 @@ medium-weak: the medium shape and seed with weak integrals (DF factors with
         and the converged amplitudes at 4096 seeded positions.  Hours on a few
         CPU cores (about 20 oracle residuals per method).
 
+medium-half-weak: the same with nv=100, naux=300 (dcsd_synth.MEDIUM_HALF_WEAK): converged
+        energies, trajectory and sampled amplitudes of both methods; minutes per method.
+
     python tests/golden/make_golden.py medium-weak [dcsd|ccsd]
+    python tests/golden/make_golden.py medium-half-weak [dcsd|ccsd]
 """
 import json
 import os
@@ -87,9 +91,8 @@ def converged_with_amplitudes(cfg, method, tol):
     }
 
 
-def main_weak(methods):
-    cfg = synth.MEDIUM_WEAK
-    path = os.path.join(HERE, "medium_weak.json")
+def main_weak(methods, cfg=synth.MEDIUM_WEAK, name="medium_weak.json"):
+    path = os.path.join(HERE, name)
     out = json.load(open(path)) if os.path.exists(path) else {}
     out["config"] = {"nc": cfg.nc, "nv": cfg.nv, "naux": cfg.naux, "seed": cfg.seed, "sigma": cfg.sigma}
     for method in methods:
@@ -100,8 +103,11 @@ def main_weak(methods):
 
 
 def main(which):
-    if which == "medium-weak":
-        return main_weak([m for m in ("dcsd", "ccsd") if m in sys.argv[2:]] or ["dcsd", "ccsd"])
+    if which in ("medium-weak", "medium-half-weak"):
+        methods = [m for m in ("dcsd", "ccsd") if m in sys.argv[2:]] or ["dcsd", "ccsd"]
+        if which == "medium-weak":
+            return main_weak(methods)
+        return main_weak(methods, synth.MEDIUM_HALF_WEAK, "medium_half_weak.json")
     cfg = {"tiny": synth.TINY, "small": SMALL, "medium": synth.MEDIUM}[which]
     out = {"config": {"nc": cfg.nc, "nv": cfg.nv, "naux": cfg.naux, "seed": cfg.seed}}
     for method in ("dcsd", "ccsd"):

@@ -1,7 +1,8 @@
-"""GPU: converged 2D-DCSD / 2D-CCSD on the nc=8, nv=200, naux=600 shape with weak
-integrals (dcsd_synth.MEDIUM_WEAK) against the oracle's converged solve of the
-same inputs (tests/golden/medium_weak.json, written by tests/golden/make_golden.py
-from oracle/ alone).
+"""GPU: converged 2D-DCSD / 2D-CCSD with weak integrals on the nc=8, nv=200,
+naux=600 shape (dcsd_synth.MEDIUM_WEAK) and on the same with half the virtuals,
+nc=8, nv=100, naux=300 (dcsd_synth.MEDIUM_HALF_WEAK), against the oracle's
+converged solves of the same inputs (tests/golden/medium_weak.json and
+medium_half_weak.json, written by tests/golden/make_golden.py from oracle/ alone).
 
 Bars: energies within 1e-8 Eh, the converged amplitudes at 4096 seeded positions
 within 1e-8, the first iterations following the oracle's (same Jacobi/DIIS
@@ -18,7 +19,8 @@ import dcsd_synth as synth
 
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
-GOLD = os.path.join(HERE, "golden", "medium_weak.json")
+GOLDS = {"medium-weak": (synth.MEDIUM_WEAK, "medium_weak.json"),
+         "medium-half-weak": (synth.MEDIUM_HALF_WEAK, "medium_half_weak.json")}
 
 
 def say(*a):
@@ -35,11 +37,15 @@ def _gpu():
     libdcsd.load()
 
 
-def _gold(method):
-    gold = json.load(open(GOLD))
+def _gold(method, which="medium-weak"):
+    cfg, name = GOLDS[which]
+    path = os.path.join(HERE, "golden", name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    gold = json.load(open(path))
     if method not in gold:
-        pytest.skip(f"{method} not in medium_weak.json")
-    c, cfg = gold["config"], synth.MEDIUM_WEAK
+        pytest.skip(f"{method} not in {name}")
+    c = gold["config"]
     assert (c["nc"], c["nv"], c["naux"], c["seed"]) == (cfg.nc, cfg.nv, cfg.naux, cfg.seed)
     assert abs(c["sigma"] - cfg.sigma) <= 1e-15
     g = gold[method]
@@ -47,12 +53,13 @@ def _gold(method):
     return g
 
 
+@pytest.mark.parametrize("which", ["medium-half-weak", "medium-weak"])
 @pytest.mark.parametrize("method", ["dcsd", "ccsd"])
-def test_converged_energies_and_amplitudes_match_oracle(method):
+def test_converged_energies_and_amplitudes_match_oracle(method, which):
     from gpu_util import GpuProblem
-    g = _gold(method)
-    cfg = synth.MEDIUM_WEAK
-    say("medium weak converged", method)
+    g = _gold(method, which)
+    cfg = GOLDS[which][0]
+    say(which, "converged", method)
     B, F = synth.make_config_inputs(cfg)
     p = GpuProblem(B, F, cfg.nc, method, tol_residual=g["tol"], max_iter=300)
     rep, T = p.solve()
