@@ -325,14 +325,9 @@ __global__ __launch_bounds__(DL_NT) void gemm_dl_kernel(KArgs g) {
     if (!diag_tile(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, g.N, g.vu, BM, BN, tm, tn))
       return;  // whole workgroup, before any barrier
   } else if (SPLIT && g.xcd_split) {
-    // one-dimensional grid of tiles x K chunks (chunk count a multiple of 8, one matrix):
-    // workgroup L runs on XCD L % 8, so every tile of one K chunk goes to one XCD,
-    // dispatched together; the chunk's A rows and B columns are then fetched once into
-    // that XCD's L2 instead of once per XCD that holds one of its tiles
-    const int64_t tiles = ((g.M + BM - 1) / BM) * g.tiles_n;
-    const int64_t L = blockIdx.x, j = L / 8;
-    z = L % 8 + 8 * (j / tiles);
-    tile_of(j % tiles, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
+    // one matrix, K chunks grouped per XCD: the chunk's A rows and B columns are fetched once
+    // into one L2 instead of once per XCD that holds one of its tiles
+    z = split_tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
   } else {
     tile_of(blockIdx.x, (g.M + BM - 1) / BM, g.tiles_n, tm, tn);
   }

@@ -361,14 +361,8 @@ __global__ __launch_bounds__(64 * DlTile<BT>::NW) void gemm_lp_dl_kernel(LArgs g
     if (!diag_tile(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, g.N, g.vu, BT, BT, tm, tn))
       return;  // whole workgroup, before any barrier
   } else if (EPI == EPI_SPLIT && g.xcd_split) {
-    // one-dimensional grid of tiles x chunks (chunks a multiple of 8): the workgroups are
-    // dealt round-robin to the 8 XCDs, so workgroup L runs on XCD L % 8; give every tile of
-    // one K chunk to the same XCD, dispatched together, so that they share the chunk's
-    // operand rows in that XCD's L2
-    const int64_t tiles = ((g.M + BT - 1) / BT) * g.tiles_n;
-    const int64_t L = blockIdx.x, j = L / 8;
-    zsplit = L % 8 + 8 * (j / tiles);
-    tile_of(j % tiles, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
+    // K chunks grouped per XCD: the tiles of one chunk share its operand rows in one L2
+    zsplit = split_tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
   } else {
     tile_of(blockIdx.x, (g.M + BT - 1) / BT, g.tiles_n, tm, tn);
   }

@@ -25,6 +25,17 @@ __device__ inline void tile_of(int64_t bid, int64_t tiles_m, int64_t tiles_n, in
   tn = w / rows;
 }
 
+// Split product on a one-dimensional grid of tiles x K chunks, the chunk count a multiple
+// of 8: workgroup L runs on XCD L % 8, and every tile of one K chunk is given to the same
+// XCD, dispatched together, so that the chunk's operand rows are fetched once into that
+// XCD's L2 and shared by its tiles.  Returns the chunk of workgroup L; (tm, tn) is its tile.
+// A bijection of [0, tiles_m * tiles_n * chunks) onto (chunk, tile).
+__device__ inline int64_t split_tile_of(int64_t L, int64_t tiles_m, int64_t tiles_n, int64_t& tm, int64_t& tn) {
+  const int64_t tiles = tiles_m * tiles_n, j = L / 8;
+  tile_of(j % tiles, tiles_m, tiles_n, tm, tn);
+  return L % 8 + 8 * (j / tiles);
+}
+
 // Diagonal pair batch of a pair-blocked product (rows (p, c), columns (q, d), both
 // orbital blocks the same, vu values of c and d per orbital): the pair (p, q) equals the
 // transpose of (q, p), so the tiles lying entirely in the p > q part are skipped and those

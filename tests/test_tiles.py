@@ -4,7 +4,9 @@ tests/tiles_check.cpp is built with hipcc for the host and checks that the
 XCD-aware order visits every output tile exactly once for 48 x 48 tile counts
 and larger shapes, and that a diagonal pair batch's grid visits exactly the
 kept tiles (those holding some pair with p <= q) once each, for batch sizes 1..40
-and pair extents 2..602 with 128- and 64-wide tiles."""
+and pair extents 2..602 with 128- and 64-wide tiles, and that the split-K order
+on a one-dimensional grid takes every (K chunk, tile) once with all tiles of a
+chunk on one XCD."""
 import os
 import shutil
 import subprocess

@@ -12,6 +12,7 @@
 using dcsd::diag_grid;
 using dcsd::diag_skips;
 using dcsd::diag_tile;
+using dcsd::split_tile_of;
 using dcsd::tile_of;
 
 static int fails = 0;
@@ -75,7 +76,32 @@ static void check_diag(int64_t np, int64_t vu, int BM, int BN) {
                                     (long long)r, (long long)c);
 }
 
+// split products on a one-dimensional grid: every (chunk, tile) exactly once for L in
+// [0, tiles * chunks), and every tile of a chunk on the XCD L % 8 == chunk % 8
+static void check_split(int64_t tm, int64_t tn, int64_t chunks) {
+  const int64_t tiles = tm * tn;
+  std::vector<int> seen(tiles * chunks, 0);
+  for (int64_t L = 0; L < tiles * chunks; ++L) {
+    int64_t a = -1, b = -1;
+    const int64_t z = split_tile_of(L, tm, tn, a, b);
+    const bool ok = z >= 0 && z < chunks && a >= 0 && a < tm && b >= 0 && b < tn;
+    CHECK(ok, "split_tile_of(%lld; %lld x %lld, %lld chunks) -> chunk %lld tile (%lld, %lld) out of range",
+          (long long)L, (long long)tm, (long long)tn, (long long)chunks, (long long)z, (long long)a, (long long)b);
+    if (!ok) continue;
+    CHECK(L % 8 == z % 8, "split_tile_of: chunk %lld on XCD %lld", (long long)z, (long long)(L % 8));
+    ++seen[z * tiles + a * tn + b];
+  }
+  for (int64_t t = 0; t < tiles * chunks; ++t)
+    CHECK(seen[t] == 1, "split_tile_of %lld x %lld, %lld chunks: (chunk, tile) %lld seen %d times", (long long)tm,
+          (long long)tn, (long long)chunks, (long long)t, seen[t]);
+}
+
 int main() {
+  for (int64_t tm = 1; tm <= 9; ++tm)
+    for (int64_t tn = 1; tn <= 9; ++tn)
+      for (int64_t chunks = 8; chunks <= 32; chunks += 8) check_split(tm, tn, chunks);
+  check_split(4, 8, 16);  // the ladder contraction at the metric shape, 128-wide tiles
+  check_split(2, 4, 32);  // the same on 256-wide tiles
   for (int64_t tm = 1; tm <= 48; ++tm)
     for (int64_t tn = 1; tn <= 48; ++tn) check_tile_of(tm, tn);
   const int64_t big[][2] = {{101, 101}, {145, 3}, {3, 145}, {82, 82}, {4, 1024}, {257, 129}, {1, 513}};
